@@ -1,0 +1,278 @@
+"""ctypes wrapper of the FP64 CPU oracle (oracle/traphic_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the slow, plain reference the HIP library is
+checked against.  Only tests/, the smoke check and the benchmark's CPU-baseline
+leg may import this module.  It shares no code with the HIP library; the only
+thing both sides use is the seeded input generator module.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "traphic_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+
+def build(force=True):
+    """Compile the oracle with gcc (scalar libm, no FMA contraction)."""
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+        return LIB
+    tmp = LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math",
+           "-fPIC", "-shared", "-o", tmp, SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+class _Params(C.Structure):
+    _fields_ = [
+        ("n_ngb", C.c_int32), ("n_tc", C.c_int32), ("n_rc", C.c_int32), ("n_ec", C.c_int32),
+        ("n_freq", C.c_int32), ("rr_bin", C.c_int32),
+        ("recomb_mode", C.c_int32), ("isothermal", C.c_int32), ("freeze_chem", C.c_int32),
+        ("n_em", C.c_int32), ("max_hops", C.c_int32), ("max_vip_depth", C.c_int32),
+        ("dt", C.c_double), ("floor_rel", C.c_double), ("chem_frac", C.c_double),
+        ("seed", C.c_uint64),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        L = C.CDLL(LIB)
+        P = C.POINTER
+        dp, ip, i64p, u64p, u32p = P(C.c_double), P(C.c_int32), P(C.c_int64), P(C.c_uint64), P(C.c_uint32)
+        L.or_create.restype = C.c_void_p
+        L.or_create.argtypes = [P(_Params), dp, dp, C.c_int32, i64p, dp, dp, dp, dp, dp, dp]
+        L.or_add_sources.restype = C.c_int
+        L.or_add_sources.argtypes = [C.c_void_p, C.c_int32, ip, ip, dp, dp, ip]
+        L.or_step.restype = C.c_int
+        L.or_step.argtypes = [C.c_void_p, C.c_int32]
+        L.or_get_state.argtypes = [C.c_void_p, dp, dp, dp, dp, dp, i64p]
+        L.or_get_bins.argtypes = [C.c_void_p, dp, dp, dp]
+        L.or_get_ngb.argtypes = [C.c_void_p, ip, dp]
+        L.or_get_emitter_ngb.argtypes = [C.c_void_p, ip, dp]
+        L.or_n_emitters.restype = C.c_int64
+        L.or_n_emitters.argtypes = [C.c_void_p]
+        L.or_cone_masks.argtypes = [C.c_void_p, u64p]
+        L.or_get_nrr.argtypes = [C.c_void_p, dp]
+        L.or_destroy.argtypes = [C.c_void_p]
+        L.or_error.restype = C.c_char_p
+        L.or_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.or_dirset.argtypes = [C.c_int32, dp]
+        L.or_rotation.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, dp]
+        L.or_in_cone.restype = C.c_int
+        L.or_in_cone.argtypes = [dp, dp, C.c_int32]
+        L.or_rates.argtypes = [C.c_double, dp]
+        L.or_chem_one.argtypes = [P(_Params), dp, dp, C.c_double, C.c_double, dp, dp, dp, i64p]
+        L.or_knn_points.argtypes = [C.c_void_p, C.c_int32, C.c_int64, dp, ip, dp]
+        L.or_vip_sample.restype = C.c_int
+        L.or_vip_sample.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, dp,
+                                    C.c_int32, dp]
+        L.or_merge_packets.argtypes = [C.c_int32, dp, dp, dp, dp, dp, dp]
+        _lib = L
+    return _lib
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def _d(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, _ptr(a, C.c_double)
+
+
+def make_params(p):
+    return _Params(
+        int(p["n_ngb"]), int(p["n_tc"]), int(p["n_rc"]), int(p["n_ec"]), int(p["n_freq"]),
+        int(p["rr_bin"]), int(p["recomb_mode"]), int(p["isothermal"]), int(p.get("freeze_chem", 0)),
+        int(p["n_em"]), int(p["max_hops"]), int(p["max_vip_depth"]),
+        float(p["dt"]), float(p["floor_rel"]), float(p["chem_frac"]), int(p["seed"]) & 0xFFFFFFFFFFFFFFFF)
+
+
+class OracleSim:
+    """One oracle simulation built from a workload dict of paper_1311_0182_amd.inputs."""
+
+    def __init__(self, cfg, with_sources=True):
+        L = lib()
+        self.cfg = cfg
+        self.p = dict(cfg["params"])
+        self._params = make_params(self.p)
+        self.N = int(cfg["pos"].shape[0])
+        self.nf = int(self.p["n_freq"])
+        self.G = int(self.p["n_rc"]) * self.nf
+        self.n_inst = int(cfg["inst_off"].shape[0] - 1)
+        keep = []
+
+        def d(a):
+            arr, ptr = _d(a)
+            keep.append(arr)
+            return ptr
+
+        off = np.ascontiguousarray(cfg["inst_off"], dtype=np.int64)
+        keep.append(off)
+        h = L.or_create(C.byref(self._params), d(cfg["sigma"]), d(cfg["eps"]), self.n_inst,
+                        _ptr(off, C.c_int64), d(cfg["box"]), d(cfg["pos"]), d(cfg["nH"]),
+                        d(cfg["NH"]), d(cfg["xHI"]), d(cfg["T"]))
+        if not h:
+            raise ValueError("oracle: " + L.or_error().decode())
+        self.h = h
+        if with_sources and cfg.get("sources") is not None:
+            self.add_sources(cfg["sources"])
+
+    def add_sources(self, s):
+        L = lib()
+        inst = np.ascontiguousarray(s["inst"], dtype=np.int32)
+        kind = np.ascontiguousarray(s["kind"], dtype=np.int32)
+        pos, pp = _d(s["pos"])
+        rate, rp = _d(s["rate"])
+        ns = np.ascontiguousarray(s["n_side"], dtype=np.int32)
+        rc = L.or_add_sources(self.h, len(inst), _ptr(inst, C.c_int32), _ptr(kind, C.c_int32), pp, rp,
+                              _ptr(ns, C.c_int32))
+        if rc:
+            raise ValueError("oracle: " + L.or_error().decode())
+
+    def step(self, n=1):
+        return lib().or_step(self.h, int(n))
+
+    def state(self):
+        N, nf = self.N, self.nf
+        x = np.empty(N)
+        T = np.empty(N)
+        A = np.empty(N * nf)
+        P = np.empty(N * nf)
+        led = np.empty(self.n_inst * nf * 5)
+        cnt = np.empty(4, dtype=np.int64)
+        lib().or_get_state(self.h, _ptr(x, C.c_double), _ptr(T, C.c_double), _ptr(A, C.c_double),
+                           _ptr(P, C.c_double), _ptr(led, C.c_double), _ptr(cnt, C.c_int64))
+        return dict(xHI=x, T=T, A=A.reshape(N, nf), P=P.reshape(N, nf),
+                    ledger=led.reshape(self.n_inst, nf, 5), counters=cnt)
+
+    def bins(self):
+        B = self.N * self.G
+        Nb = np.empty(B)
+        d = np.empty(B * 3)
+        c = np.empty(B)
+        lib().or_get_bins(self.h, _ptr(Nb, C.c_double), _ptr(d, C.c_double), _ptr(c, C.c_double))
+        return Nb, d.reshape(B, 3), c
+
+    def ngb(self):
+        k = int(self.p["n_ngb"])
+        nb = np.empty(self.N * k, dtype=np.int32)
+        h = np.empty(self.N)
+        lib().or_get_ngb(self.h, _ptr(nb, C.c_int32), _ptr(h, C.c_double))
+        return nb.reshape(self.N, k), h
+
+    def emitter_ngb(self):
+        k = int(self.p["n_ngb"])
+        m = int(lib().or_n_emitters(self.h))
+        nb = np.empty(max(m, 1) * k, dtype=np.int32)
+        h = np.empty(max(m, 1))
+        lib().or_get_emitter_ngb(self.h, _ptr(nb, C.c_int32), _ptr(h, C.c_double))
+        return nb[: m * k].reshape(m, k), h[:m]
+
+    def cone_masks(self):
+        m = np.empty(self.N * self.G, dtype=np.uint64)
+        lib().or_cone_masks(self.h, _ptr(m, C.c_uint64))
+        return m
+
+    def nrr(self):
+        a = np.empty(self.N)
+        lib().or_get_nrr(self.h, _ptr(a, C.c_double))
+        return a
+
+    def knn_points(self, inst, q):
+        k = int(self.p["n_ngb"])
+        q, qp = _d(np.asarray(q).reshape(-1, 3))
+        nb = np.empty(q.shape[0] * k, dtype=np.int32)
+        h = np.empty(q.shape[0])
+        lib().or_knn_points(self.h, int(inst), q.shape[0], qp, _ptr(nb, C.c_int32), _ptr(h, C.c_double))
+        return nb.reshape(-1, k), h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().or_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----- primitives -------------------------------------------------------------
+
+def philox(ctr, key):
+    c = np.asarray(ctr, dtype=np.uint32)
+    k = np.asarray(key, dtype=np.uint32)
+    o = np.empty(4, dtype=np.uint32)
+    lib().or_philox4x32_10(_ptr(c, C.c_uint32), _ptr(k, C.c_uint32), _ptr(o, C.c_uint32))
+    return o
+
+
+def dirset(n):
+    u = np.empty(3 * n)
+    lib().or_dirset(int(n), _ptr(u, C.c_double))
+    return u.reshape(n, 3)
+
+
+def rotation(seed, tag, step, a=0, b=0):
+    R = np.empty(9)
+    lib().or_rotation(int(seed), int(tag), int(step), int(a), int(b), _ptr(R, C.c_double))
+    return R.reshape(3, 3)
+
+
+def in_cone(v, d, n_tc):
+    v, vp = _d(v)
+    d, dp = _d(d)
+    return bool(lib().or_in_cone(vp, dp, int(n_tc)))
+
+
+def rates(T):
+    o = np.empty(8)
+    lib().or_rates(float(T), _ptr(o, C.c_double))
+    return dict(alpha_A=o[0], alpha_B=o[1], beta=o[2], recA_cool=o[3], recB_cool=o[4],
+                ce_cool=o[5], ff_cool=o[6], compton=o[7])
+
+
+def chem_one(params, eps, A, nH, NH, xHI, T):
+    p = make_params(params)
+    e, ep = _d(eps)
+    a, ap = _d(A)
+    x = C.c_double(xHI)
+    t = C.c_double(T)
+    r = C.c_double(0.0)
+    n = C.c_int64(0)
+    lib().or_chem_one(C.byref(p), ep, ap, float(nH), float(NH), C.byref(x), C.byref(t), C.byref(r), C.byref(n))
+    return x.value, t.value, r.value, n.value
+
+
+def vip_sample(seed, tag, step, ida, idb, d, n_tc):
+    d, dp_ = _d(d)
+    p = np.empty(3)
+    ok = lib().or_vip_sample(int(seed), int(tag), int(step), int(ida), int(idb), dp_, int(n_tc),
+                             _ptr(p, C.c_double))
+    return p if ok else None
+
+
+def merge_packets(N, d, c):
+    N, Np = _d(N)
+    d, dp_ = _d(np.asarray(d).reshape(-1, 3))
+    c, cp = _d(c)
+    oN = C.c_double(0)
+    od = np.empty(3)
+    oc = C.c_double(0)
+    lib().or_merge_packets(len(N), Np, dp_, cp, C.byref(oN), _ptr(od, C.c_double), C.byref(oc))
+    return oN.value, od, oc.value

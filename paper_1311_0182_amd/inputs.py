@@ -1,0 +1,212 @@
+"""Seeded synthetic workloads for the TRAPHIC radiative-transfer step.
+
+This module only builds input arrays and numerical parameters: particle
+positions, densities, atom counts, initial ionization state and temperature,
+sources and the per-bin grey constants.  It holds none of the transport,
+chemistry or recombination arithmetic of the method, and it is the only code
+shared by the CPU oracle and the HIP path (both take these arrays as inputs).
+
+The shapes follow the paper's test set-ups:
+  * Stromgren HII region (section 3): uniform hydrogen, n_H = 1e-3 cm^-3,
+    T = 1e4 K, one source of 5e48 photons/s at the box centre, monochromatic
+    13.6 eV photons with sigma = 6.3e-18 cm^2, N_EC = N_TC = N_RC = 8,
+    dt = 0.1 Myr, emission sub-step dt_em = 0.01 Myr.
+  * Recombination radiation in its own frequency bin with the 13.6 eV
+    cross-section (section 2.2).
+  * Plane-parallel front from one box face (section 4 and its footnote on the
+    boundary emitters).
+Particle sets are jittered lattices: x = (i + 1/2 + U(-0.3, 0.3)) dx per axis.
+Every generator is seeded (numpy PCG64) so both sides see identical inputs.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# Physical constants used only to express the recipes in cgs units.
+KPC_CM = 3.0857e21
+MYR_S = 3.1536e13
+EV_ERG = 1.602176634e-12
+K_BOLTZ = 1.380649e-16
+SIGMA_13P6 = 6.3e-18          # cm^2, hydrogen cross-section at 13.6 eV (section 2.2)
+ALPHA_B_1E4 = 2.59e-13        # cm^3/s, only to size batched boxes (R_S/L recipe)
+
+# Enumerations mirrored from include/traphic_rt.h
+CASE_B_OTS, CASE_A_NO_RR, RR_TRANSPORT = 0, 1, 2
+FP64, FP32 = 0, 1
+SRC_POINT, SRC_PLANE_XLO = 0, 1
+
+BASE_SEED = 1311018200
+
+
+def default_params(**kw):
+    """Numerical parameters of one RT step (names follow the paper's notation)."""
+    p = dict(
+        n_ngb=32,          # SPH neighbours per particle
+        n_tc=8,            # transmission cones: solid angle 4 pi / N_TC
+        n_rc=8,            # reception cones
+        n_ec=8,            # emission cones
+        n_freq=1,          # grey frequency bins
+        rr_bin=-1,         # bin that carries recombination photons (-1: none)
+        recomb_mode=CASE_B_OTS,
+        isothermal=1,
+        freeze_chem=0,     # 1: skip the chemistry update (transport-only runs)
+        precision=FP64,
+        n_em=10,           # emission sub-steps per RT step (dt / dt_em)
+        max_hops=4096,
+        max_vip_depth=4,
+        dt=0.1 * MYR_S,
+        floor_rel=1e-20,   # packets below floor_rel * N_H of their particle are absorbed there
+        chem_frac=0.1,     # sub-step = chem_frac * relaxation time
+        seed=BASE_SEED,
+    )
+    p.update(kw)
+    return p
+
+
+def jittered_lattice(n_side, box_lo, box_len, rng, jitter=0.3):
+    """Positions (i + 1/2 + U(-jitter, jitter)) * dx on an n_side^3 lattice, C order."""
+    dx = box_len / n_side
+    idx = np.arange(n_side, dtype=np.float64)
+    gx, gy, gz = np.meshgrid(idx, idx, idx, indexing="ij")
+    lat = np.stack([gx.ravel(), gy.ravel(), gz.ravel()], axis=1)
+    jit = rng.uniform(-jitter, jitter, size=lat.shape)
+    return np.asarray(box_lo, dtype=np.float64)[None, :] + (lat + 0.5 + jit) * dx
+
+
+def _uniform_gas(pos, n_h, box_len, x_hi0, t0):
+    n = pos.shape[0]
+    nh = np.full(n, n_h, dtype=np.float64)
+    vol = box_len ** 3 / n
+    NH = nh * vol
+    return nh, NH, np.full(n, x_hi0, dtype=np.float64), np.full(n, t0, dtype=np.float64)
+
+
+def _pack(name, params, sigma, eps, insts, sources, n_steps):
+    """insts: list of dicts with pos, nH, NH, xHI, T, box_lo, box_hi."""
+    pos = np.concatenate([d["pos"] for d in insts], axis=0)
+    off = np.zeros(len(insts) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([d["pos"].shape[0] for d in insts])
+    box = np.array([list(d["box_lo"]) + list(d["box_hi"]) for d in insts], dtype=np.float64)
+    cfg = dict(
+        name=name,
+        params=params,
+        sigma=np.asarray(sigma, dtype=np.float64),
+        eps=np.asarray(eps, dtype=np.float64),
+        inst_off=off,
+        box=box,
+        pos=np.ascontiguousarray(pos),
+        nH=np.concatenate([d["nH"] for d in insts]),
+        NH=np.concatenate([d["NH"] for d in insts]),
+        xHI=np.concatenate([d["xHI"] for d in insts]),
+        T=np.concatenate([d["T"] for d in insts]),
+        sources=sources,
+        n_steps=n_steps,
+    )
+    return cfg
+
+
+def _point_sources(inst, pos, rate):
+    pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+    return dict(
+        inst=np.asarray(inst, dtype=np.int32),
+        kind=np.full(len(inst), SRC_POINT, dtype=np.int32),
+        pos=np.ascontiguousarray(pos),
+        rate=np.ascontiguousarray(np.asarray(rate, dtype=np.float64)),
+        n_side=np.zeros(len(inst), dtype=np.int32),
+    )
+
+
+def stromgren(n_side=16, box_kpc=6.6, rr=False, n_ngb=32, ndot=5e48, n_h=1e-3,
+              n_steps=100, seed_k=1, dt_myr=0.1, n_em=10, **pkw):
+    """Stromgren HII region (section 3 set-up, scaled): uniform neutral hydrogen,
+    one monochromatic 13.6 eV source at the exact box centre.  With rr=True a
+    second bin carries recombination photons (case A + explicit transport)."""
+    rng = np.random.default_rng(BASE_SEED + seed_k)
+    L = box_kpc * KPC_CM
+    lo = np.zeros(3)
+    pos = jittered_lattice(n_side, lo, L, rng)
+    nh, NH, xhi, T = _uniform_gas(pos, n_h, L, 1.0, 1e4)
+    n_freq = 2 if rr else 1
+    params = default_params(
+        n_ngb=n_ngb, n_freq=n_freq, rr_bin=(1 if rr else -1),
+        recomb_mode=(RR_TRANSPORT if rr else CASE_B_OTS),
+        dt=dt_myr * MYR_S, n_em=n_em, seed=BASE_SEED + seed_k)
+    params.update(pkw)
+    sigma = [SIGMA_13P6] * n_freq
+    eps = [0.0] * n_freq          # 13.6 eV photons carry no excess energy; isothermal runs
+    rate = np.zeros((1, n_freq))
+    rate[0, 0] = ndot
+    src = _point_sources([0], [L / 2, L / 2, L / 2], rate)
+    inst = dict(pos=pos, nH=nh, NH=NH, xHI=xhi, T=T, box_lo=lo, box_hi=lo + L)
+    return _pack(f"stromgren{n_side}{'_rr' if rr else ''}", params, sigma, eps, [inst], src, n_steps)
+
+
+def batched(n_inst=64, side_lo=8, side_hi=48, n_ngb=48, n_steps=100, seed_k=4, rr=True, **pkw):
+    """Many independent HII regions of uneven size in one batch: n_side log-uniform
+    in [side_lo, side_hi], n_H log-uniform in 1e-4..1e-1, Ndot log-uniform in
+    1e47..1e50, box side L = R_S / U(0.2, 0.4)."""
+    rng = np.random.default_rng(BASE_SEED + seed_k)
+    insts = []
+    rates = []
+    spos = []
+    x0 = 0.0
+    n_freq = 2 if rr else 1
+    for k in range(n_inst):
+        ns = int(round(math.exp(rng.uniform(math.log(side_lo), math.log(side_hi)))))
+        n_h = math.exp(rng.uniform(math.log(1e-4), math.log(1e-1)))
+        ndot = math.exp(rng.uniform(math.log(1e47), math.log(1e50)))
+        rs = (3.0 * ndot / (4.0 * math.pi * n_h * n_h * ALPHA_B_1E4)) ** (1.0 / 3.0)
+        L = rs / rng.uniform(0.2, 0.4)
+        lo = np.array([x0, 0.0, 0.0])
+        x0 += 2.0 * L          # instances sit side by side; each keeps its own box
+        pos = jittered_lattice(ns, lo, L, rng)
+        nh, NH, xhi, T = _uniform_gas(pos, n_h, L, 1.0, 1e4)
+        insts.append(dict(pos=pos, nH=nh, NH=NH, xHI=xhi, T=T, box_lo=lo, box_hi=lo + L))
+        r = np.zeros(n_freq)
+        r[0] = ndot
+        rates.append(r)
+        spos.append(lo + L / 2)
+    params = default_params(
+        n_ngb=n_ngb, n_freq=n_freq, rr_bin=(1 if rr else -1),
+        recomb_mode=(RR_TRANSPORT if rr else CASE_B_OTS), seed=BASE_SEED + seed_k)
+    params.update(pkw)
+    src = _point_sources(list(range(n_inst)), np.array(spos), np.array(rates))
+    return _pack(f"batched{n_inst}", params, [SIGMA_13P6] * n_freq, [0.0] * n_freq, insts, src, n_steps)
+
+
+def chain(n=12, spacing_kpc=0.1, n_h=1e-3, x_hi=1e-3, **pkw):
+    """A 1-D chain of particles along x with two neighbours each and a plane
+    front on the x = 0 face: used to check attenuation exp(-sigma n sum l)."""
+    L = n * spacing_kpc * KPC_CM
+    dxs = spacing_kpc * KPC_CM
+    pos = np.zeros((n, 3))
+    pos[:, 0] = (np.arange(n) + 0.5) * dxs
+    pos[:, 1] = 0.5 * dxs
+    pos[:, 2] = 0.5 * dxs
+    nh = np.full(n, n_h)
+    NH = nh * dxs ** 3
+    params = default_params(n_ngb=2, n_freq=1, n_em=1, freeze_chem=1)
+    params.update(pkw)
+    src = dict(inst=np.zeros(1, np.int32), kind=np.array([SRC_PLANE_XLO], np.int32),
+               pos=np.zeros((1, 3)), rate=np.array([[1e6]]), n_side=np.array([1], np.int32))
+    inst = dict(pos=pos, nH=nh, NH=NH, xHI=np.full(n, x_hi), T=np.full(n, 1e4),
+                box_lo=np.zeros(3), box_hi=np.array([L, dxs, dxs]))
+    return _pack("chain", params, [SIGMA_13P6], [0.0], [inst], src, 1)
+
+
+def config(k, **kw):
+    """Named workloads: 1 = 16^3 Stromgren case B (FP64), 2 = 64^3 with recombination
+    radiation (FP32 vs FP64), 4 = 64 batched instances with recombination radiation."""
+    if k == 1:
+        return stromgren(16, rr=False, n_ngb=32, n_steps=100, seed_k=1, **kw)
+    if k == 2:
+        return stromgren(64, rr=True, n_ngb=48, n_steps=500, seed_k=2, **kw)
+    if k == 4:
+        return batched(**kw)
+    raise ValueError(f"unknown workload {k}")
+
+
+def n_particles(cfg):
+    return int(cfg["pos"].shape[0])
