@@ -1,0 +1,171 @@
+/*
+ * traphic_rt.h -- C ABI of the MI355X (gfx950) implementation of one TRAPHIC
+ * radiative-transfer step on SPH particles with transport of ionizing
+ * recombination radiation (RR) in the particles' reception cones, after
+ * Raicevic, Pawlik, Schaye & Rahmati, "The effect of recombination radiation
+ * on the temperature and ionization state of partially ionized gas".
+ *
+ * Conventions for every entry point
+ *   - Units are cgs: positions in cm, densities in cm^-3, time in s, photon
+ *     counts in photons, energies in erg, temperatures in K.
+ *   - Every array argument is a HOST pointer, owned by the caller and only
+ *     read (inputs) or written (outputs) during the call.  The library copies
+ *     inputs to device memory it owns.
+ *   - All device work runs on the HIP stream given to rt_init.  rt_step only
+ *     enqueues work (it waits on the stream only to decide when a step's
+ *     forward steps have finished); rt_get_* synchronise the stream.
+ *   - On RT_EINVAL nothing changes.  After RT_EDEVICE only rt_destroy and
+ *     rt_last_error are valid.  No C++ exception crosses this interface.
+ *   - A context is not thread-safe.
+ */
+#ifndef TRAPHIC_RT_H
+#define TRAPHIC_RT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rt_ctx rt_ctx;
+
+typedef enum {
+    RT_OK = 0,
+    RT_EINVAL = 1,      /* bad argument; the context is unchanged */
+    RT_ENOMEM = 2,      /* device allocation failed */
+    RT_EDEVICE = 3,     /* a HIP call failed; the context is unusable */
+    RT_EHOPCAP = 4,     /* a step stopped at max_hops; unfinished packets stay in flight */
+    RT_ENONFINITE = 5,  /* a ledger entry is not finite */
+    RT_ESTATE = 6,      /* call out of order (e.g. state blob of the wrong size) */
+    RT_EOVERFLOW = 7    /* the virtual-particle or record buffer overflowed; photons were dropped */
+} rt_status;
+
+/* Treatment of recombinations (section 2.1 "case B with on-the-spot", "case A";
+ * section 2.2 explicit transport of the ground-state recombination photons). */
+enum { RT_CASE_B_OTS = 0, RT_CASE_A_NO_RR = 1, RT_RR_TRANSPORT = 2 };
+/* Arithmetic of the packet transport, absorption and merging.  Positions,
+ * chemistry and the photon ledger are FP64 in both. */
+enum { RT_FP64 = 0, RT_FP32 = 1 };
+/* Source kinds: a point source emitting in N_EC randomly rotated directions
+ * (section 2.1), or a plane-parallel front entering through the x = lo face
+ * of its box as a regular grid of emitters moving along +x (section 4 and its
+ * footnote on the front). */
+enum { RT_SRC_POINT = 0, RT_SRC_PLANE_XLO = 1 };
+
+typedef struct {
+    int32_t n_ngb;         /* SPH neighbours per particle, 1..64 */
+    int32_t n_tc;          /* transmission cones: cone solid angle 4 pi / N_TC, >= 3 */
+    int32_t n_rc;          /* reception cones per particle and bin: 1, 2, 4, 8, 16 or 32 */
+    int32_t n_ec;          /* emission cones of point sources, 1..64 */
+    int32_t n_freq;        /* grey frequency bins, 1..15 */
+    int32_t rr_bin;        /* bin that carries RR photons, or -1 */
+    int32_t recomb_mode;   /* RT_CASE_B_OTS, RT_CASE_A_NO_RR or RT_RR_TRANSPORT */
+    int32_t isothermal;    /* 1: T fixed; 0: photoheating and radiative cooling */
+    int32_t freeze_chem;   /* 1: ionization state and T frozen (transport-only runs) */
+    int32_t precision;     /* RT_FP64 or RT_FP32 */
+    int32_t n_em;          /* emission sub-steps per step (dt / dt_em), >= 1 */
+    int32_t max_hops;      /* cap on forward steps per RT step, >= 0 */
+    int32_t max_vip_depth; /* virtual particles chained at most this deep, 1..15 */
+    int32_t hop_batch;     /* forward steps enqueued between termination checks (0: 8) */
+    double dt;             /* RT and chemistry step, s */
+    double floor_rel;      /* packets below floor_rel * N_H of their particle are absorbed there */
+    double chem_frac;      /* chemistry sub-step: max relative change of x_HI or T */
+    uint64_t seed;         /* key of every random draw (rotations, virtual particles) */
+    int64_t vip_capacity;  /* virtual particles per forward step (0: default) */
+    int64_t record_capacity; /* arrival/deposit records per forward step (0: default) */
+    /* Optional device allocator (e.g. PyTorch's caching allocator).  NULL: hipMalloc/hipFree. */
+    void *(*alloc)(void *user, size_t bytes);
+    void (*dealloc)(void *user, void *ptr);
+    void *alloc_user;
+} rt_params;
+
+/* Create a context and build the neighbour lists of the static density field
+ * (section 2.1: packets move to neighbours inside the smoothing volume; the
+ * density field is static, so the lists are built once).
+ *   sigma_nu[n_freq]  grey cross-section per bin, cm^2 (section 2.1 grey approximation)
+ *   eps_nu[n_freq]    grey excess energy per photoionization, erg (for the RR bin: k T)
+ *   n_inst, inst_off[n_inst+1]  independent problems; particles of instance k
+ *                     are inst_off[k] .. inst_off[k+1]-1 (each needs > n_ngb particles)
+ *   box[n_inst*6]     lo_x lo_y lo_z hi_x hi_y hi_z of each instance (not periodic)
+ *   pos[N*3], n_H[N], N_H[N], x_HI0[N], T0[N]   particle data, N = inst_off[n_inst]
+ *   hip_stream        hipStream_t to run on (NULL: the null stream)
+ * Errors: RT_EINVAL (parameters, sizes, a particle outside its box), RT_ENOMEM,
+ * RT_EDEVICE. */
+rt_status rt_init(rt_ctx **out, const rt_params *p, const double *sigma_nu, const double *eps_nu,
+                  int32_t n_inst, const int64_t *inst_off, const double *box, const double *pos,
+                  const double *n_H, const double *N_H, const double *x_HI0, const double *T0,
+                  void *hip_stream);
+
+/* Set the sources (replacing earlier ones).  Section 2.1: a source emits
+ * N_EC x N_freq packets per emission sub-step, directions randomly rotated
+ * before each emission.
+ *   inst[n_src], kind[n_src]   instance and RT_SRC_* kind
+ *   pos[n_src*3]               point-source position (ignored for planes; must lie in its box)
+ *   rate[n_src*n_freq]         photons/s per bin (point) or photons/s/cm^2 per bin (plane)
+ *   n_side[n_src]              plane: emitters per side of the face grid; may be NULL if no planes
+ * Errors: RT_EINVAL, RT_ENOMEM, RT_EDEVICE. */
+rt_status rt_add_sources(rt_ctx *ctx, int32_t n_src, const int32_t *inst, const int32_t *kind,
+                         const double *pos, const double *rate, const int32_t *n_side);
+
+/* Advance n_steps RT steps, each followed by the chemistry step and the
+ * emission of the RR photons into the reception cones (sections 2.1, 2.2).
+ * Returns RT_EHOPCAP if a step hit max_hops (the state stays consistent),
+ * RT_EOVERFLOW if a work buffer overflowed, RT_ENONFINITE on a non-finite
+ * ledger, RT_EDEVICE on a HIP failure. */
+rt_status rt_step(rt_ctx *ctx, int32_t n_steps);
+
+/* Copy the state out (synchronises).  Any pointer may be NULL.
+ *   x_HI[N], T[N]
+ *   absorbed[N*n_freq], passing[N*n_freq]  photons absorbed by / arriving at each
+ *                     particle per bin during the last step (section 3 intensity
+ *                     diagnostic uses the passing photons)
+ *   ledger[n_inst*n_freq*5]  cumulative emitted, absorbed, escaped, removed, and
+ *                     photons still in flight (section 2.1: photon conserving)
+ *   counters[4]       steps, forward steps, virtual particles, packet updates */
+rt_status rt_get_state(rt_ctx *ctx, double *x_HI, double *T, double *absorbed, double *passing,
+                       double *ledger, int64_t *counters);
+
+/* Packet bins [N][n_freq][n_rc] in physical units: photons, unit direction
+ * (3 per bin) and clock in s since the start of the last step.  Any pointer may be NULL. */
+rt_status rt_get_bins(rt_ctx *ctx, double *N, double *dir, double *clock);
+
+/* Neighbour lists [N][n_ngb] (ascending distance, ties by index) and smoothing
+ * lengths h[N] (distance to the n_ngb-th neighbour).  Either may be NULL. */
+rt_status rt_get_neighbours(rt_ctx *ctx, int32_t *ngb, double *h);
+
+/* Number of emitters (point sources plus plane-front grid points), and their
+ * neighbour lists [n_emit][n_ngb] and h[n_emit]. */
+int64_t rt_n_emitters(const rt_ctx *ctx);
+rt_status rt_get_emitter_neighbours(rt_ctx *ctx, int32_t *ngb, double *h);
+
+/* Transmission-cone membership of the packets that move in the next forward
+ * step: bit k of mask[b] is set when neighbour k of the packet's particle is in
+ * the packet's cone; 0 for packets that will not move.  mask[N*n_freq*n_rc]. */
+rt_status rt_get_cone_masks(rt_ctx *ctx, uint64_t *mask);
+
+/* Recombination photons waiting to be emitted at the start of the next step, [N]. */
+rt_status rt_get_pending_rr(rt_ctx *ctx, double *nrr);
+
+/* Timing of the last rt_step, in ms, accumulated over its kernels (only when
+ * timing is on): out[0] transport kernel total, out[1] launches of it, out[2]
+ * virtual-particle kernel total, out[3] chemistry, out[4] emission, out[5]
+ * ledger, out[6] bytes the transport kernel must move per launch on average
+ * (algorithmic, from the packets it handled). */
+rt_status rt_set_timing(rt_ctx *ctx, int32_t on);
+rt_status rt_get_timing(rt_ctx *ctx, double *out, int32_t n);
+
+/* Checkpoint: the full dynamic state (bins, ionization state, temperatures,
+ * pending RR photons, ledger, counters) as an opaque blob.  rt_get_state_blob
+ * with blob == NULL returns the size in *bytes.  rt_set_state_blob restores a
+ * blob taken from a context with identical inputs (RT_ESTATE otherwise). */
+rt_status rt_get_state_blob(rt_ctx *ctx, void *blob, size_t *bytes);
+rt_status rt_set_state_blob(rt_ctx *ctx, const void *blob, size_t bytes);
+
+void rt_destroy(rt_ctx *ctx);
+const char *rt_last_error(const rt_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

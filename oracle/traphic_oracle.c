@@ -663,6 +663,21 @@ static void merge_in(or_sim *S, int64_t t, double N, const double d[3], double c
     S->aC[t] += N * c;
 }
 
+/* Split N_in photons over optical depth tau into absorbed N_in (1 - exp(-tau))
+ * and transmitted N_in exp(-tau) (section 2.1).  Reading: the smaller of the
+ * two parts is evaluated directly and the other is the remainder, so that both
+ * keep full relative precision at any tau and their sum is N_in. */
+static void attenuate(double N_in, double tau, double *Nabs, double *Nout)
+{
+    if (tau < 0.6931471805599453) {
+        *Nabs = -N_in * expm1(-tau);
+        *Nout = N_in - *Nabs;
+    } else {
+        *Nout = N_in * exp(-tau);
+        *Nabs = N_in - *Nout;
+    }
+}
+
 /* One packet leg onto real particle j (section 2.1): tau = sigma_nu n_HI,j l,
  * N_abs = N_in (1 - exp(-tau)); the rest arrives at j, keeping its direction
  * (reading: the sub-packet keeps the parent's propagation direction), its clock
@@ -671,8 +686,8 @@ static void leg_to_particle(or_sim *S, int64_t j, int nu, const double d[3], dou
                             double c_prev)
 {
     double tau = S->sigma[nu] * S->xHI[j] * S->nH[j] * l;
-    double Nabs = -N_in * expm1(-tau);
-    double Nout = N_in - Nabs;
+    double Nabs, Nout;
+    attenuate(N_in, tau, &Nabs, &Nout);
     S->A[j * S->nf + nu] += Nabs;
     S->P[j * S->nf + nu] += N_in;
     int r = nearest_dir(S->w_rc, S->p.n_rc, d);
@@ -800,9 +815,9 @@ static void vip_chain(or_sim *S, vip_req q, double *X, double *R)
         double dd = sqrt(dot3(q.d, q.d));
         double l = ((xv[0] - q.x[0]) * q.d[0] + (xv[1] - q.x[1]) * q.d[1] + (xv[2] - q.x[2]) * q.d[2]) / dd;
         double tau = S->sigma[q.nu] * nhi * l;
-        double Nabs = -q.N * expm1(-tau);
+        double Nabs, Nrem;
+        attenuate(q.N, tau, &Nabs, &Nrem);
         for (int k = 0; k < K; ++k) S->A[(int64_t)vn[k] * nf + q.nu] += Nabs * wk[k] / wsum;
-        double Nrem = q.N - Nabs;
         double cv = q.c + l / C_LIGHT;
         int nc = 0;
         for (int k = 0; k < K; ++k) {

@@ -1,0 +1,241 @@
+// rt_device.hpp -- device building blocks of the TRAPHIC step on gfx950:
+// counter-based random numbers, rotations, the transmission-cone test, the
+// grid-binned k-nearest-neighbour query, the SPH kernel and the rate fits of
+// the chemistry.  Everything here runs on the GPU (some helpers are also
+// callable on the host for set-up).  Compiled with -ffp-contract=off so that
+// the FP64 arithmetic is plain IEEE operations in source order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace trt {
+
+constexpr double kCLight = 2.99792458e10;  // cm/s
+constexpr double kBoltz = 1.380649e-16;    // erg/K
+constexpr double kTHI = 157807.0;          // K, hydrogen ionization potential over k_B
+constexpr double kTCMB = 2.725;            // K, CMB temperature today
+constexpr int kMaxNgb = 64;
+constexpr uint32_t kVipAttempts = 65536;
+
+// Purposes of random draws (first counter word).
+enum : uint32_t { kTagRC = 1, kTagEC = 2, kTagVipT = 3, kTagVipE = 4 };
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two
+// 32x32->64 multiplies and xors with a Weyl-sequence key schedule.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int rnd = 0; rnd < 10; ++rnd) {
+        const uint64_t m0 = static_cast<uint64_t>(0xD2511F53u) * c[0];
+        const uint64_t m1 = static_cast<uint64_t>(0xCD9E8D57u) * c[2];
+        const uint32_t n0 = static_cast<uint32_t>(m1 >> 32) ^ c[1] ^ k0;
+        const uint32_t n2 = static_cast<uint32_t>(m0 >> 32) ^ c[3] ^ k1;
+        c[1] = static_cast<uint32_t>(m1);
+        c[3] = static_cast<uint32_t>(m0);
+        c[0] = n0;
+        c[2] = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// Four uniforms on (-1, 1), each an exact double (32-bit resolution).
+__host__ __device__ inline void uniforms4(uint64_t seed, uint32_t tag, uint32_t attempt,
+                                          uint32_t step, uint32_t a, uint32_t b, double u[4]) {
+    uint32_t c[4] = {tag | (attempt << 4), step, a, b};
+    philox4x32_10(c, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double v = (static_cast<double>(c[i]) + 0.5) * (1.0 / 4294967296.0);
+        u[i] = 2.0 * v - 1.0;
+    }
+}
+
+// Haar-uniform rotation: a uniform point of the unit 4-ball (rejection), made
+// a unit quaternion, turned into its rotation matrix (row major).
+__host__ __device__ inline void random_rotation(uint64_t seed, uint32_t tag, uint32_t step,
+                                                uint32_t a, uint32_t b, double R[9]) {
+    double q[4];
+    double s = 0.0;
+    for (uint32_t att = 0;; ++att) {
+        uniforms4(seed, tag, att, step, a, b, q);
+        s = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+        if (s <= 1.0 && s >= 1e-6) break;
+    }
+    const double n = sqrt(s);
+    const double w = q[0] / n, x = q[1] / n, y = q[2] / n, z = q[3] / n;
+    R[0] = 1.0 - 2.0 * (y * y + z * z);
+    R[1] = 2.0 * (x * y - w * z);
+    R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);
+    R[4] = 1.0 - 2.0 * (x * x + z * z);
+    R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);
+    R[7] = 2.0 * (y * z + w * x);
+    R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+__host__ __device__ inline void rotate3(const double R[9], const double u[3], double o[3]) {
+    o[0] = R[0] * u[0] + R[1] * u[1] + R[2] * u[2];
+    o[1] = R[3] * u[0] + R[4] * u[1] + R[5] * u[2];
+    o[2] = R[6] * u[0] + R[7] * u[1] + R[8] * u[2];
+}
+
+// Transmission cone of solid angle 4 pi / N_TC around d (half-angle with
+// cosine C = 1 - 2/N_TC): v.d > 0 and (v.d)^2 >= C^2 |v|^2 |d|^2, inclusive.
+template <typename R>
+__host__ __device__ inline bool in_cone(R vx, R vy, R vz, R dx, R dy, R dz, R c2) {
+    const R a = vx * dx + vy * dy + vz * dz;
+    if (!(a > R(0))) return false;
+    return a * a >= c2 * (vx * vx + vy * vy + vz * vz) * (dx * dx + dy * dy + dz * dz);
+}
+
+// Index of the direction in w[n][3] with the largest dot product with d
+// (ties to the lower index): reception-cone binning and Voronoi emission cones.
+template <typename R>
+__host__ __device__ inline int nearest_direction(const R* w, int n, R dx, R dy, R dz) {
+    int best = 0;
+    R bv = dx * w[0] + dy * w[1] + dz * w[2];
+    for (int k = 1; k < n; ++k) {
+        const R v = dx * w[3 * k] + dy * w[3 * k + 1] + dz * w[3 * k + 2];
+        if (v > bv) {
+            bv = v;
+            best = k;
+        }
+    }
+    return best;
+}
+
+// Absorbed N_in (1 - e^-tau) and transmitted N_in e^-tau parts of a packet leg:
+// the smaller part is evaluated directly, the larger is the remainder, so both
+// keep full relative precision at any optical depth and they sum to N_in.
+template <typename R>
+__device__ inline void attenuate(R nin, R tau, R& nabs, R& nout) {
+    if (tau < R(0.6931471805599453)) {
+        nabs = -nin * expm1(-tau);
+        nout = nin - nabs;
+    } else {
+        nout = nin * exp(-tau);
+        nabs = nin - nout;
+    }
+}
+
+// Cubic-spline kernel shape with support h (Monaghan & Lattanzio 1985); its
+// normalisation cancels in normalised interpolation weights.
+__device__ inline double spline_shape(double r, double h) {
+    const double q = r / h;
+    if (q < 0.5) return 1.0 - 6.0 * q * q + 6.0 * q * q * q;
+    if (q < 1.0) {
+        const double t = 1.0 - q;
+        return 2.0 * t * t * t;
+    }
+    return 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Rate fits (cgs).  Recombination: Hui & Gnedin (1997) case A and B;
+// collisional ionization: Hui & Gnedin (1997); cooling: HG97 recombination
+// cooling, Cen (1992) collisional excitation, free-free (Gaunt factor 1.3),
+// Compton cooling off the z = 0 CMB.
+// ---------------------------------------------------------------------------
+struct Rates {
+    double aA, aB, beta, recA, recB, cexc, ff, compton;
+};
+
+__device__ inline Rates rates_at(double T) {
+    Rates r;
+    const double lam = 2.0 * kTHI / T;
+    r.aA = 1.269e-13 * pow(lam, 1.503) / pow(1.0 + pow(lam / 0.522, 0.470), 1.923);
+    r.aB = 2.753e-14 * pow(lam, 1.500) / pow(1.0 + pow(lam / 2.740, 0.407), 2.242);
+    r.beta = 21.11 * pow(T, -1.5) * exp(-lam / 2.0) * pow(lam, -1.089) /
+             pow(1.0 + pow(lam / 0.354, 0.874), 1.101);
+    r.recA = 1.778e-29 * T * pow(lam, 1.965) / pow(1.0 + pow(lam / 0.541, 0.502), 2.697);
+    r.recB = 3.435e-30 * T * pow(lam, 1.970) / pow(1.0 + pow(lam / 2.250, 0.376), 3.720);
+    r.cexc = 7.5e-19 * exp(-118348.0 / T) / (1.0 + sqrt(T / 1e5));
+    r.ff = 1.42e-27 * 1.3 * sqrt(T);
+    r.compton = 1.017e-37 * pow(kTCMB, 4.0) * (T - kTCMB);
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Uniform cell grid of one instance and the exact k-nearest-neighbour query.
+// The result is the N_ngb smallest (d^2, index) pairs, d^2 = (dx dx + dy dy)
+// + dz dz with d = x_j - q, which does not depend on the grid.
+// ---------------------------------------------------------------------------
+struct GridInfo {
+    int nc[3];
+    int pad;
+    double lo[3];
+    double cs[3];
+    long long cell0;
+};
+
+__device__ inline void knn_insert(double* bd, int* bi, int& cnt, int K, double d2, int j) {
+    if (cnt == K) {
+        const double ld = bd[K - 1];
+        if (d2 > ld || (d2 == ld && j > bi[K - 1])) return;
+    }
+    int pos = (cnt < K) ? cnt++ : K - 1;
+    while (pos > 0 && (bd[pos - 1] > d2 || (bd[pos - 1] == d2 && bi[pos - 1] > j))) {
+        bd[pos] = bd[pos - 1];
+        bi[pos] = bi[pos - 1];
+        --pos;
+    }
+    bd[pos] = d2;
+    bi[pos] = j;
+}
+
+// Fills bi[0..K) / bd[0..K) sorted ascending; returns h = sqrt(bd[K-1]).
+__device__ inline double knn_query(const GridInfo& g, const int* __restrict__ cell_start,
+                                   const int* __restrict__ cell_idx, const double* __restrict__ pos,
+                                   double qx, double qy, double qz, int self, int K, double* bd,
+                                   int* bi) {
+    int cnt = 0;
+    int c[3];
+    const double q[3] = {qx, qy, qz};
+    for (int a = 0; a < 3; ++a) {
+        int v = static_cast<int>(floor((q[a] - g.lo[a]) / g.cs[a]));
+        v = v < 0 ? 0 : (v >= g.nc[a] ? g.nc[a] - 1 : v);
+        c[a] = v;
+    }
+    double csmin = g.cs[0] < g.cs[1] ? g.cs[0] : g.cs[1];
+    csmin = csmin < g.cs[2] ? csmin : g.cs[2];
+    int smax = g.nc[0] > g.nc[1] ? g.nc[0] : g.nc[1];
+    smax = smax > g.nc[2] ? smax : g.nc[2];
+    for (int s = 0; s <= smax; ++s) {
+        const int x0 = c[0] - s < 0 ? 0 : c[0] - s, x1 = c[0] + s >= g.nc[0] ? g.nc[0] - 1 : c[0] + s;
+        const int y0 = c[1] - s < 0 ? 0 : c[1] - s, y1 = c[1] + s >= g.nc[1] ? g.nc[1] - 1 : c[1] + s;
+        const int z0 = c[2] - s < 0 ? 0 : c[2] - s, z1 = c[2] + s >= g.nc[2] ? g.nc[2] - 1 : c[2] + s;
+        for (int ix = x0; ix <= x1; ++ix) {
+            const int ex = abs(ix - c[0]);
+            for (int iy = y0; iy <= y1; ++iy) {
+                const int exy = max(ex, abs(iy - c[1]));
+                for (int iz = z0; iz <= z1; ++iz) {
+                    // only the shell at Chebyshev distance s
+                    if (max(exy, abs(iz - c[2])) != s) {
+                        if (iz < c[2] + s && exy < s) iz = c[2] + s - 1;  // skip the interior
+                        continue;
+                    }
+                    const long long cell = g.cell0 + (static_cast<long long>(ix) * g.nc[1] + iy) * g.nc[2] + iz;
+                    const int t1 = cell_start[cell + 1];
+                    for (int t = cell_start[cell]; t < t1; ++t) {
+                        const int j = cell_idx[t];
+                        if (j == self) continue;
+                        const double dx = pos[3 * static_cast<long long>(j) + 0] - qx;
+                        const double dy = pos[3 * static_cast<long long>(j) + 1] - qy;
+                        const double dz = pos[3 * static_cast<long long>(j) + 2] - qz;
+                        const double d2 = dx * dx + dy * dy + dz * dz;
+                        knn_insert(bd, bi, cnt, K, d2, j);
+                    }
+                }
+            }
+        }
+        const double reach = static_cast<double>(s) * csmin;
+        if (cnt == K && bd[K - 1] <= reach * reach) break;
+    }
+    return sqrt(bd[K - 1]);
+}
+
+}  // namespace trt

@@ -1,0 +1,1107 @@
+// traphic_rt.hip -- host side of the MI355X TRAPHIC library: context, device
+// memory, the C ABI of include/traphic_rt.h and the launch sequence of a step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/traphic_rt.h"
+#include "rt_kernels.hpp"
+
+using namespace trt;
+
+namespace {
+
+constexpr int kChunk = 2048;      // particles per ledger partial sum
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t n = 0;
+};
+
+}  // namespace
+
+struct rt_ctx {
+    rt_params p{};
+    hipStream_t stream = nullptr;
+    bool sticky = false;
+    std::string err;
+
+    long long N = 0, B = 0;
+    int n_inst = 0, G = 0, nf = 0, K = 0, nrc = 0, nec = 0, nsub = 1;
+    bool f32 = false, rr_on = false;
+    double c2 = 0.0;
+    std::vector<long long> inst_off;
+    std::vector<double> box, sigma, eps, U, L;
+    std::vector<DevBuf> owned;
+
+    // static geometry
+    int* inst_of = nullptr;
+    double* box_d = nullptr;
+    double* pos = nullptr;
+    float4* posf = nullptr;
+    double *nH = nullptr, *NH = nullptr, *xHI = nullptr, *T = nullptr, *h = nullptr;
+    void* floor_b = nullptr;
+    float* kappa = nullptr;
+    double* sigma_d = nullptr;
+    float* sigmaf_d = nullptr;
+    double* eps_d = nullptr;
+    double* U_d = nullptr;
+    double* L_d = nullptr;
+    float* clf_d = nullptr;
+    int* ngb = nullptr;
+    int* rev_off = nullptr;
+    int* rev_src = nullptr;
+    unsigned char* rev_pos = nullptr;
+    GridInfo* grid_d = nullptr;
+    int* cell_start = nullptr;
+    int* cell_idx = nullptr;
+    double *u_rc = nullptr, *u_ec = nullptr;
+    double* rot = nullptr;
+    float* wrcf = nullptr;
+    // emitters
+    long long n_emit = 0;
+    int* em_kind = nullptr;
+    int* em_inst = nullptr;
+    double* em_pos = nullptr;
+    double* em_pk = nullptr;
+    int* em_ngb = nullptr;
+    double* em_h = nullptr;
+    double* ecd = nullptr;
+    double* exs = nullptr;
+    double* ers = nullptr;
+    std::vector<int> h_em_inst;
+    double* E_src = nullptr;
+    // dynamic state
+    void* pk[2] = {nullptr, nullptr};
+    void* pc[2] = {nullptr, nullptr};
+    unsigned long long* cm[2] = {nullptr, nullptr};
+    unsigned int* sm[2] = {nullptr, nullptr};
+    int cur = 0;
+    double *A = nullptr, *P = nullptr;
+    double* nrr[2] = {nullptr, nullptr};
+    int nrr_cur = 0;
+    double *xs = nullptr, *rs = nullptr;
+    Vip* vip[2] = {nullptr, nullptr};
+    long long vip_cap = 0;
+    Rec* rec = nullptr;
+    int* rec_next = nullptr;
+    int* head[2] = {nullptr, nullptr};
+    long long rec_cap = 0;
+    long long* cnt = nullptr;
+    long long* h_cnt = nullptr;  // pinned host mirror
+    double* led = nullptr;
+    double* scale = nullptr;
+    double* partial = nullptr;
+    long long n_chunks = 0;
+    int* chunk_inst = nullptr;
+    long long* chunk_lo = nullptr;
+    long long* chunk_hi = nullptr;
+    long long* inst_chunk0 = nullptr;
+    long long step = 0;
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    double tm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+};
+
+namespace {
+
+rt_status fail(rt_ctx* c, rt_status s, const std::string& m) {
+    if (c) {
+        c->err = m;
+        if (s == RT_EDEVICE) c->sticky = true;
+    }
+    return s;
+}
+
+#define HIPCHK(ctx, call)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(ctx, RT_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+rt_status dalloc(rt_ctx* c, void** out, size_t bytes) {
+    bytes = std::max<size_t>(bytes, 256);
+    void* q = nullptr;
+    if (c->p.alloc) {
+        q = c->p.alloc(c->p.alloc_user, bytes);
+        if (!q) return fail(c, RT_ENOMEM, "allocator callback returned NULL");
+    } else {
+        hipError_t e = hipMalloc(&q, bytes);
+        if (e != hipSuccess) return fail(c, RT_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    c->owned.push_back({q, bytes});
+    *out = q;
+    return RT_OK;
+}
+
+template <typename T>
+rt_status alloc_n(rt_ctx* c, T** out, long long n) {
+    return dalloc(c, reinterpret_cast<void**>(out), sizeof(T) * static_cast<size_t>(std::max<long long>(n, 1)));
+}
+
+template <typename T>
+rt_status upload(rt_ctx* c, T** out, const T* host, long long n) {
+    rt_status s = alloc_n(c, out, n);
+    if (s != RT_OK) return s;
+    if (n > 0) HIPCHK(c, hipMemcpyAsync(*out, host, sizeof(T) * n, hipMemcpyHostToDevice, c->stream));
+    return RT_OK;
+}
+
+unsigned grid_for(long long n, int bs) { return static_cast<unsigned>(std::max<long long>(1, (n + bs - 1) / bs)); }
+
+// Isotropic direction sets: the cube diagonals for 8, otherwise a spherical
+// Fibonacci lattice on one hemisphere mirrored through the centre.
+void direction_set(int n, std::vector<double>& u) {
+    u.assign(3 * n, 0.0);
+    if (n == 8) {
+        const double s = 1.0 / std::sqrt(3.0);
+        for (int k = 0; k < 8; ++k) {
+            u[3 * k + 0] = (k & 4) ? -s : s;
+            u[3 * k + 1] = (k & 2) ? -s : s;
+            u[3 * k + 2] = (k & 1) ? -s : s;
+        }
+        return;
+    }
+    const double ga = M_PI * (3.0 - std::sqrt(5.0));
+    const int half = (n % 2 == 0) ? n / 2 : n;
+    for (int k = 0; k < half; ++k) {
+        const double z = 1.0 - (2.0 * k + 1.0) / static_cast<double>(n);
+        const double r = std::sqrt(1.0 - z * z);
+        const double ph = ga * static_cast<double>(k);
+        u[3 * k + 0] = r * std::cos(ph);
+        u[3 * k + 1] = r * std::sin(ph);
+        u[3 * k + 2] = z;
+    }
+    for (int k = half; k < n; ++k)
+        for (int a = 0; a < 3; ++a) u[3 * k + a] = -u[3 * (k - half) + a];
+}
+
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+template <typename R>
+rt_status launch_hop(rt_ctx* c, int hop, int base) {
+    HopArgs<R> a{};
+    a.N = c->N;
+    a.B = c->B;
+    a.G = c->G;
+    a.nrc = c->nrc;
+    a.nf = c->nf;
+    a.K = c->K;
+    a.rr_bin = c->p.rr_bin;
+    a.rr_on = c->rr_on ? 1 : 0;
+    a.hop = hop;
+    a.hop0 = hop == 0;
+    a.max_hops = c->p.max_hops;
+    a.pos = c->pos;
+    a.posf = c->posf;
+    a.ngb = c->ngb;
+    a.rev_off = c->rev_off;
+    a.rev_src = c->rev_src;
+    a.rev_pos = c->rev_pos;
+    a.inst_of = c->inst_of;
+    a.xHI = c->xHI;
+    a.nH = c->nH;
+    a.kappa = c->kappa;
+    a.floor_b = static_cast<const R*>(c->floor_b);
+    a.h = c->h;
+    a.sigma = c->sigma_d;
+    a.sigmaf = c->sigmaf_d;
+    a.c2 = static_cast<R>(c->c2);
+    a.dtc = c->f32 ? R(1) : static_cast<R>(c->p.dt);
+    a.clf = c->clf_d;
+    a.U = c->U_d;
+    a.scale = c->scale;
+    a.nrr_prev = c->nrr[c->nrr_cur];
+    a.wrc = c->rot + 9;
+    a.wrcf = c->wrcf;
+    a.dt = c->p.dt;
+    const int rd = (base + hop) & 1, wr = rd ^ 1;
+    a.pk_rd = static_cast<const Bin4<R>*>(c->pk[rd]);
+    a.pc_rd = static_cast<const R*>(c->pc[rd]);
+    a.cm_rd = c->cm[rd];
+    a.sm_rd = c->sm[rd];
+    a.pk_wr = static_cast<Bin4<R>*>(c->pk[wr]);
+    a.pc_wr = static_cast<R*>(c->pc[wr]);
+    a.cm_wr = c->cm[wr];
+    a.sm_wr = c->sm[wr];
+    a.A = c->A;
+    a.P = c->P;
+    a.rec = c->rec;
+    a.rec_next = c->rec_next;
+    a.head_rd = c->head[hop & 1];
+    a.head_reset = c->head[(hop + 1) & 1];
+    a.vip_out = c->vip[(hop + 1) & 1];
+    a.vip_cap = c->vip_cap;
+    a.list_wr = (hop + 1) & 1;
+    a.cnt = c->cnt;
+    a.act_rd = hop & 1;
+    a.act_wr = (hop + 1) & 1;
+    hipLaunchKernelGGL(k_hop<R>, dim3(grid_for(c->B, 256)), dim3(256), 0, c->stream, a);
+    HIPCHK(c, hipGetLastError());
+    return RT_OK;
+}
+
+rt_status launch_vip(rt_ctx* c, int hop) {
+    VipArgs a{};
+    a.hop = hop;
+    a.hop0 = hop == 0;
+    a.max_hops = c->p.max_hops;
+    a.K = c->K;
+    a.nf = c->nf;
+    a.nrc = c->nrc;
+    a.nec = c->nec;
+    a.max_depth = c->p.max_vip_depth;
+    a.seed = c->p.seed;
+    a.step = static_cast<uint32_t>(c->step);
+    a.c2 = c->c2;
+    a.list = c->vip[hop & 1];
+    a.vip_cap = c->vip_cap;
+    a.box = c->box_d;
+    a.grid = c->grid_d;
+    a.cell_start = c->cell_start;
+    a.cell_idx = c->cell_idx;
+    a.pos = c->pos;
+    a.xHI = c->xHI;
+    a.nH = c->nH;
+    a.NH = c->NH;
+    a.sigma = c->sigma_d;
+    a.wrc = c->rot + 9;
+    a.ecd = c->ecd;
+    a.xs = c->xs;
+    a.rs = c->rs;
+    a.exs = c->exs;
+    a.ers = c->ers;
+    a.rec = c->rec;
+    a.rec_next = c->rec_next;
+    a.head = c->head[hop & 1];
+    a.rec_cap = c->rec_cap;
+    a.cnt = c->cnt;
+    a.act_rd = hop & 1;
+    a.act_wr = (hop + 1) & 1;
+    a.list_rd = hop & 1;
+    a.list_wr = (hop + 1) & 1;
+    hipLaunchKernelGGL(k_vip, dim3(256), dim3(64), 0, c->stream, a);
+    HIPCHK(c, hipGetLastError());
+    return RT_OK;
+}
+
+__global__ void k_step_reset(long long* cnt) {
+    if (threadIdx.x == 0) {
+        cnt[kCntAct0] = 0;
+        cnt[kCntAct0 + 1] = 0;
+        cnt[kCntVipCnt0] = 0;
+        cnt[kCntVipCnt0 + 1] = 0;
+        cnt[kCntRec] = 0;
+        cnt[kCntHopsStep] = 0;
+        cnt[kCntDone] = 0;
+        cnt[kCntSteps] += 1;
+    }
+}
+
+__global__ void k_kappa_init(long long N, const double* xHI, const double* nH, const double* L, const int* inst_of, float* kappa) {
+    const long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (j < N) kappa[j] = static_cast<float>(xHI[j] * nH[j] * L[inst_of[j]]);
+}
+
+rt_status fill_i32(rt_ctx* c, int* p, long long n, int v) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(std::min<unsigned>(grid_for(n, 256), 4096)), dim3(256), 0, c->stream, p, n, v);
+    HIPCHK(c, hipGetLastError());
+    return RT_OK;
+}
+rt_status fill_f64(rt_ctx* c, double* p, long long n, double v) {
+    hipLaunchKernelGGL(k_fill_f64, dim3(std::min<unsigned>(grid_for(n, 256), 4096)), dim3(256), 0, c->stream, p, n, v);
+    HIPCHK(c, hipGetLastError());
+    return RT_OK;
+}
+
+#define TRY(x)                        \
+    do {                              \
+        rt_status s_ = (x);           \
+        if (s_ != RT_OK) return s_;   \
+    } while (0)
+
+rt_status time_begin(rt_ctx* c, size_t slot) {
+    if (!c->timing) return RT_OK;
+    while (c->ev.size() < 2 * (slot + 1)) {
+        hipEvent_t e;
+        HIPCHK(c, hipEventCreate(&e));
+        c->ev.push_back(e);
+    }
+    HIPCHK(c, hipEventRecord(c->ev[2 * slot], c->stream));
+    return RT_OK;
+}
+rt_status time_end(rt_ctx* c, size_t slot) {
+    if (!c->timing) return RT_OK;
+    HIPCHK(c, hipEventRecord(c->ev[2 * slot + 1], c->stream));
+    return RT_OK;
+}
+float elapsed(rt_ctx* c, size_t slot) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev[2 * slot], c->ev[2 * slot + 1]) != hipSuccess) return 0.f;
+    return ms;
+}
+
+// One RT step (sections 2.1 and 2.2): rotations, emission, forward steps
+// until no packet is active, chemistry, ledger.
+rt_status one_step(rt_ctx* c, bool* hopcap) {
+    const int base = c->cur;
+    // timing slots: 0 emission, 1 chemistry, 2 ledger, 3.. hops (vip then hop)
+    TRY(fill_i32(c, c->head[0], c->N, -1));
+    TRY(fill_i32(c, c->head[1], c->N, -1));
+    TRY(fill_f64(c, c->A, c->N * c->nf, 0.0));
+    TRY(fill_f64(c, c->P, c->N * c->nf, 0.0));
+    hipLaunchKernelGGL(k_step_reset, dim3(1), dim3(64), 0, c->stream, c->cnt);
+    HIPCHK(c, hipGetLastError());
+    TRY(time_begin(c, 0));
+    StepBeginArgs sb{};
+    sb.seed = c->p.seed;
+    sb.step = static_cast<uint32_t>(c->step);
+    sb.nrc = c->nrc;
+    sb.nec = c->nec;
+    sb.nsub = c->nsub;
+    sb.n_emit = c->n_emit;
+    sb.u_rc = c->u_rc;
+    sb.u_ec = c->u_ec;
+    sb.em_kind = c->em_kind;
+    sb.rot = c->rot;
+    sb.wrcf = c->wrcf;
+    sb.ecd = c->ecd;
+    hipLaunchKernelGGL(k_step_rotations, dim3(grid_for(std::max<long long>(1, c->n_emit * c->nsub), 64)), dim3(64), 0,
+                       c->stream, sb);
+    HIPCHK(c, hipGetLastError());
+    if (c->n_emit > 0) {
+        EmitArgs ea{};
+        ea.n_emit = c->n_emit;
+        ea.K = c->K;
+        ea.nf = c->nf;
+        ea.nrc = c->nrc;
+        ea.nec = c->nec;
+        ea.nsub = c->nsub;
+        ea.n_em = c->p.n_em;
+        ea.c2 = c->c2;
+        ea.em_kind = c->em_kind;
+        ea.em_inst = c->em_inst;
+        ea.em_pos = c->em_pos;
+        ea.em_pk = c->em_pk;
+        ea.em_ngb = c->em_ngb;
+        ea.em_h = c->em_h;
+        ea.ecd = c->ecd;
+        ea.pos = c->pos;
+        ea.xHI = c->xHI;
+        ea.nH = c->nH;
+        ea.sigma = c->sigma_d;
+        ea.wrc = c->rot + 9;
+        ea.rec = c->rec;
+        ea.rec_next = c->rec_next;
+        ea.head = c->head[0];
+        ea.rec_cap = c->rec_cap;
+        ea.vip = c->vip[0];
+        ea.vip_cap = c->vip_cap;
+        ea.cnt = c->cnt;
+        hipLaunchKernelGGL(k_emit, dim3(grid_for(c->n_emit * c->nsub * c->K, 256)), dim3(256), 0, c->stream, ea);
+        HIPCHK(c, hipGetLastError());
+    }
+    TRY(launch_vip(c, 0));
+    TRY(time_end(c, 0));
+    TRY(time_begin(c, 3));
+    if (c->f32)
+        TRY(launch_hop<float>(c, 0, base));
+    else
+        TRY(launch_hop<double>(c, 0, base));
+    TRY(time_end(c, 3));
+    const int batch = c->p.hop_batch > 0 ? c->p.hop_batch : 8;
+    long long H = 0;
+    int h = 1;
+    for (;;) {
+        if (h <= c->p.max_hops) {
+            const int hend = std::min(h + batch - 1, c->p.max_hops);
+            for (int q = h; q <= hend; ++q) {
+                TRY(time_begin(c, 2 + 2 * q));
+                TRY(launch_vip(c, q));
+                TRY(time_end(c, 2 + 2 * q));
+                TRY(time_begin(c, 3 + 2 * q));
+                if (c->f32)
+                    TRY(launch_hop<float>(c, q, base));
+                else
+                    TRY(launch_hop<double>(c, q, base));
+                TRY(time_end(c, 3 + 2 * q));
+            }
+            h = hend + 1;
+        }
+        HIPCHK(c, hipMemcpyAsync(c->h_cnt, c->cnt, sizeof(long long) * kCntN, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        H = c->h_cnt[kCntHopsStep];
+        const long long act = c->h_cnt[kCntAct0 + ((H + 1) & 1)];
+        if (act == 0) break;
+        if (H >= c->p.max_hops) {
+            *hopcap = true;
+            break;
+        }
+    }
+    c->cur = static_cast<int>((base + H + 1) & 1);
+    // chemistry
+    TRY(time_begin(c, 1));
+    ChemArgs ca{};
+    ca.N = c->N;
+    ca.nf = c->nf;
+    ca.mode = c->p.recomb_mode;
+    ca.isothermal = c->p.isothermal;
+    ca.freeze = c->p.freeze_chem;
+    ca.rr_on = c->rr_on ? 1 : 0;
+    ca.dt = c->p.dt;
+    ca.frac = c->p.chem_frac;
+    ca.A = c->A;
+    ca.eps = c->eps_d;
+    ca.nH = c->nH;
+    ca.NH = c->NH;
+    ca.xHI = c->xHI;
+    ca.T = c->T;
+    ca.nrr_wr = c->nrr[c->nrr_cur ^ 1];
+    ca.kappa = c->f32 ? c->kappa : nullptr;
+    ca.Linst = c->L_d;
+    ca.inst_of = c->inst_of;
+    hipLaunchKernelGGL(k_chem, dim3(grid_for(c->N, 256)), dim3(256), 0, c->stream, ca);
+    HIPCHK(c, hipGetLastError());
+    TRY(time_end(c, 1));
+    // ledger
+    TRY(time_begin(c, 2));
+    LedgerArgs la{};
+    la.nf = c->nf;
+    la.nrc = c->nrc;
+    la.G = c->G;
+    la.rr_bin = c->p.rr_bin;
+    la.rr_on = c->rr_on ? 1 : 0;
+    la.f32 = c->f32 ? 1 : 0;
+    la.n_chunks = c->n_chunks;
+    la.chunk_inst = c->chunk_inst;
+    la.chunk_lo = c->chunk_lo;
+    la.chunk_hi = c->chunk_hi;
+    la.A = c->A;
+    la.nrr_prev = c->nrr[c->nrr_cur];
+    la.xs = c->xs;
+    la.rs = c->rs;
+    la.pk = c->pk[c->cur];
+    la.U = c->U_d;
+    la.partial = c->partial;
+    hipLaunchKernelGGL(k_ledger_partial, dim3(static_cast<unsigned>(c->n_chunks)), dim3(256), 0, c->stream, la);
+    HIPCHK(c, hipGetLastError());
+    LedgerFinalArgs lf{};
+    lf.n_inst = c->n_inst;
+    lf.nf = c->nf;
+    lf.f32 = c->f32 ? 1 : 0;
+    lf.nec = c->nec;
+    lf.nsub = c->nsub;
+    lf.n_emit = c->n_emit;
+    lf.inst_chunk0 = c->inst_chunk0;
+    lf.partial = c->partial;
+    lf.E_src = c->E_src;
+    lf.em_inst = c->em_inst;
+    lf.exs = c->exs;
+    lf.ers = c->ers;
+    lf.led = c->led;
+    lf.scale = c->scale;
+    lf.cnt = c->cnt;
+    hipLaunchKernelGGL(k_ledger_final, dim3(grid_for(c->n_inst * c->nf, 64)), dim3(64), 0, c->stream, lf);
+    HIPCHK(c, hipGetLastError());
+    TRY(time_end(c, 2));
+    c->nrr_cur ^= 1;
+    c->step += 1;
+    HIPCHK(c, hipMemcpyAsync(c->h_cnt, c->cnt, sizeof(long long) * kCntN, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->timing) {
+        c->tm[4] += elapsed(c, 0);
+        c->tm[3] += elapsed(c, 1);
+        c->tm[5] += elapsed(c, 2);
+        c->tm[0] += elapsed(c, 3);
+        c->tm[1] += 1;
+        for (long long q = 1; q <= H; ++q) {
+            c->tm[2] += elapsed(c, 2 + 2 * q);
+            c->tm[0] += elapsed(c, 3 + 2 * q);
+            c->tm[1] += 1;
+        }
+    }
+    return RT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rt_last_error(const rt_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, const double* eps_nu, int32_t n_inst,
+                  const int64_t* inst_off, const double* box, const double* pos, const double* n_H, const double* N_H,
+                  const double* x_HI0, const double* T0, void* hip_stream) {
+    if (!out || !p || !sigma_nu || !eps_nu || !inst_off || !box || !pos || !n_H || !N_H || !x_HI0 || !T0)
+        return RT_EINVAL;
+    *out = nullptr;
+    if (p->n_ngb < 1 || p->n_ngb > kMaxNgb || p->n_tc < 3 || !pow2(p->n_rc) || p->n_rc > 32 || p->n_ec < 1 ||
+        p->n_ec > 64 || p->n_freq < 1 || p->n_freq > 15 || p->rr_bin >= p->n_freq || p->rr_bin < -1 ||
+        p->recomb_mode < 0 || p->recomb_mode > 2 || (p->recomb_mode == RT_RR_TRANSPORT && p->rr_bin < 0) ||
+        p->precision < 0 || p->precision > 1 || p->n_em < 1 || p->n_em > 4095 || p->max_hops < 0 ||
+        p->max_hops > 4095 || p->max_vip_depth < 1 || p->max_vip_depth > 15 || !(p->dt > 0.0) ||
+        !(p->floor_rel >= 0.0) || !(p->chem_frac > 0.0) || n_inst < 1)
+        return RT_EINVAL;
+    if (inst_off[0] != 0) return RT_EINVAL;
+    for (int k = 0; k < n_inst; ++k) {
+        if (inst_off[k + 1] - inst_off[k] <= p->n_ngb) return RT_EINVAL;
+        for (int a = 0; a < 3; ++a)
+            if (!(box[6 * k + 3 + a] > box[6 * k + a])) return RT_EINVAL;
+        for (long long i = inst_off[k]; i < inst_off[k + 1]; ++i) {
+            for (int a = 0; a < 3; ++a)
+                if (!(pos[3 * i + a] >= box[6 * k + a] && pos[3 * i + a] <= box[6 * k + 3 + a])) return RT_EINVAL;
+            if (!(n_H[i] > 0.0) || !(N_H[i] > 0.0) || !(x_HI0[i] >= 0.0 && x_HI0[i] <= 1.0) || !(T0[i] > 0.0))
+                return RT_EINVAL;
+        }
+    }
+    const long long N = inst_off[n_inst];
+    if (N >= (1ll << 31) - 1 || N * static_cast<long long>(p->n_ngb) >= (1ll << 31) - 1) return RT_EINVAL;
+    rt_ctx* c = new rt_ctx();
+    c->p = *p;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->N = N;
+    c->n_inst = n_inst;
+    c->nf = p->n_freq;
+    c->nrc = p->n_rc;
+    c->nec = p->n_ec;
+    c->G = p->n_rc * p->n_freq;
+    c->K = p->n_ngb;
+    c->B = N * c->G;
+    c->f32 = p->precision == RT_FP32;
+    c->rr_on = p->recomb_mode == RT_RR_TRANSPORT;
+    const double cc = 1.0 - 2.0 / static_cast<double>(p->n_tc);
+    c->c2 = cc * cc;
+    c->inst_off.assign(inst_off, inst_off + n_inst + 1);
+    c->box.assign(box, box + 6 * n_inst);
+    c->sigma.assign(sigma_nu, sigma_nu + c->nf);
+    c->eps.assign(eps_nu, eps_nu + c->nf);
+    c->nsub = p->n_em;
+    auto bail = [&](rt_status s) {
+        rt_destroy(c);
+        return s;
+    };
+#define ITRY(x)                      \
+    do {                             \
+        rt_status s_ = (x);          \
+        if (s_ != RT_OK) return bail(s_); \
+    } while (0)
+    // per-instance constants: box side, photon unit (mean N_H, for FP32 bins), clock factor
+    std::vector<int> inst_of(N);
+    c->U.assign(n_inst, 1.0);
+    c->L.assign(n_inst, 1.0);
+    std::vector<float> clf(n_inst);
+    std::vector<GridInfo> grid(n_inst);
+    long long ncell = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        const long long n = inst_off[k + 1] - inst_off[k];
+        double sum = 0.0;
+        for (long long i = inst_off[k]; i < inst_off[k + 1]; ++i) {
+            inst_of[i] = k;
+            sum += N_H[i];
+        }
+        double Lmax = 0.0, vol = 1.0;
+        GridInfo& g = grid[k];
+        for (int a = 0; a < 3; ++a) {
+            const double La = box[6 * k + 3 + a] - box[6 * k + a];
+            Lmax = std::max(Lmax, La);
+            vol *= La;
+        }
+        c->U[k] = c->f32 ? sum / static_cast<double>(n) : 1.0;
+        c->L[k] = Lmax;
+        clf[k] = static_cast<float>(Lmax / (kCLight * p->dt));
+        const double cs = std::cbrt(2.0 * vol / static_cast<double>(n));
+        for (int a = 0; a < 3; ++a) {
+            const double La = box[6 * k + 3 + a] - box[6 * k + a];
+            int m = static_cast<int>(La / cs);
+            m = std::max(1, std::min(m, 1024));
+            g.nc[a] = m;
+            g.cs[a] = La / m;
+            g.lo[a] = box[6 * k + a];
+        }
+        g.cell0 = ncell;
+        ncell += static_cast<long long>(g.nc[0]) * g.nc[1] * g.nc[2];
+    }
+    // FP32 positions in units of the instance's box side, relative to its corner
+    std::vector<float4> posf(c->f32 ? N : 1);
+    if (c->f32)
+        for (long long i = 0; i < N; ++i) {
+            const int k = inst_of[i];
+            posf[i] = make_float4(static_cast<float>((pos[3 * i] - box[6 * k]) / c->L[k]),
+                                  static_cast<float>((pos[3 * i + 1] - box[6 * k + 1]) / c->L[k]),
+                                  static_cast<float>((pos[3 * i + 2] - box[6 * k + 2]) / c->L[k]), 0.f);
+        }
+    std::vector<double> floor_d(N);
+    std::vector<float> floor_f(c->f32 ? N : 1);
+    for (long long i = 0; i < N; ++i) {
+        floor_d[i] = p->floor_rel * N_H[i];
+        if (c->f32) floor_f[i] = static_cast<float>(floor_d[i] / c->U[inst_of[i]]);
+    }
+    std::vector<float> sigf(c->nf);
+    for (int nu = 0; nu < c->nf; ++nu) sigf[nu] = static_cast<float>(c->sigma[nu]);
+    std::vector<double> urc, uec;
+    direction_set(c->nrc, urc);
+    direction_set(c->nec, uec);
+
+    ITRY(upload(c, &c->inst_of, inst_of.data(), N));
+    ITRY(upload(c, &c->box_d, box, 6ll * n_inst));
+    ITRY(upload(c, &c->pos, pos, 3 * N));
+    ITRY(upload(c, &c->nH, n_H, N));
+    ITRY(upload(c, &c->NH, N_H, N));
+    ITRY(upload(c, &c->xHI, x_HI0, N));
+    ITRY(upload(c, &c->T, T0, N));
+    ITRY(upload(c, &c->sigma_d, c->sigma.data(), c->nf));
+    ITRY(upload(c, &c->sigmaf_d, sigf.data(), c->nf));
+    ITRY(upload(c, &c->eps_d, c->eps.data(), c->nf));
+    ITRY(upload(c, &c->U_d, c->U.data(), n_inst));
+    ITRY(upload(c, &c->L_d, c->L.data(), n_inst));
+    ITRY(upload(c, &c->clf_d, clf.data(), n_inst));
+    ITRY(upload(c, &c->u_rc, urc.data(), 3ll * c->nrc));
+    ITRY(upload(c, &c->u_ec, uec.data(), 3ll * c->nec));
+    ITRY(upload(c, &c->grid_d, grid.data(), n_inst));
+    if (c->f32) {
+        ITRY(upload(c, &c->posf, posf.data(), N));
+        float* fb = nullptr;
+        ITRY(upload(c, &fb, floor_f.data(), N));
+        c->floor_b = fb;
+        ITRY(alloc_n(c, &c->kappa, N));
+    } else {
+        double* fb = nullptr;
+        ITRY(upload(c, &fb, floor_d.data(), N));
+        c->floor_b = fb;
+    }
+    ITRY(alloc_n(c, &c->h, N));
+    ITRY(alloc_n(c, &c->ngb, N * c->K));
+    ITRY(alloc_n(c, &c->rot, 9 + 3ll * c->nrc));
+    ITRY(alloc_n(c, &c->wrcf, 3ll * c->nrc));
+    // neighbour search: counting sort into cells, then exact kNN per particle
+    int *cell_of = nullptr, *cnt = nullptr, *cursor = nullptr;
+    ITRY(alloc_n(c, &cell_of, N));
+    ITRY(alloc_n(c, &cnt, ncell));
+    ITRY(alloc_n(c, &cursor, std::max<long long>(ncell, N)));
+    ITRY(alloc_n(c, &c->cell_start, ncell + 1));
+    ITRY(alloc_n(c, &c->cell_idx, N));
+    ITRY(fill_i32(c, cnt, ncell, 0));
+    ITRY(fill_i32(c, cursor, std::max<long long>(ncell, N), 0));
+    hipLaunchKernelGGL(k_cell_count, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, c->pos, c->inst_of, c->grid_d,
+                       cell_of, cnt);
+    hipLaunchKernelGGL(k_scan_i32, dim3(1), dim3(1024), 0, c->stream, cnt, ncell, c->cell_start);
+    hipLaunchKernelGGL(k_cell_fill, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, cell_of, c->cell_start, cursor,
+                       c->cell_idx);
+    hipLaunchKernelGGL(k_knn, dim3(grid_for(N, 128)), dim3(128), 0, c->stream, N, c->pos, c->inst_of, 1, c->grid_d,
+                       c->cell_start, c->cell_idx, c->pos, c->K, c->ngb, c->h);
+    // reverse lists, sorted by sender
+    ITRY(alloc_n(c, &c->rev_off, N + 1));
+    ITRY(alloc_n(c, &c->rev_src, N * c->K));
+    ITRY(alloc_n(c, &c->rev_pos, N * c->K));
+    int* rcnt = nullptr;
+    ITRY(alloc_n(c, &rcnt, N));
+    ITRY(fill_i32(c, rcnt, N, 0));
+    ITRY(fill_i32(c, cursor, N, 0));
+    hipLaunchKernelGGL(k_rev_count, dim3(grid_for(N * c->K, 256)), dim3(256), 0, c->stream, N * c->K, c->ngb, rcnt);
+    hipLaunchKernelGGL(k_scan_i32, dim3(1), dim3(1024), 0, c->stream, rcnt, N, c->rev_off);
+    hipLaunchKernelGGL(k_rev_fill, dim3(grid_for(N * c->K, 256)), dim3(256), 0, c->stream, N, c->K, c->ngb, c->rev_off,
+                       cursor, c->rev_src, c->rev_pos);
+    hipLaunchKernelGGL(k_rev_sort, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, c->rev_off, c->rev_src,
+                       c->rev_pos);
+    HIPCHK(c, hipGetLastError());
+    // bins and work buffers
+    const size_t rsz = c->f32 ? sizeof(float) : sizeof(double);
+    for (int b = 0; b < 2; ++b) {
+        ITRY(dalloc(c, &c->pk[b], 4 * rsz * c->B));
+        ITRY(dalloc(c, &c->pc[b], rsz * c->B));
+        ITRY(alloc_n(c, &c->cm[b], c->B));
+        ITRY(alloc_n(c, &c->sm[b], c->B));
+        HIPCHK(c, hipMemsetAsync(c->pk[b], 0, 4 * rsz * c->B, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->pc[b], 0, rsz * c->B, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->cm[b], 0, 8 * c->B, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->sm[b], 0, 4 * c->B, c->stream));
+        ITRY(alloc_n(c, &c->nrr[b], N));
+        ITRY(fill_f64(c, c->nrr[b], N, 0.0));
+        ITRY(alloc_n(c, &c->head[b], N));
+    }
+    ITRY(alloc_n(c, &c->A, N * c->nf));
+    ITRY(alloc_n(c, &c->P, N * c->nf));
+    ITRY(fill_f64(c, c->A, N * c->nf, 0.0));
+    ITRY(fill_f64(c, c->P, N * c->nf, 0.0));
+    ITRY(alloc_n(c, &c->xs, c->B));
+    ITRY(alloc_n(c, &c->rs, c->B));
+    ITRY(fill_f64(c, c->xs, c->B, 0.0));
+    ITRY(fill_f64(c, c->rs, c->B, 0.0));
+    c->vip_cap = p->vip_capacity > 0 ? p->vip_capacity : std::max<long long>(1 << 16, c->B / 8);
+    c->rec_cap = p->record_capacity > 0 ? p->record_capacity : std::max<long long>(1 << 20, c->vip_cap * 4);
+    if (c->rec_cap >= (1ll << 31)) c->rec_cap = (1ll << 31) - 1;
+    for (int b = 0; b < 2; ++b) ITRY(alloc_n(c, &c->vip[b], c->vip_cap));
+    ITRY(alloc_n(c, &c->rec, c->rec_cap));
+    ITRY(alloc_n(c, &c->rec_next, c->rec_cap));
+    ITRY(alloc_n(c, &c->cnt, kCntN));
+    HIPCHK(c, hipMemsetAsync(c->cnt, 0, sizeof(long long) * kCntN, c->stream));
+    HIPCHK(c, hipHostMalloc(reinterpret_cast<void**>(&c->h_cnt), sizeof(long long) * kCntN, hipHostMallocDefault));
+    ITRY(alloc_n(c, &c->led, 5ll * n_inst * c->nf));
+    ITRY(fill_f64(c, c->led, 5ll * n_inst * c->nf, 0.0));
+    ITRY(alloc_n(c, &c->scale, 1ll * n_inst * c->nf));
+    ITRY(fill_f64(c, c->scale, 1ll * n_inst * c->nf, 1.0));
+    // ledger chunks: fixed ranges of particles inside one instance
+    std::vector<int> ci;
+    std::vector<long long> clo, chi, c0(n_inst + 1, 0);
+    for (int k = 0; k < n_inst; ++k) {
+        c0[k] = static_cast<long long>(ci.size());
+        for (long long a = inst_off[k]; a < inst_off[k + 1]; a += kChunk) {
+            ci.push_back(k);
+            clo.push_back(a);
+            chi.push_back(std::min<long long>(a + kChunk, inst_off[k + 1]));
+        }
+    }
+    c0[n_inst] = static_cast<long long>(ci.size());
+    c->n_chunks = static_cast<long long>(ci.size());
+    ITRY(upload(c, &c->chunk_inst, ci.data(), c->n_chunks));
+    ITRY(upload(c, &c->chunk_lo, clo.data(), c->n_chunks));
+    ITRY(upload(c, &c->chunk_hi, chi.data(), c->n_chunks));
+    ITRY(upload(c, &c->inst_chunk0, c0.data(), n_inst + 1));
+    ITRY(alloc_n(c, &c->partial, c->n_chunks * c->nf * 5));
+    if (c->f32) {
+        hipLaunchKernelGGL(k_kappa_init, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, c->xHI, c->nH, c->L_d,
+                           c->inst_of, c->kappa);
+        HIPCHK(c, hipGetLastError());
+    }
+    // no sources yet
+    c->n_emit = 0;
+    ITRY(alloc_n(c, &c->E_src, 1ll * n_inst * c->nf));
+    ITRY(fill_f64(c, c->E_src, 1ll * n_inst * c->nf, 0.0));
+    ITRY(alloc_n(c, &c->em_inst, 1));
+    ITRY(alloc_n(c, &c->em_kind, 1));
+    ITRY(alloc_n(c, &c->ecd, 3));
+    ITRY(alloc_n(c, &c->exs, 1));
+    ITRY(alloc_n(c, &c->ers, 1));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+#undef ITRY
+    *out = c;
+    return RT_OK;
+}
+
+rt_status rt_add_sources(rt_ctx* c, int32_t n_src, const int32_t* inst, const int32_t* kind, const double* pos,
+                         const double* rate, const int32_t* n_side) {
+    if (!c) return RT_EINVAL;
+    if (c->sticky) return RT_EDEVICE;
+    if (n_src < 0 || (n_src > 0 && (!inst || !kind || !pos || !rate))) return fail(c, RT_EINVAL, "null source arrays");
+    long long total = 0;
+    for (int s = 0; s < n_src; ++s) {
+        if (inst[s] < 0 || inst[s] >= c->n_inst) return fail(c, RT_EINVAL, "source instance out of range");
+        if (kind[s] == RT_SRC_POINT) {
+            const double* bx = &c->box[6 * inst[s]];
+            for (int a = 0; a < 3; ++a)
+                if (!(pos[3 * s + a] >= bx[a] && pos[3 * s + a] <= bx[3 + a]))
+                    return fail(c, RT_EINVAL, "point source outside its box");
+            total += 1;
+        } else if (kind[s] == RT_SRC_PLANE_XLO) {
+            if (!n_side || n_side[s] < 1 || n_side[s] > 4096) return fail(c, RT_EINVAL, "bad plane n_side");
+            total += static_cast<long long>(n_side[s]) * n_side[s];
+        } else {
+            return fail(c, RT_EINVAL, "bad source kind");
+        }
+        for (int nu = 0; nu < c->nf; ++nu)
+            if (!(rate[s * c->nf + nu] >= 0.0) || !std::isfinite(rate[s * c->nf + nu]))
+                return fail(c, RT_EINVAL, "bad source rate");
+    }
+    if (total >= (1ll << 24)) return fail(c, RT_EINVAL, "too many emitters");
+    std::vector<int> ek(total), ei(total);
+    std::vector<double> ep(3 * total), epk(total * c->nf);
+    std::vector<double> esrc(static_cast<size_t>(c->n_inst) * c->nf, 0.0);
+    long long m = 0;
+    const double dt = c->p.dt;
+    for (int s = 0; s < n_src; ++s) {
+        const int k = inst[s];
+        const double* bx = &c->box[6 * k];
+        if (kind[s] == RT_SRC_POINT) {
+            ek[m] = 0;
+            ei[m] = k;
+            for (int a = 0; a < 3; ++a) ep[3 * m + a] = pos[3 * s + a];
+            for (int nu = 0; nu < c->nf; ++nu) {
+                const double pk = rate[s * c->nf + nu] * dt / static_cast<double>(c->p.n_em * c->p.n_ec);
+                epk[m * c->nf + nu] = pk;
+                if (pk > 0.0) esrc[k * c->nf + nu] += pk * c->p.n_em * c->p.n_ec;
+            }
+            ++m;
+        } else {
+            const int n = n_side[s];
+            const double dy = (bx[4] - bx[1]) / n, dz = (bx[5] - bx[2]) / n;
+            for (int a = 0; a < n; ++a)
+                for (int b = 0; b < n; ++b) {
+                    ek[m] = 1;
+                    ei[m] = k;
+                    ep[3 * m] = bx[0];
+                    ep[3 * m + 1] = bx[1] + (static_cast<double>(a) + 0.5) * dy;
+                    ep[3 * m + 2] = bx[2] + (static_cast<double>(b) + 0.5) * dz;
+                    for (int nu = 0; nu < c->nf; ++nu) {
+                        const double pk = rate[s * c->nf + nu] * dt * (dy * dz);
+                        epk[m * c->nf + nu] = pk;
+                        if (pk > 0.0) esrc[k * c->nf + nu] += pk;
+                    }
+                    ++m;
+                }
+        }
+    }
+    c->n_emit = total;
+    c->h_em_inst = ei;
+    TRY(upload(c, &c->em_kind, ek.data(), total));
+    TRY(upload(c, &c->em_inst, ei.data(), total));
+    TRY(upload(c, &c->em_pos, ep.data(), 3 * total));
+    TRY(upload(c, &c->em_pk, epk.data(), total * c->nf));
+    TRY(upload(c, &c->E_src, esrc.data(), static_cast<long long>(c->n_inst) * c->nf));
+    TRY(alloc_n(c, &c->em_ngb, std::max<long long>(1, total) * c->K));
+    TRY(alloc_n(c, &c->em_h, std::max<long long>(1, total)));
+    const long long necd = std::max<long long>(1, total * c->nsub * c->nec);
+    TRY(alloc_n(c, &c->ecd, 3 * necd));
+    TRY(alloc_n(c, &c->exs, necd * c->nf));
+    TRY(alloc_n(c, &c->ers, necd * c->nf));
+    TRY(fill_f64(c, c->exs, necd * c->nf, 0.0));
+    TRY(fill_f64(c, c->ers, necd * c->nf, 0.0));
+    TRY(fill_f64(c, c->ecd, 3 * necd, 0.0));
+    if (total > 0) {
+        hipLaunchKernelGGL(k_knn, dim3(grid_for(total, 128)), dim3(128), 0, c->stream, total, c->em_pos, c->em_inst, 0,
+                           c->grid_d, c->cell_start, c->cell_idx, c->pos, c->K, c->em_ngb, c->em_h);
+        HIPCHK(c, hipGetLastError());
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return RT_OK;
+}
+
+rt_status rt_step(rt_ctx* c, int32_t n_steps) {
+    if (!c) return RT_EINVAL;
+    if (c->sticky) return RT_EDEVICE;
+    if (n_steps < 0) return fail(c, RT_EINVAL, "n_steps < 0");
+    for (int k = 0; k < 8; ++k) c->tm[k] = 0.0;
+    bool hopcap = false;
+    for (int s = 0; s < n_steps; ++s) {
+        TRY(one_step(c, &hopcap));
+        const long long flags = c->h_cnt[kCntFlags];
+        if (flags & (kFlagVipOverflow | kFlagRecOverflow)) return fail(c, RT_EOVERFLOW, "work buffer overflow");
+        if (flags & kFlagNonFinite) return fail(c, RT_ENONFINITE, "non-finite ledger");
+    }
+    if (hopcap) return fail(c, RT_EHOPCAP, "a step reached max_hops");
+    return RT_OK;
+}
+
+rt_status rt_get_state(rt_ctx* c, double* x_HI, double* T, double* absorbed, double* passing, double* ledger,
+                       int64_t* counters) {
+    if (!c) return RT_EINVAL;
+    if (c->sticky) return RT_EDEVICE;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (x_HI) HIPCHK(c, hipMemcpy(x_HI, c->xHI, sizeof(double) * c->N, hipMemcpyDeviceToHost));
+    if (T) HIPCHK(c, hipMemcpy(T, c->T, sizeof(double) * c->N, hipMemcpyDeviceToHost));
+    if (absorbed) HIPCHK(c, hipMemcpy(absorbed, c->A, sizeof(double) * c->N * c->nf, hipMemcpyDeviceToHost));
+    if (passing) HIPCHK(c, hipMemcpy(passing, c->P, sizeof(double) * c->N * c->nf, hipMemcpyDeviceToHost));
+    if (ledger) HIPCHK(c, hipMemcpy(ledger, c->led, sizeof(double) * 5 * c->n_inst * c->nf, hipMemcpyDeviceToHost));
+    if (counters) {
+        long long h[kCntN];
+        HIPCHK(c, hipMemcpy(h, c->cnt, sizeof(h), hipMemcpyDeviceToHost));
+        counters[0] = h[kCntSteps];
+        counters[1] = h[kCntHops];
+        counters[2] = h[kCntVips];
+        counters[3] = h[kCntUpdates];
+    }
+    return RT_OK;
+}
+
+rt_status rt_get_bins(rt_ctx* c, double* N, double* dir, double* clock) {
+    if (!c) return RT_EINVAL;
+    if (c->sticky) return RT_EDEVICE;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const long long B = c->B;
+    std::vector<double> U(c->n_inst);
+    std::vector<int> inst_of(c->N);
+    HIPCHK(c, hipMemcpy(inst_of.data(), c->inst_of, sizeof(int) * c->N, hipMemcpyDeviceToHost));
+    if (c->f32) {
+        std::vector<Bin4<float>> pk(B);
+        std::vector<float> pc(B);
+        HIPCHK(c, hipMemcpy(pk.data(), c->pk[c->cur], sizeof(Bin4<float>) * B, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(pc.data(), c->pc[c->cur], sizeof(float) * B, hipMemcpyDeviceToHost));
+        for (long long b = 0; b < B; ++b) {
+            const int k = inst_of[b / c->G];
+            if (N) N[b] = static_cast<double>(pk[b].n) * c->U[k];
+            if (dir) {
+                dir[3 * b] = pk[b].x;
+                dir[3 * b + 1] = pk[b].y;
+                dir[3 * b + 2] = pk[b].z;
+            }
+            if (clock) clock[b] = static_cast<double>(pc[b]) * c->p.dt;
+        }
+    } else {
+        std::vector<Bin4<double>> pk(B);
+        std::vector<double> pc(B);
+        HIPCHK(c, hipMemcpy(pk.data(), c->pk[c->cur], sizeof(Bin4<double>) * B, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(pc.data(), c->pc[c->cur], sizeof(double) * B, hipMemcpyDeviceToHost));
+        for (long long b = 0; b < B; ++b) {
+            if (N) N[b] = pk[b].n;
+            if (dir) {
+                dir[3 * b] = pk[b].x;
+                dir[3 * b + 1] = pk[b].y;
+                dir[3 * b + 2] = pk[b].z;
+            }
+            if (clock) clock[b] = pc[b];
+        }
+    }
+    return RT_OK;
+}
+
+rt_status rt_get_neighbours(rt_ctx* c, int32_t* ngb, double* h) {
+    if (!c) return RT_EINVAL;
+    if (c->sticky) return RT_EDEVICE;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (ngb) HIPCHK(c, hipMemcpy(ngb, c->ngb, sizeof(int) * c->N * c->K, hipMemcpyDeviceToHost));
+    if (h) HIPCHK(c, hipMemcpy(h, c->h, sizeof(double) * c->N, hipMemcpyDeviceToHost));
+    return RT_OK;
+}
+
+int64_t rt_n_emitters(const rt_ctx* c) { return c ? c->n_emit : 0; }
+
+rt_status rt_get_emitter_neighbours(rt_ctx* c, int32_t* ngb, double* h) {
+    if (!c) return RT_EINVAL;
+    if (c->sticky) return RT_EDEVICE;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->n_emit == 0) return RT_OK;
+    if (ngb) HIPCHK(c, hipMemcpy(ngb, c->em_ngb, sizeof(int) * c->n_emit * c->K, hipMemcpyDeviceToHost));
+    if (h) HIPCHK(c, hipMemcpy(h, c->em_h, sizeof(double) * c->n_emit, hipMemcpyDeviceToHost));
+    return RT_OK;
+}
+
+rt_status rt_get_cone_masks(rt_ctx* c, uint64_t* mask) {
+    if (!c || !mask) return RT_EINVAL;
+    if (c->sticky) return RT_EDEVICE;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(mask, c->cm[c->cur], sizeof(uint64_t) * c->B, hipMemcpyDeviceToHost));
+    return RT_OK;
+}
+
+rt_status rt_get_pending_rr(rt_ctx* c, double* nrr) {
+    if (!c || !nrr) return RT_EINVAL;
+    if (c->sticky) return RT_EDEVICE;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(nrr, c->nrr[c->nrr_cur], sizeof(double) * c->N, hipMemcpyDeviceToHost));
+    return RT_OK;
+}
+
+rt_status rt_set_timing(rt_ctx* c, int32_t on) {
+    if (!c) return RT_EINVAL;
+    c->timing = on != 0;
+    return RT_OK;
+}
+
+rt_status rt_get_timing(rt_ctx* c, double* out, int32_t n) {
+    if (!c || !out || n < 0) return RT_EINVAL;
+    const double rsz = c->f32 ? 4.0 : 8.0;
+    // algorithmic bytes of one forward-step launch: every slot's packet, clock,
+    // cone mask and sender mask read once and written once; per particle its
+    // neighbour list, incoming edge list (4 + 1 bytes per edge), position,
+    // absorbed and passing photons (read + write).
+    const double per_slot = 2.0 * (4.0 * rsz + rsz + 8.0 + 4.0);
+    const double per_part = 4.0 * c->K + 5.0 * c->K + (c->f32 ? 16.0 : 24.0) + 2.0 * 2.0 * 8.0 * c->nf;
+    const double bytes = per_slot * static_cast<double>(c->B) + per_part * static_cast<double>(c->N);
+    double v[8] = {c->tm[0], c->tm[1], c->tm[2], c->tm[3], c->tm[4], c->tm[5], bytes, 0.0};
+    for (int k = 0; k < n && k < 8; ++k) out[k] = v[k];
+    return RT_OK;
+}
+
+namespace {
+struct BlobHeader {
+    long long magic, N, B, nf, n_inst, f32, step, cur, nrr_cur;
+};
+}  // namespace
+
+rt_status rt_get_state_blob(rt_ctx* c, void* blob, size_t* bytes) {
+    if (!c || !bytes) return RT_EINVAL;
+    if (c->sticky) return RT_EDEVICE;
+    const size_t rsz = c->f32 ? 4 : 8;
+    const size_t need = sizeof(BlobHeader) + 5 * rsz * c->B + 3 * 8 * c->N + 8 * 5 * c->n_inst * c->nf +
+                        8 * c->n_inst * c->nf + 8 * kCntN;
+    if (!blob) {
+        *bytes = need;
+        return RT_OK;
+    }
+    if (*bytes < need) return fail(c, RT_ESTATE, "blob too small");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    char* q = static_cast<char*>(blob);
+    BlobHeader hd{0x54524150ll, c->N, c->B, c->nf, c->n_inst, c->f32, c->step, 0, 0};
+    std::memcpy(q, &hd, sizeof hd);
+    q += sizeof hd;
+    HIPCHK(c, hipMemcpy(q, c->pk[c->cur], 4 * rsz * c->B, hipMemcpyDeviceToHost));
+    q += 4 * rsz * c->B;
+    HIPCHK(c, hipMemcpy(q, c->pc[c->cur], rsz * c->B, hipMemcpyDeviceToHost));
+    q += rsz * c->B;
+    HIPCHK(c, hipMemcpy(q, c->xHI, 8 * c->N, hipMemcpyDeviceToHost));
+    q += 8 * c->N;
+    HIPCHK(c, hipMemcpy(q, c->T, 8 * c->N, hipMemcpyDeviceToHost));
+    q += 8 * c->N;
+    HIPCHK(c, hipMemcpy(q, c->nrr[c->nrr_cur], 8 * c->N, hipMemcpyDeviceToHost));
+    q += 8 * c->N;
+    HIPCHK(c, hipMemcpy(q, c->led, 8 * 5 * c->n_inst * c->nf, hipMemcpyDeviceToHost));
+    q += 8 * 5 * c->n_inst * c->nf;
+    HIPCHK(c, hipMemcpy(q, c->scale, 8 * c->n_inst * c->nf, hipMemcpyDeviceToHost));
+    q += 8 * c->n_inst * c->nf;
+    HIPCHK(c, hipMemcpy(q, c->cnt, 8 * kCntN, hipMemcpyDeviceToHost));
+    *bytes = need;
+    return RT_OK;
+}
+
+rt_status rt_set_state_blob(rt_ctx* c, const void* blob, size_t bytes) {
+    if (!c || !blob) return RT_EINVAL;
+    if (c->sticky) return RT_EDEVICE;
+    size_t need = 0;
+    TRY(rt_get_state_blob(c, nullptr, &need));
+    if (bytes != need) return fail(c, RT_ESTATE, "blob size mismatch");
+    BlobHeader hd;
+    std::memcpy(&hd, blob, sizeof hd);
+    if (hd.magic != 0x54524150ll || hd.N != c->N || hd.B != c->B || hd.nf != c->nf || hd.n_inst != c->n_inst ||
+        hd.f32 != (c->f32 ? 1 : 0))
+        return fail(c, RT_ESTATE, "blob from a different context");
+    const size_t rsz = c->f32 ? 4 : 8;
+    const char* q = static_cast<const char*>(blob) + sizeof hd;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->cur = 0;
+    c->nrr_cur = 0;
+    HIPCHK(c, hipMemcpy(c->pk[0], q, 4 * rsz * c->B, hipMemcpyHostToDevice));
+    q += 4 * rsz * c->B;
+    HIPCHK(c, hipMemcpy(c->pc[0], q, rsz * c->B, hipMemcpyHostToDevice));
+    q += rsz * c->B;
+    HIPCHK(c, hipMemcpy(c->xHI, q, 8 * c->N, hipMemcpyHostToDevice));
+    q += 8 * c->N;
+    HIPCHK(c, hipMemcpy(c->T, q, 8 * c->N, hipMemcpyHostToDevice));
+    q += 8 * c->N;
+    HIPCHK(c, hipMemcpy(c->nrr[0], q, 8 * c->N, hipMemcpyHostToDevice));
+    q += 8 * c->N;
+    HIPCHK(c, hipMemcpy(c->led, q, 8 * 5 * c->n_inst * c->nf, hipMemcpyHostToDevice));
+    q += 8 * 5 * c->n_inst * c->nf;
+    HIPCHK(c, hipMemcpy(c->scale, q, 8 * c->n_inst * c->nf, hipMemcpyHostToDevice));
+    q += 8 * c->n_inst * c->nf;
+    HIPCHK(c, hipMemcpy(c->cnt, q, 8 * kCntN, hipMemcpyHostToDevice));
+    c->step = hd.step;
+    if (c->f32) {
+        hipLaunchKernelGGL(k_kappa_init, dim3(grid_for(c->N, 256)), dim3(256), 0, c->stream, c->N, c->xHI, c->nH,
+                           c->L_d, c->inst_of, c->kappa);
+        HIPCHK(c, hipGetLastError());
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return RT_OK;
+}
+
+void rt_destroy(rt_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& b : c->owned) {
+        if (c->p.dealloc)
+            c->p.dealloc(c->p.alloc_user, b.p);
+        else if (!c->p.alloc)
+            (void)hipFree(b.p);
+    }
+    for (auto e : c->ev) (void)hipEventDestroy(e);
+    if (c->h_cnt) (void)hipHostFree(c->h_cnt);
+    delete c;
+}
+
+}  // extern "C"

@@ -54,7 +54,7 @@ def default_params(**kw):
         freeze_chem=0,     # 1: skip the chemistry update (transport-only runs)
         precision=FP64,
         n_em=10,           # emission sub-steps per RT step (dt / dt_em)
-        max_hops=4096,
+        max_hops=4000,
         max_vip_depth=4,
         dt=0.1 * MYR_S,
         floor_rel=1e-20,   # packets below floor_rel * N_H of their particle are absorbed there

@@ -1,0 +1,209 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bars: integers (neighbour lists, cone masks, counters) bit-exact; FP64 x_HI and
+T within 1e-6 relative; FP32 transport max |dx_HI| <= 1e-3 absolute; photon
+ledger residual <= 1e-12 (FP64) and <= 1e-6 (FP32) of the emitted photons.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1311_0182_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _rt():
+    from paper_1311_0182_amd import traphic_rt as RT
+    return RT
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_oracle(cfg, steps):
+    s = O.OracleSim(cfg)
+    rc = s.step(steps)
+    return s, rc
+
+
+def run_gpu(cfg, steps, precision="fp64", **kw):
+    RT = _rt()
+    ctx = RT.Context(cfg, precision=precision, **kw)
+    ctx.step(steps)
+    return ctx
+
+
+def residual(led):
+    E, A, X, R, F = np.moveaxis(led, -1, 0)
+    return np.abs(E - A - X - R - F) / np.maximum(E, 1e-300)
+
+
+def rel(a, b):
+    return np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300))
+
+
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["stromgren11", "batched4"])
+def test_neighbour_lists_bit_exact(name):
+    cfg = I.stromgren(11, rr=False, n_ngb=32) if name == "stromgren11" else \
+        I.batched(n_inst=4, side_lo=6, side_hi=10, n_ngb=48)
+    say("case", name, "N", cfg["pos"].shape[0])
+    s = O.OracleSim(cfg)
+    ctx = _rt().Context(cfg, precision="fp64")
+    nb_o, h_o = s.ngb()
+    nb_g, h_g = ctx.neighbours()
+    assert np.array_equal(nb_o, nb_g)
+    assert np.array_equal(h_o, h_g)
+    enb_o, eh_o = s.emitter_ngb()
+    enb_g, eh_g = ctx.emitter_neighbours()
+    assert np.array_equal(enb_o, enb_g)
+    assert np.array_equal(eh_o, eh_g)
+
+
+@pytest.mark.parametrize("max_hops", [0, 1, 3])
+def test_cone_edges_bit_exact_first_hops(max_hops):
+    cfg = I.stromgren(12, rr=True, n_ngb=32, max_hops=max_hops)
+    # start partly ionized so that the RR bin is populated from the first step
+    cfg["xHI"] = np.full(cfg["pos"].shape[0], 0.3)
+    say("max_hops", max_hops)
+    s = O.OracleSim(cfg)
+    assert s.step(2) == 4
+    ctx = _rt().Context(cfg, precision="fp64")
+    assert ctx.step(2) == _rt().RT_EHOPCAP
+    mo = s.cone_masks()
+    mg = ctx.cone_masks()
+    Nb_o, d_o, c_o = s.bins()
+    Nb_g, d_g, c_g = ctx.bins()
+    active = (Nb_o > 0) & (c_o < cfg["params"]["dt"])
+    assert active.sum() > 100
+    assert np.array_equal(mo, mg)
+    assert np.array_equal(Nb_o > 0, Nb_g > 0)
+    assert rel(Nb_g[Nb_o > 0], Nb_o[Nb_o > 0]) < 1e-12
+    assert np.max(np.abs(d_g - d_o)) < 1e-12
+    assert np.max(np.abs(c_g - c_o)) < 1e-12 * cfg["params"]["dt"]
+    so, sg = s.state(), ctx.state()
+    assert np.array_equal(so["counters"], sg["counters"])
+
+
+def _compare_fp64(cfg, steps, xtol=1e-6):
+    s, rc_o = run_oracle(cfg, steps)
+    ctx = run_gpu(cfg, steps, "fp64")
+    so, sg = s.state(), ctx.state()
+    say("counters oracle", so["counters"], "gpu", sg["counters"])
+    assert np.array_equal(so["counters"], sg["counters"])
+    assert rel(sg["xHI"], so["xHI"]) < xtol
+    assert rel(sg["T"], so["T"]) < xtol
+    assert np.max(residual(sg["ledger"])) < 1e-12
+    Eo, Eg = so["ledger"][..., 0], sg["ledger"][..., 0]
+    assert rel(Eg, Eo) < 1e-12
+    assert rel(sg["ledger"][..., 1], so["ledger"][..., 1]) < 1e-9
+    return s, ctx
+
+
+def test_fp64_parity_stromgren_case_b_full_run():
+    cfg = I.config(1)   # 16^3, case B, 100 steps of 0.1 Myr
+    say("config 1, 100 steps")
+    _compare_fp64(cfg, 100)
+
+
+def test_fp64_parity_rr_ragged():
+    cfg = I.stromgren(11, rr=True, n_ngb=32, dt_myr=0.5)
+    say("11^3 with RR, 20 steps")
+    _compare_fp64(cfg, 20)
+
+
+def test_fp64_parity_batched():
+    cfg = I.batched(n_inst=6, side_lo=6, side_hi=12, n_ngb=32, n_steps=10)
+    say("batched 6 instances, 10 steps")
+    _compare_fp64(cfg, 10)
+
+
+def test_fp64_parity_plane_front_chain():
+    cfg = I.chain(n=16, x_hi=0.3)
+    s, rc = run_oracle(cfg, 2)
+    ctx = run_gpu(cfg, 2)
+    so, sg = s.state(), ctx.state()
+    assert np.array_equal(so["counters"], sg["counters"])
+    assert rel(sg["A"], so["A"]) < 1e-12
+    assert rel(sg["P"], so["P"]) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["rr11", "batched6"])
+def test_fp32_transport_within_bound(name):
+    if name == "rr11":
+        cfg, steps = I.stromgren(11, rr=True, n_ngb=32, dt_myr=0.5), 20
+    else:
+        cfg, steps = I.batched(n_inst=6, side_lo=6, side_hi=12, n_ngb=32), 10
+    say("fp32", name)
+    s, _ = run_oracle(cfg, steps)
+    ctx = run_gpu(cfg, steps, "fp32")
+    so, sg = s.state(), ctx.state()
+    dx = np.max(np.abs(sg["xHI"] - so["xHI"]))
+    say("max |dx_HI|", dx, "residual", np.max(residual(sg["ledger"])))
+    assert dx <= 1e-3
+    assert np.max(residual(sg["ledger"])) <= 1e-6
+
+
+def test_determinism_bitwise():
+    cfg = I.stromgren(10, rr=True, n_ngb=32, dt_myr=0.5)
+    for prec in ("fp64", "fp32"):
+        a = run_gpu(cfg, 6, prec)
+        b = run_gpu(cfg, 6, prec)
+        sa, sb = a.state(), b.state()
+        for k in ("xHI", "T", "A", "P", "ledger"):
+            assert np.array_equal(sa[k], sb[k]), (prec, k)
+        assert a.get_blob() == b.get_blob()
+
+
+def test_checkpoint_restore_bitwise():
+    cfg = I.stromgren(10, rr=True, n_ngb=32, dt_myr=0.5)
+    for prec in ("fp64", "fp32"):
+        ref = run_gpu(cfg, 6, prec)
+        a = run_gpu(cfg, 3, prec)
+        blob = a.get_blob()
+        b = _rt().Context(cfg, precision=prec)
+        b.set_blob(blob)
+        b.step(3)
+        assert ref.get_blob() == b.get_blob(), prec
+
+
+def test_errors_and_hop_cap():
+    RT = _rt()
+    cfg = I.stromgren(8, rr=False, n_ngb=16)
+    with pytest.raises(RT.RTError) as e:
+        RT.Context(cfg, n_ngb=65)
+    assert e.value.status == RT.RT_EINVAL
+    with pytest.raises(RT.RTError) as e:
+        RT.Context(cfg, n_rc=6)
+    assert e.value.status == RT.RT_EINVAL
+    bad = dict(cfg)
+    bad["pos"] = cfg["pos"].copy()
+    bad["pos"][0, 0] = -1.0
+    with pytest.raises(RT.RTError):
+        RT.Context(bad)
+    ctx = RT.Context(cfg, max_hops=1)
+    assert ctx.step(1) == RT.RT_EHOPCAP
+    led = ctx.state()["ledger"]
+    assert np.max(residual(led)) < 1e-12
+    assert led[0, 0, 4] > 0            # packets left in flight
+
+
+def test_full_size_first_steps_fp64():
+    """64^3 particles, N_ngb = 48, RR on: the first steps (sparse) against the oracle."""
+    cfg = I.config(2)
+    say("config 2 full size, 3 steps")
+    s, _ = run_oracle(cfg, 3)
+    ctx = run_gpu(cfg, 3, "fp64")
+    nb_o, _ = s.ngb()
+    nb_g, _ = ctx.neighbours()
+    assert np.array_equal(nb_o, nb_g)
+    so, sg = s.state(), ctx.state()
+    assert np.array_equal(so["counters"], sg["counters"])
+    assert rel(sg["xHI"], so["xHI"]) < 1e-6
+    assert np.max(residual(sg["ledger"])) < 1e-12
