@@ -996,12 +996,13 @@ rt_status rt_set_timing(rt_ctx* c, int32_t on) {
 rt_status rt_get_timing(rt_ctx* c, double* out, int32_t n) {
     if (!c || !out || n < 0) return RT_EINVAL;
     const double rsz = c->f32 ? 4.0 : 8.0;
-    // algorithmic bytes of one forward-step launch: every slot's packet, clock,
-    // cone mask and sender mask read once and written once; per particle its
-    // neighbour list, incoming edge list (4 + 1 bytes per edge), position,
-    // absorbed and passing photons (read + write).
-    const double per_slot = 2.0 * (4.0 * rsz + rsz + 8.0 + 4.0);
-    const double per_part = 4.0 * c->K + 5.0 * c->K + (c->f32 ? 16.0 : 24.0) + 2.0 * 2.0 * 8.0 * c->nf;
+    // algorithmic bytes of one forward-step launch, counting only what every
+    // launch moves whatever the activity: each slot's packet and clock read,
+    // its sender mask read once, and packet, clock, cone mask and sender mask
+    // written; per particle its incoming edge list (4 + 1 bytes per edge), its
+    // position and its absorbed and passing photons (read + write).
+    const double per_slot = (4.0 * rsz + rsz) + 4.0 + (4.0 * rsz + rsz + 8.0 + 4.0);
+    const double per_part = 5.0 * c->K + (c->f32 ? 16.0 : 24.0) + 2.0 * 2.0 * 8.0 * c->nf;
     const double bytes = per_slot * static_cast<double>(c->B) + per_part * static_cast<double>(c->N);
     double v[8] = {c->tm[0], c->tm[1], c->tm[2], c->tm[3], c->tm[4], c->tm[5], bytes, 0.0};
     for (int k = 0; k < n && k < 8; ++k) out[k] = v[k];
