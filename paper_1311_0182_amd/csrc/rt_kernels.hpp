@@ -580,6 +580,7 @@ struct HopArgs {
     R dtc;                   // clock limit in clock units
     const float* clf;        // FP32: L_inst / (c dt) per instance
     const double* U;         // photons per bin unit per instance (1 in FP64)
+    const double* Linst;     // box side per instance
     const double* scale;     // [n_inst*nf] rescale of in-flight photons at hop 0 (FP32)
     const double* nrr_prev;  // RR photons to emit at hop 0
     const double* wrc;
@@ -694,6 +695,7 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R> a) {
     const int inst = valid ? a.inst_of[j] : 0;
     constexpr bool f32 = sizeof(R) == 4;
     const double U = f32 ? a.U[inst] : 1.0;
+    const double Linv = f32 ? 1.0 / a.Linst[inst] : 1.0;
 
     Acc<R> acc = {};
     R asum = 0, aerr = 0, psum = 0, perr = 0;
@@ -749,10 +751,10 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R> a) {
                 if (!sm) continue;
                 R vx, vy, vz;
                 if constexpr (f32) {
-                    const float4 pi = a.posf[i];
-                    vx = pjx - pi.x;
-                    vy = pjy - pi.y;
-                    vz = pjz - pi.z;
+                    // offsets in FP64, rounded once (box units)
+                    vx = static_cast<R>((a.pos[3 * j] - a.pos[3 * i]) * Linv);
+                    vy = static_cast<R>((a.pos[3 * j + 1] - a.pos[3 * i + 1]) * Linv);
+                    vz = static_cast<R>((a.pos[3 * j + 2] - a.pos[3 * i + 2]) * Linv);
                 } else {
                     vx = pjx - a.pos[3 * i];
                     vy = pjy - a.pos[3 * i + 1];
@@ -866,10 +868,9 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R> a) {
             const long long jj = nb[k];
             R vx, vy, vz;
             if constexpr (f32) {
-                const float4 q = a.posf[jj];
-                vx = q.x - pjx;
-                vy = q.y - pjy;
-                vz = q.z - pjz;
+                vx = static_cast<R>((a.pos[3 * jj] - a.pos[3 * j]) * Linv);
+                vy = static_cast<R>((a.pos[3 * jj + 1] - a.pos[3 * j + 1]) * Linv);
+                vz = static_cast<R>((a.pos[3 * jj + 2] - a.pos[3 * j + 2]) * Linv);
             } else {
                 vx = a.pos[3 * jj] - pjx;
                 vy = a.pos[3 * jj + 1] - pjy;

@@ -217,6 +217,7 @@ rt_status launch_hop(rt_ctx* c, int hop, int base) {
     a.dtc = c->f32 ? R(1) : static_cast<R>(c->p.dt);
     a.clf = c->clf_d;
     a.U = c->U_d;
+    a.Linst = c->L_d;
     a.scale = c->scale;
     a.nrr_prev = c->nrr[c->nrr_cur];
     a.wrc = c->rot + 9;

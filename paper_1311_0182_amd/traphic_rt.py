@@ -137,7 +137,10 @@ class Context:
                 return torch.cuda.caching_allocator_alloc(int(nbytes), dev, strm)
 
             def _dealloc(user, ptr):
-                torch.cuda.caching_allocator_delete(int(ptr))
+                try:
+                    torch.cuda.caching_allocator_delete(int(ptr))
+                except Exception:       # interpreter shutdown: the allocator is gone
+                    pass
 
             self._alloc_cb = ALLOC_FN(_alloc)
             self._dealloc_cb = DEALLOC_FN(_dealloc)
