@@ -20,6 +20,31 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_hop_float_stromgren64_rr_hbm_bytes.md")
+
+
+def kernel_sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("rt_kernels.hpp", "rt_device.hpp"):
+        with open(os.path.join(ROOT, "paper_1311_0182_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per forward-step launch from the committed counter summary,
+    valid only while the kernel sources are the ones that were measured."""
+    import re
+    try:
+        txt = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    sha = re.search(r"kernel_sources_sha256:\s*([0-9a-f]+)", txt)
+    val = re.search(r"traffic_bytes_per_launch:\s*([0-9]+)", txt)
+    if not sha or not val or sha.group(1) != kernel_sources_sha():
+        return None
+    return float(val.group(1))
 
 
 def cpu_baseline(budget_s):
@@ -49,11 +74,13 @@ def cpu_baseline(budget_s):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=float, default=0.0,
+                    help="first copy this many MiB device-to-device (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
@@ -67,6 +94,16 @@ def main():
     from paper_1311_0182_amd import traphic_rt as RT
 
     torch.cuda.set_device(0)
+    if args.calib_copy_mb > 0:
+        # a plain device copy of known size, so that hardware byte counters of a
+        # profiled run can be scaled to bytes
+        n = int(args.calib_copy_mb * (1 << 20)) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cfg = I.config(2)
     K, W = args.steps, args.warmup
 
@@ -129,7 +166,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "avg_launch_ms": avg_ms,
             "launches": int(tm["hop_launches"]),
             "bytes_per_launch": tm["hop_bytes"],

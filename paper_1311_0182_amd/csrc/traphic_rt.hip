@@ -103,6 +103,7 @@ struct rt_ctx {
     long long* chunk_hi = nullptr;
     long long* inst_chunk0 = nullptr;
     long long step = 0;
+    long long last_hops = 8;   // forward steps of the previous RT step
     // timing
     bool timing = false;
     std::vector<hipEvent_t> ev;
@@ -417,12 +418,17 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
     else
         TRY(launch_hop<double>(c, 0, base));
     TRY(time_end(c, 3));
-    const int batch = c->p.hop_batch > 0 ? c->p.hop_batch : 8;
+    // Forward steps are enqueued in batches between host checks of the device
+    // counters.  Automatic batching starts with the previous step's count less
+    // a margin, then goes one step at a time, so that almost no launch finds
+    // the step already finished.
+    int batch = c->p.hop_batch > 0 ? c->p.hop_batch : std::max(1, static_cast<int>(c->last_hops) - 3);
     long long H = 0;
     int h = 1;
     for (;;) {
         if (h <= c->p.max_hops) {
             const int hend = std::min(h + batch - 1, c->p.max_hops);
+            if (c->p.hop_batch <= 0) batch = 1;
             for (int q = h; q <= hend; ++q) {
                 TRY(time_begin(c, 2 + 2 * q));
                 TRY(launch_vip(c, q));
@@ -447,6 +453,7 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
         }
     }
     c->cur = static_cast<int>((base + H + 1) & 1);
+    c->last_hops = H;
     // chemistry
     TRY(time_begin(c, 1));
     ChemArgs ca{};
