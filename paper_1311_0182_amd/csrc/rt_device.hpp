@@ -238,4 +238,102 @@ __device__ inline double knn_query(const GridInfo& g, const int* __restrict__ ce
     return sqrt(bd[K - 1]);
 }
 
+// ---------------------------------------------------------------------------
+// Wavefront-cooperative exact kNN.  The 64 lanes scan the cells of one
+// Chebyshev shell at a time and append candidates (d^2, index) to an LDS
+// buffer; once there are K candidates, each candidate's rank in (d^2, index)
+// order is counted against all others, and the search stops when the K-th
+// smallest d^2 cannot be beaten by unvisited cells.  Same result as the
+// serial query (the K smallest pairs are unique).
+// ---------------------------------------------------------------------------
+constexpr int kWaveCand = 640;
+
+struct WaveKnn {
+    double d2[kWaveCand];
+    int idx[kWaveCand];
+    double res_d2[kMaxNgb];
+    int res_idx[kMaxNgb];
+    double kth;
+    int n;
+};
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ inline double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Returns false if the candidate buffer overflowed (the caller then falls
+// back to the serial query).  On success res_idx/res_d2[0..K) are sorted and
+// kth = res_d2[K-1].
+__device__ inline bool knn_wave(const GridInfo& g, const int* __restrict__ cell_start,
+                                const int* __restrict__ cell_idx, const double* __restrict__ pos,
+                                double qx, double qy, double qz, int self, int K, WaveKnn& L, int lane) {
+    if (lane == 0) L.n = 0;
+    wave_sync();
+    int c[3];
+    const double q[3] = {qx, qy, qz};
+    for (int a = 0; a < 3; ++a) {
+        int v = static_cast<int>(floor((q[a] - g.lo[a]) / g.cs[a]));
+        c[a] = v < 0 ? 0 : (v >= g.nc[a] ? g.nc[a] - 1 : v);
+    }
+    double csmin = g.cs[0] < g.cs[1] ? g.cs[0] : g.cs[1];
+    csmin = csmin < g.cs[2] ? csmin : g.cs[2];
+    int smax = g.nc[0] > g.nc[1] ? g.nc[0] : g.nc[1];
+    smax = smax > g.nc[2] ? smax : g.nc[2];
+    for (int s = 0; s <= smax; ++s) {
+        const int side = 2 * s + 1;
+        const int ncube = side * side * side;
+        for (int t = lane; t < ncube; t += 64) {
+            const int dx = t % side - s, dy = (t / side) % side - s, dz = t / (side * side) - s;
+            if (max(abs(dx), max(abs(dy), abs(dz))) != s) continue;
+            const int ix = c[0] + dx, iy = c[1] + dy, iz = c[2] + dz;
+            if (ix < 0 || ix >= g.nc[0] || iy < 0 || iy >= g.nc[1] || iz < 0 || iz >= g.nc[2]) continue;
+            const long long cell = g.cell0 + (static_cast<long long>(ix) * g.nc[1] + iy) * g.nc[2] + iz;
+            const int t1 = cell_start[cell + 1];
+            for (int u = cell_start[cell]; u < t1; ++u) {
+                const int j = cell_idx[u];
+                if (j == self) continue;
+                const double ex = pos[3 * static_cast<long long>(j) + 0] - qx;
+                const double ey = pos[3 * static_cast<long long>(j) + 1] - qy;
+                const double ez = pos[3 * static_cast<long long>(j) + 2] - qz;
+                const double d2 = ex * ex + ey * ey + ez * ez;
+                const int slot = atomicAdd(&L.n, 1);
+                if (slot < kWaveCand) {
+                    L.d2[slot] = d2;
+                    L.idx[slot] = j;
+                }
+            }
+        }
+        wave_sync();
+        const int n = L.n;
+        if (n > kWaveCand) return false;
+        if (n >= K) {
+            for (int cc = lane; cc < n; cc += 64) {
+                const double dc = L.d2[cc];
+                const int ic = L.idx[cc];
+                int rank = 0;
+                for (int u = 0; u < n; ++u) {
+                    const double du = L.d2[u];
+                    rank += (du < dc) || (du == dc && L.idx[u] < ic);
+                }
+                if (rank < K) {
+                    L.res_d2[rank] = dc;
+                    L.res_idx[rank] = ic;
+                }
+                if (rank == K - 1) L.kth = dc;
+            }
+            wave_sync();
+            const double reach = static_cast<double>(s) * csmin;
+            if (L.kth <= reach * reach) return true;
+        }
+        wave_sync();
+    }
+    return true;  // every cell visited
+}
+
 }  // namespace trt

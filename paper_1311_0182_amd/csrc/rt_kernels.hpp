@@ -7,9 +7,12 @@
 //     sm[b]  = for receiver slot r of (j, nu): bit p set when packet (j, nu, p)
 //              moves this forward step and arrives in reception cone r
 //   double-buffered (read one, write the other, swap per forward step).
-//   Neighbour lists ngb[j*K+k]; reverse lists (receiver-sorted) rev_off /
-//   rev_src / rev_pos, each sorted by sender index.
+//   Neighbour lists ngb[j*K+k]; receiver-sorted reverse lists rev_off /
+//   rev_ik (sender << 6 | position in the sender's list), sorted by sender,
+//   with the edge offsets rev_v; neighbour offsets fwd_v.
 #pragma once
+
+#include <type_traits>
 
 #include "rt_device.hpp"
 
@@ -30,6 +33,9 @@ enum : int {
     kCntN = 16
 };
 enum : long long { kFlagHopCap = 1, kFlagVipOverflow = 2, kFlagRecOverflow = 4, kFlagNonFinite = 8 };
+// units of the two fixed-point deposit accumulators, relative to the receiving particle's N_H
+constexpr double kDepositCoarse = 1.0 / 1073741824.0;         // 2^-30
+constexpr double kDepositFine = 1.0 / 4611686018427387904.0;  // 2^-62
 
 template <typename R>
 struct alignas(4 * sizeof(R)) Bin4 {
@@ -168,6 +174,50 @@ __global__ void k_rev_sort(long long N, const int* __restrict__ off, int* __rest
         }
         src[u + 1] = s;
         kpos[u + 1] = k;
+    }
+}
+
+// Static per-edge data of the forward step: packed reverse edges and offsets.
+// FP64: exact offsets.  FP32: receiver-minus-sender offsets in box units and
+// unit vectors towards the neighbours, both computed in FP64 and rounded once.
+template <typename V4>
+__global__ void k_edge_vectors(long long N, int K, const double* __restrict__ pos, const int* __restrict__ ngb,
+                               const int* __restrict__ rev_off, const int* __restrict__ rev_src,
+                               const unsigned char* __restrict__ rev_pos, const int* __restrict__ inst_of,
+                               const double* __restrict__ Linst, unsigned int* __restrict__ rev_ik,
+                               V4* __restrict__ rev_v, V4* __restrict__ fwd_v) {
+    const long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    constexpr bool f32 = sizeof(V4) == 16;
+    const double Li = f32 ? 1.0 / Linst[inst_of[j]] : 1.0;
+    const double xj = pos[3 * j], yj = pos[3 * j + 1], zj = pos[3 * j + 2];
+    for (int e = rev_off[j]; e < rev_off[j + 1]; ++e) {
+        const long long i = rev_src[e];
+        rev_ik[e] = (static_cast<unsigned int>(i) << 6) | rev_pos[e];
+        const double vx = xj - pos[3 * i], vy = yj - pos[3 * i + 1], vz = zj - pos[3 * i + 2];
+        V4 w;
+        w.x = vx * Li;
+        w.y = vy * Li;
+        w.z = vz * Li;
+        w.w = 0;
+        rev_v[e] = w;
+    }
+    for (int k = 0; k < K; ++k) {
+        const long long n = ngb[j * K + k];
+        const double vx = pos[3 * n] - xj, vy = pos[3 * n + 1] - yj, vz = pos[3 * n + 2] - zj;
+        V4 w;
+        if (f32) {
+            const double len = sqrt(vx * vx + vy * vy + vz * vz);
+            w.x = vx / len;
+            w.y = vy / len;
+            w.z = vz / len;
+        } else {
+            w.x = vx;
+            w.y = vy;
+            w.z = vz;
+        }
+        w.w = 0;
+        fwd_v[j * K + k] = w;
     }
 }
 
@@ -379,6 +429,7 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
 
 struct VipArgs {
     int hop, hop0, max_hops, K, nf, nrc, nec, max_depth;
+    long long* dep;  // [N*nf][2] deposited photons of virtual-particle legs, fixed point
     uint64_t seed;
     uint32_t step;
     double c2;
@@ -407,120 +458,140 @@ struct VipArgs {
     int act_rd, act_wr, list_rd, list_wr;
 };
 
-// Virtual particles (section 2.1): one thread per packet with an empty cone.
-// The particle is drawn uniformly in the cone inside the ball of radius h
-// around the origin; outside the box the packet escapes; otherwise it takes
-// SPH-interpolated properties from its own neighbours, the leg's absorptions
-// go to those neighbours in proportion to W_k N_H,k / n_H,k, and it forwards
-// the rest into its own transmission cone (chaining up to max_depth).
-__global__ __launch_bounds__(64) void k_vip(VipArgs a) {
-    const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+// Virtual particles (section 2.1): one wavefront per packet with an empty
+// cone.  The particle is drawn uniformly in the cone inside the ball of radius
+// h around the origin (64 rejection attempts per round, the lowest accepted
+// attempt wins, as if drawn one by one); outside the box the packet escapes;
+// otherwise it takes SPH-interpolated properties from its own N_ngb
+// neighbours (one lane each), the leg's absorptions go to those neighbours in
+// proportion to W_k N_H,k / n_H,k, and it forwards the rest into its own
+// transmission cone (chaining up to max_depth).
+__global__ __launch_bounds__(256) void k_vip(VipArgs a) {
+    __shared__ WaveKnn lds[4];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const long long gw = blockIdx.x * 4LL + wv;
+    const long long nw = gridDim.x * 4LL;
     if (!a.hop0) {
         // Once one forward step has found nothing to move, every later launch
         // of this step must exit: the ping-pong counters it would read are stale.
         if (a.cnt[kCntDone] != 0 || a.cnt[kCntAct0 + a.act_rd] == 0 || a.hop > a.max_hops) {
-            if (gid == 0) a.cnt[kCntDone] = 1;
+            if (gw == 0 && lane == 0) a.cnt[kCntDone] = 1;
             return;
         }
     }
-    if (gid == 0) {
+    if (gw == 0 && lane == 0) {
         a.cnt[kCntAct0 + a.act_wr] = 0;
         a.cnt[kCntVipCnt0 + a.list_wr] = 0;
     }
     long long n = a.cnt[kCntVipCnt0 + a.list_rd];
     if (n > a.vip_cap) n = a.vip_cap;
-    double bd[kMaxNgb];
-    int bi[kMaxNgb];
-    double wk[kMaxNgb];
-    for (long long v = gid; v < n; v += (long long)gridDim.x * blockDim.x) {
+    WaveKnn& L = lds[wv];
+    const int K = a.K;
+    for (long long v = gw; v < n; v += nw) {
         Vip q = a.list[v];
         const double* bx = a.box + 6 * q.inst;
         double* X = q.xr_emis ? a.exs : a.xs;
         double* Rm = q.xr_emis ? a.ers : a.rs;
         const GridInfo g = a.grid[q.inst];
         for (int depth = 1;; ++depth) {
-            atomicAdd(reinterpret_cast<unsigned long long*>(&a.cnt[kCntVips]), 1ull);
-            double p[3] = {0.0, 0.0, 0.0};
-            bool ok = false;
+            if (lane == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&a.cnt[kCntVips]), 1ull);
             const double* ecs = (q.ec >= 0 && depth == 1) ? a.ecd + 3 * (static_cast<long long>(q.ec) * a.nec) : nullptr;
-            for (uint32_t att = 0; att < kVipAttempts; ++att) {
+            double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+            bool found = false;
+            for (uint32_t base = 0; base < kVipAttempts; base += 64) {
                 double u[4];
-                uniforms4(a.seed, q.tag, att, a.step, q.ida, q.idb | static_cast<uint32_t>(depth), u);
-                p[0] = u[0];
-                p[1] = u[1];
-                p[2] = u[2];
-                if (p[0] * p[0] + p[1] * p[1] + p[2] * p[2] > 1.0) continue;
-                if (ecs) {
-                    if (nearest_direction(ecs, a.nec, p[0], p[1], p[2]) != q.ek) continue;
-                } else if (!in_cone(p[0], p[1], p[2], q.d[0], q.d[1], q.d[2], a.c2)) {
-                    continue;
+                uniforms4(a.seed, q.tag, base + lane, a.step, q.ida, q.idb | static_cast<uint32_t>(depth), u);
+                bool ok = u[0] * u[0] + u[1] * u[1] + u[2] * u[2] <= 1.0;
+                if (ok) ok = ecs ? nearest_direction(ecs, a.nec, u[0], u[1], u[2]) == q.ek
+                                 : in_cone(u[0], u[1], u[2], q.d[0], q.d[1], q.d[2], a.c2);
+                const unsigned long long b = __ballot(ok);
+                if (b) {
+                    const int f = __ffsll(static_cast<long long>(b)) - 1;
+                    p0 = __shfl(u[0], f, 64);
+                    p1 = __shfl(u[1], f, 64);
+                    p2 = __shfl(u[2], f, 64);
+                    found = true;
+                    break;
                 }
-                ok = true;
+            }
+            if (!found) {
+                if (lane == 0) Rm[q.xr] += q.N;
                 break;
             }
-            if (!ok) {
-                Rm[q.xr] += q.N;
-                break;
-            }
-            const double xv[3] = {q.x[0] + q.h * p[0], q.x[1] + q.h * p[1], q.x[2] + q.h * p[2]};
+            const double xv[3] = {q.x[0] + q.h * p0, q.x[1] + q.h * p1, q.x[2] + q.h * p2};
             if (xv[0] < bx[0] || xv[0] > bx[3] || xv[1] < bx[1] || xv[1] > bx[4] || xv[2] < bx[2] || xv[2] > bx[5]) {
-                X[q.xr] += q.N;
+                if (lane == 0) X[q.xr] += q.N;
                 break;
             }
-            const double hv = knn_query(g, a.cell_start, a.cell_idx, a.pos, xv[0], xv[1], xv[2], -1, a.K, bd, bi);
-            double wsum = 0.0;
-            for (int k = 0; k < a.K; ++k) {
-                const long long jk = bi[k];
-                const double dx = a.pos[3 * jk] - xv[0], dy = a.pos[3 * jk + 1] - xv[1], dz = a.pos[3 * jk + 2] - xv[2];
-                const double r = sqrt(dx * dx + dy * dy + dz * dz);
-                wk[k] = spline_shape(r, hv) * (a.NH[jk] / a.nH[jk]);
-                wsum += wk[k];
+            if (!knn_wave(g, a.cell_start, a.cell_idx, a.pos, xv[0], xv[1], xv[2], -1, K, L, lane)) {
+                // candidate buffer overflow (very clustered cells): serial query on one lane
+                if (lane == 0) {
+                    double bd[kMaxNgb];
+                    int bi[kMaxNgb];
+                    knn_query(g, a.cell_start, a.cell_idx, a.pos, xv[0], xv[1], xv[2], -1, K, bd, bi);
+                    for (int k = 0; k < K; ++k) {
+                        L.res_d2[k] = bd[k];
+                        L.res_idx[k] = bi[k];
+                    }
+                    L.kth = bd[K - 1];
+                }
+                wave_sync();
             }
+            const bool nbl = lane < K;
+            const long long jk = nbl ? L.res_idx[lane] : 0;
+            const double d2k = nbl ? L.res_d2[lane] : 0.0;
+            const double hv = sqrt(L.kth);
+            wave_sync();
+            double w = nbl ? spline_shape(sqrt(d2k), hv) * (a.NH[jk] / a.nH[jk]) : 0.0;
+            double wsum = wave_sum(w);
             if (!(wsum > 0.0)) {
-                for (int k = 0; k < a.K; ++k) wk[k] = 1.0;
-                wsum = static_cast<double>(a.K);
+                w = nbl ? 1.0 : 0.0;
+                wsum = static_cast<double>(K);
             }
-            double nhi = 0.0;
-            for (int k = 0; k < a.K; ++k) nhi += wk[k] * (a.xHI[bi[k]] * a.nH[bi[k]]);
-            nhi = nhi / wsum;
+            const double nhi = wave_sum(nbl ? w * (a.xHI[jk] * a.nH[jk]) : 0.0) / wsum;
             const double dd = sqrt(q.d[0] * q.d[0] + q.d[1] * q.d[1] + q.d[2] * q.d[2]);
             const double l = ((xv[0] - q.x[0]) * q.d[0] + (xv[1] - q.x[1]) * q.d[1] + (xv[2] - q.x[2]) * q.d[2]) / dd;
             const double tau = a.sigma[q.nu] * nhi * l;
             double nabs, nrem;
             attenuate(q.N, tau, nabs, nrem);
-            // deposits of the leg's absorptions
-            {
-                const int idx = alloc_records(a.cnt, a.K, a.rec_cap);
-                if (idx >= 0) {
-                    for (int k = 0; k < a.K; ++k) {
-                        Rec rc;
-                        rc.nout = 0.0;
-                        rc.dx = rc.dy = rc.dz = 0.0;
-                        rc.clk = 0.0;
-                        rc.nabs = nabs * wk[k] / wsum;
-                        rc.nin = 0.0;
-                        rc.key = q.key | (static_cast<unsigned long long>(depth) << 8) | static_cast<unsigned long long>(k);
-                        rc.j = bi[k];
-                        rc.o = -1 - q.nu;
-                        push_record(a.rec, a.rec_next, a.head, idx + k, rc);
+            // deposits of the leg's absorptions to the neighbours, as integers
+            // (order-independent, deterministic sums): a coarse part in units of
+            // N_H,k 2^-30 and a fine part in units of N_H,k 2^-62
+            if (nbl) {
+                const double x = (nabs * w / wsum) / a.NH[jk] * 1073741824.0;  // 2^30
+                if (x > 0.0) {
+                    double cpart = floor(x);
+                    if (!(cpart < 9.0e18)) {
+                        cpart = 9.0e18;
+                        atomicOr(reinterpret_cast<unsigned long long*>(&a.cnt[kCntFlags]), static_cast<unsigned long long>(kFlagRecOverflow));
                     }
+                    const long long ic = static_cast<long long>(cpart);
+                    const long long ifn = __double2ll_rn((x - cpart) * 4294967296.0);  // 2^32
+                    unsigned long long* d = reinterpret_cast<unsigned long long*>(&a.dep[2 * (jk * a.nf + q.nu)]);
+                    if (ic) atomicAdd(d, static_cast<unsigned long long>(ic));
+                    if (ifn) atomicAdd(d + 1, static_cast<unsigned long long>(ifn));
                 }
             }
             const double cv = q.c + l / kCLight;
-            int nc = 0;
-            for (int k = 0; k < a.K; ++k) {
-                const long long jk = bi[k];
-                nc += in_cone(a.pos[3 * jk] - xv[0], a.pos[3 * jk + 1] - xv[1], a.pos[3 * jk + 2] - xv[2], q.d[0], q.d[1], q.d[2], a.c2);
+            double vx = 0.0, vy = 0.0, vz = 0.0;
+            bool member = false;
+            if (nbl) {
+                vx = a.pos[3 * jk] - xv[0];
+                vy = a.pos[3 * jk + 1] - xv[1];
+                vz = a.pos[3 * jk + 2] - xv[2];
+                member = in_cone(vx, vy, vz, q.d[0], q.d[1], q.d[2], a.c2);
             }
+            const unsigned long long bm = __ballot(member);
+            const int nc = __popcll(bm);
             if (nc > 0) {
                 const int r = nearest_direction(a.wrc, a.nrc, q.d[0], q.d[1], q.d[2]);
                 const double nin = nrem / static_cast<double>(nc);
-                const int idx = alloc_records(a.cnt, nc, a.rec_cap);
-                int w = 0;
-                for (int k = 0; k < a.K; ++k) {
-                    const long long jk = bi[k];
-                    const double vx = a.pos[3 * jk] - xv[0], vy = a.pos[3 * jk + 1] - xv[1], vz = a.pos[3 * jk + 2] - xv[2];
-                    if (!in_cone(vx, vy, vz, q.d[0], q.d[1], q.d[2], a.c2)) continue;
+                int idx1 = 0;
+                if (lane == 0) idx1 = alloc_records(a.cnt, nc, a.rec_cap);
+                idx1 = __shfl(idx1, 0, 64);
+                if (member && idx1 >= 0) {
+                    const int w8 = __popcll(bm & ((1ull << lane) - 1ull));
                     const double lk = (vx * q.d[0] + vy * q.d[1] + vz * q.d[2]) / dd;
                     const double tk = a.sigma[q.nu] * a.xHI[jk] * a.nH[jk] * lk;
                     double ak, outk;
@@ -533,16 +604,16 @@ __global__ __launch_bounds__(64) void k_vip(VipArgs a) {
                     rc.clk = cv + lk / kCLight;
                     rc.nabs = ak;
                     rc.nin = nin;
-                    rc.key = q.key | (static_cast<unsigned long long>(depth) << 8) | (1ull << 7) | static_cast<unsigned long long>(k);
+                    rc.key = q.key | (static_cast<unsigned long long>(depth) << 8) | (1ull << 7) |
+                             static_cast<unsigned long long>(lane);
                     rc.j = static_cast<int>(jk);
                     rc.o = q.nu * a.nrc + r;
-                    if (idx >= 0) push_record(a.rec, a.rec_next, a.head, idx + w, rc);
-                    ++w;
+                    push_record(a.rec, a.rec_next, a.head, idx1 + w8, rc);
                 }
                 break;
             }
             if (depth >= a.max_depth) {
-                Rm[q.xr] += nrem;
+                if (lane == 0) Rm[q.xr] += nrem;
                 break;
             }
             q.x[0] = xv[0];
@@ -557,17 +628,29 @@ __global__ __launch_bounds__(64) void k_vip(VipArgs a) {
 
 // --------------------------------------------------------- forward step --
 
+// Per-step working arrays of a forward step, double-buffered:
+//   pk[b] = {dx, dy, dz, N}            packet of slot b
+//   pc[b] = {clock, N / n_c}            clock; photons per cone member if it moves
+//   cm[b] = cone mask over the neighbours of its particle (next step)
+//   tg[b] = reception cone it arrives in downstream (next step)
+//   dl[j*K + k] = bit (nu*N_RC + p) set: packet (j, nu, p) moves next step and
+//                 neighbour k of j is in its cone (delivery mask)
+//   nd[j] = 1 if a moving packet of j arrives in a cone other than its own index
 template <typename R>
+struct R2 {
+    R c, s;
+};
+
+template <typename R, typename DT>
 struct HopArgs {
     long long N, B;
-    int G, nrc, nf, K, rr_bin, rr_on;
+    int G, nrc, nf, K, rr_bin, rr_on, T;
     int hop, hop0, max_hops;
     const double* pos;
-    const float4* posf;
-    const int* ngb;
     const int* rev_off;
-    const int* rev_src;
-    const unsigned char* rev_pos;
+    const unsigned int* rev_ik;   // receiver-sorted edges: sender << 6 | position in the sender's list
+    const void* rev_v;            // their offsets x_receiver - x_sender (FP32: box units)
+    const void* fwd_v;            // offsets x_neighbour - x_particle (FP32: unit vectors)
     const int* inst_of;
     const double* xHI;
     const double* nH;
@@ -577,23 +660,26 @@ struct HopArgs {
     const double* sigma;
     const float* sigmaf;
     R c2;
+    R cosc;                  // cosine of the cone half-angle (FP32 unit-vector test)
     R dtc;                   // clock limit in clock units
     const float* clf;        // FP32: L_inst / (c dt) per instance
     const double* U;         // photons per bin unit per instance (1 in FP64)
-    const double* Linst;     // box side per instance
     const double* scale;     // [n_inst*nf] rescale of in-flight photons at hop 0 (FP32)
     const double* nrr_prev;  // RR photons to emit at hop 0
     const double* wrc;
     const float* wrcf;
     double dt;
     const Bin4<R>* pk_rd;
-    const R* pc_rd;
-    const unsigned long long* cm_rd;
-    const unsigned int* sm_rd;
+    const R2<R>* pc_rd;
+    const unsigned char* tg_rd;
+    const DT* dl_rd;
+    const unsigned char* nd_rd;
     Bin4<R>* pk_wr;
-    R* pc_wr;
+    R2<R>* pc_wr;
     unsigned long long* cm_wr;
-    unsigned int* sm_wr;
+    unsigned char* tg_wr;
+    DT* dl_wr;
+    unsigned char* nd_wr;
     double* A;
     double* P;
     const Rec* rec;
@@ -655,18 +741,23 @@ __device__ inline R group_sum(R v, int width) {
     return v;
 }
 
-// One forward step (section 2.1), receiver-sorted: lane = (particle j, bin nu,
-// reception cone r).  The lane gathers, over j's incoming neighbour edges,
-// the packets that move this step and arrive in its cone (split equally among
-// their cone members, attenuated by exp(-tau)), plus packets that stay, plus
-// records of emission and virtual particles, and merges them (photons add,
-// direction and clock luminosity-weighted).  Then, for the next step, it
-// finds its packet's cone members among j's neighbours and its reception cone
-// downstream, and publishes them as bit masks.  Hop 0 of a step merges what
-// stays (clocks carried over by -dt), the recombination photons of the last
+// One forward step (section 2.1), receiver-sorted.  A workgroup owns a tile
+// of T = 256 / G consecutive particles, one lane per slot (particle j, bin nu,
+// reception cone r).  The tile's incoming edges and their senders' delivery
+// masks are staged in LDS; a lane finds the packets that move this step from
+// a neighbour into its cone (split equally among the packet's cone members,
+// attenuated by exp(-tau)) from LDS alone and loads only those packets.  It
+// merges them with the packet that stays and the records of emission and
+// virtual particles (photons add, direction and clock luminosity-weighted).
+// For the next step it finds its packet's cone members among j's neighbours
+// (offsets staged in LDS) and its downstream reception cone, and the tile
+// publishes them as delivery masks.  Hop 0 of a step merges what stays
+// (clocks carried over by -dt), the recombination photons of the last
 // chemistry step (section 2.2) and the emission records.
-template <typename R>
-__global__ __launch_bounds__(256) void k_hop(HopArgs<R> a) {
+constexpr int kEdgeChunk = 512;
+
+template <typename R, typename DT>
+__global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
     if (!a.hop0) {
         if (a.cnt[kCntDone] != 0 || a.cnt[kCntAct0 + a.act_rd] == 0) {
             if (blockIdx.x == 0 && threadIdx.x == 0) a.cnt[kCntDone] = 1;
@@ -678,6 +769,14 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R> a) {
             return;
         }
     }
+    constexpr bool f32 = sizeof(R) == 4;
+    using V4 = typename std::conditional<f32, float4, double4>::type;
+    __shared__ unsigned int e_ik[kEdgeChunk];
+    __shared__ DT e_dl[kEdgeChunk];
+    __shared__ unsigned char e_nd[kEdgeChunk];
+    extern __shared__ __align__(32) unsigned char dyn_lds[];
+    V4* fv = reinterpret_cast<V4*>(dyn_lds);   // [T][K] offsets of the tile's neighbours
+
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (!a.hop0) {
             atomicAdd(reinterpret_cast<unsigned long long*>(&a.cnt[kCntHops]), 1ull);
@@ -685,35 +784,26 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R> a) {
         }
         a.cnt[kCntRec] = 0;  // records of this step were all linked before launch
     }
-    const long long blk = xcd_block(blockIdx.x, gridDim.x);
-    const long long s = blk * 256 + threadIdx.x;
-    const bool valid = s < a.B;
-    const long long j = valid ? s / a.G : 0;
-    const int o = valid ? static_cast<int>(s - j * a.G) : 0;
-    const int nu = o / a.nrc;
-    const int r = o - nu * a.nrc;
+    const int G = a.G, nrc = a.nrc, K = a.K, T = a.T;
+    const long long tile = xcd_block(blockIdx.x, gridDim.x);
+    const long long j0 = tile * T;
+    const int jl = threadIdx.x / G;
+    const int o = threadIdx.x - jl * G;
+    const long long j = j0 + jl;
+    const bool valid = jl < T && j < a.N;
+    const long long s = j * G + o;
+    const int nu = o / nrc;
+    const int r = o - nu * nrc;
     const int inst = valid ? a.inst_of[j] : 0;
-    constexpr bool f32 = sizeof(R) == 4;
     const double U = f32 ? a.U[inst] : 1.0;
-    const double Linv = f32 ? 1.0 / a.Linst[inst] : 1.0;
+    const long long jend = (j0 + T < a.N) ? j0 + T : a.N;
 
     Acc<R> acc = {};
     R asum = 0, aerr = 0, psum = 0, perr = 0;
     bool old_active = false;
-    R pjx = 0, pjy = 0, pjz = 0;
     if (valid) {
-        if constexpr (f32) {
-            const float4 q = a.posf[j];
-            pjx = q.x;
-            pjy = q.y;
-            pjz = q.z;
-        } else {
-            pjx = a.pos[3 * j];
-            pjy = a.pos[3 * j + 1];
-            pjz = a.pos[3 * j + 2];
-        }
         Bin4<R> q = a.pk_rd[s];
-        R c = a.pc_rd[s];
+        R c = a.pc_rd[s].c;
         if (q.n > R(0)) {
             if (a.hop0) {
                 if constexpr (f32) q.n = static_cast<R>(static_cast<double>(q.n) * a.scale[inst * a.nf + nu]);
@@ -728,66 +818,93 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R> a) {
         if (a.hop0 && a.rr_on && nu == a.rr_bin) {
             const double nr = a.nrr_prev[j];
             if (nr > 0.0) {
-                const R per = static_cast<R>(nr / static_cast<double>(a.nrc) / U);
+                const R per = static_cast<R>(nr / static_cast<double>(nrc) / U);
                 if constexpr (f32)
                     acc_add(acc, per, a.wrcf[3 * r], a.wrcf[3 * r + 1], a.wrcf[3 * r + 2], R(0));
                 else
                     acc_add(acc, per, R(a.wrc[3 * r]), R(a.wrc[3 * r + 1]), R(a.wrc[3 * r + 2]), R(0));
             }
         }
-        if (!a.hop0) {
-            const int e1 = a.rev_off[j + 1];
-            R kap = 0, clf = 0, sg = 0;
-            if constexpr (f32) {
+    }
+    if (!a.hop0) {
+        const long long e_t0 = a.rev_off[j0], e_t1 = a.rev_off[jend];
+        const long long my0 = valid ? a.rev_off[j] : 0, my1 = valid ? a.rev_off[j + 1] : 0;
+        R kap = 0, clf = 0, sg = 0;
+        if constexpr (f32) {
+            if (valid) {
                 kap = a.kappa[j];
                 clf = a.clf[inst];
                 sg = a.sigmaf[nu];
             }
-            for (int e = a.rev_off[j]; e < e1; ++e) {
-                const long long i = a.rev_src[e];
-                const int kp = a.rev_pos[e];
-                const long long base = i * a.G + static_cast<long long>(nu) * a.nrc;
-                unsigned int sm = a.sm_rd[base + r];
-                if (!sm) continue;
-                R vx, vy, vz;
-                if constexpr (f32) {
-                    // offsets in FP64, rounded once (box units)
-                    vx = static_cast<R>((a.pos[3 * j] - a.pos[3 * i]) * Linv);
-                    vy = static_cast<R>((a.pos[3 * j + 1] - a.pos[3 * i + 1]) * Linv);
-                    vz = static_cast<R>((a.pos[3 * j + 2] - a.pos[3 * i + 2]) * Linv);
-                } else {
-                    vx = pjx - a.pos[3 * i];
-                    vy = pjy - a.pos[3 * i + 1];
-                    vz = pjz - a.pos[3 * i + 2];
+        }
+        const DT gm = static_cast<DT>(nrc >= 8 * static_cast<int>(sizeof(DT)) ? ~DT(0) : ((DT(1) << nrc) - DT(1)));
+        for (long long cb = e_t0; cb < e_t1; cb += kEdgeChunk) {
+            __syncthreads();
+            const long long ne = (e_t1 - cb < kEdgeChunk) ? e_t1 - cb : kEdgeChunk;
+            for (long long t = threadIdx.x; t < ne; t += 256) {
+                const unsigned int ik = a.rev_ik[cb + t];
+                const long long i = ik >> 6;
+                e_ik[t] = ik;
+                e_dl[t] = a.dl_rd[i * K + (ik & 63u)];
+                e_nd[t] = a.nd_rd[i];
+            }
+            __syncthreads();
+            const long long lo = my0 > cb ? my0 : cb;
+            const long long hi = my1 < cb + ne ? my1 : cb + ne;
+            for (long long seg = lo; seg < hi; seg += 64) {
+                const int nseg = static_cast<int>((hi - seg) < 64 ? hi - seg : 64);
+                // pass 1 (LDS only): edges that bring something into this slot
+                unsigned long long hit = 0;
+                for (int u = 0; u < nseg; ++u) {
+                    const int t = static_cast<int>(seg - cb) + u;
+                    const DT m = (e_dl[t] >> (nu * nrc)) & gm;
+                    if (m == DT(0)) continue;
+                    if (e_nd[t] ? true : ((m >> r) & DT(1)) != DT(0)) hit |= 1ull << u;
                 }
-                while (sm) {
-                    const int p = __builtin_ctz(sm);
-                    sm &= sm - 1u;
-                    const long long t = base + p;
-                    const unsigned long long cm = a.cm_rd[t];
-                    if (!((cm >> kp) & 1ull)) continue;
-                    const Bin4<R> q = a.pk_rd[t];
-                    const R ct = a.pc_rd[t];
-                    const int nc = __popcll(cm);
-                    const R aa = vx * q.x + vy * q.y + vz * q.z;
-                    const R l = aa / sqrt(q.x * q.x + q.y * q.y + q.z * q.z);
-                    const R nin = q.n / static_cast<R>(nc);
-                    R tau, cl;
-                    if constexpr (f32) {
-                        tau = sg * kap * l;
-                        cl = ct + l * clf;
-                    } else {
-                        tau = a.sigma[nu] * a.xHI[j] * a.nH[j] * l;
-                        cl = ct + l / kCLight;
+                // pass 2: load and add the arriving packets, in edge order
+                while (hit) {
+                    const int u = __builtin_ctzll(hit);
+                    hit &= hit - 1ull;
+                    const int t = static_cast<int>(seg - cb) + u;
+                    const unsigned int ik = e_ik[t];
+                    const long long i = ik >> 6;
+                    const long long base = i * G + static_cast<long long>(nu) * nrc;
+                    DT m = (e_dl[t] >> (nu * nrc)) & gm;
+                    if (!e_nd[t]) m = DT(1) << r;
+                    V4 v;
+                    if constexpr (f32)
+                        v = static_cast<const float4*>(a.rev_v)[cb + t];
+                    else
+                        v = static_cast<const double4*>(a.rev_v)[cb + t];
+                    while (m != DT(0)) {
+                        const int pp = static_cast<int>(__builtin_ctzll(static_cast<unsigned long long>(m)));
+                        m &= m - DT(1);
+                        const long long tt = base + pp;
+                        if (e_nd[t] && a.tg_rd[tt] != r) continue;
+                        const Bin4<R> q = a.pk_rd[tt];
+                        const R2<R> qc = a.pc_rd[tt];
+                        const R aa = static_cast<R>(v.x) * q.x + static_cast<R>(v.y) * q.y + static_cast<R>(v.z) * q.z;
+                        const R l = aa / sqrt(q.x * q.x + q.y * q.y + q.z * q.z);
+                        const R nin = qc.s;
+                        R tau, cl;
+                        if constexpr (f32) {
+                            tau = sg * kap * l;
+                            cl = qc.c + l * clf;
+                        } else {
+                            tau = a.sigma[nu] * a.xHI[j] * a.nH[j] * l;
+                            cl = qc.c + l / kCLight;
+                        }
+                        R nabs, nout;
+                        attenuate(nin, tau, nabs, nout);
+                        sum_add(asum, aerr, nabs);
+                        sum_add(psum, perr, nin);
+                        acc_add(acc, nout, q.x, q.y, q.z, cl);
                     }
-                    R nabs, nout;
-                    attenuate(nin, tau, nabs, nout);
-                    sum_add(asum, aerr, nabs);
-                    sum_add(psum, perr, nin);
-                    acc_add(acc, nout, q.x, q.y, q.z, cl);
                 }
             }
         }
+    }
+    if (valid) {
         // records of emission and virtual particles, in key order
         const int hd = a.head_rd[j];
         if (hd >= 0) {
@@ -850,50 +967,52 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R> a) {
         dx = dy = dz = cn = 0;
     }
     // absorbed / passing photons of (j, nu): sum over the n_rc lanes
-    const R ag = group_sum(asum + aerr, a.nrc);
-    const R pg = group_sum(psum + perr, a.nrc);
+    const R ag = group_sum(asum + aerr, nrc);
+    const R pg = group_sum(psum + perr, nrc);
     if (valid && r == 0) {
         const long long ia = j * a.nf + nu;
         a.A[ia] += static_cast<double>(ag) * U;
         a.P[ia] += static_cast<double>(pg) * U;
     }
-    // next forward step: cone members and downstream reception cone
+    // next forward step: cone members and downstream reception cone.  The
+    // tile's neighbour offsets are staged only if some packet of it moves.
     const bool act = valid && nn > R(0) && cn < a.dtc;
+    if (__syncthreads_or(act)) {
+        const long long nfv = (jend - j0) * K;
+        const V4* src = static_cast<const V4*>(a.fwd_v) + j0 * K;
+        for (long long t = threadIdx.x; t < nfv; t += 256) fv[t] = src[t];
+        __syncthreads();
+    }
     unsigned long long cmw = 0;
-    int tgt = 0;
+    int tgt = r;
     if (act) {
-        const int* nb = a.ngb + j * a.K;
-        const R c2 = a.c2;
-        for (int k = 0; k < a.K; ++k) {
-            const long long jj = nb[k];
-            R vx, vy, vz;
-            if constexpr (f32) {
-                vx = static_cast<R>((a.pos[3 * jj] - a.pos[3 * j]) * Linv);
-                vy = static_cast<R>((a.pos[3 * jj + 1] - a.pos[3 * j + 1]) * Linv);
-                vz = static_cast<R>((a.pos[3 * jj + 2] - a.pos[3 * j + 2]) * Linv);
-            } else {
-                vx = a.pos[3 * jj] - pjx;
-                vy = a.pos[3 * jj + 1] - pjy;
-                vz = a.pos[3 * jj + 2] - pjz;
-            }
-            if (in_cone(vx, vy, vz, dx, dy, dz, c2)) cmw |= 1ull << k;
+        const V4* f = fv + static_cast<long long>(jl) * K;
+        for (int k = 0; k < K; ++k) {
+            const V4 w = f[k];
+            bool in;
+            if constexpr (f32)
+                in = w.x * dx + w.y * dy + w.z * dz >= a.cosc;
+            else
+                in = in_cone(w.x, w.y, w.z, dx, dy, dz, a.c2);
+            if (in) cmw |= 1ull << k;
         }
         if constexpr (f32)
-            tgt = nearest_direction(a.wrcf, a.nrc, dx, dy, dz);
+            tgt = nearest_direction(a.wrcf, nrc, dx, dy, dz);
         else
-            tgt = nearest_direction(a.wrc, a.nrc, dx, dy, dz);
+            tgt = nearest_direction(a.wrc, nrc, dx, dy, dz);
     }
     const bool send = act && cmw != 0;
     const bool vip = act && cmw == 0;
-    // sender masks: lane r of group (j, nu) gets the packets of the group that go to cone r
+    const int nc = __popcll(cmw);
+    // delivery masks: for each neighbour k, the packets of the particle that reach it
     const int lane = threadIdx.x & 63;
-    const int gbase = lane & ~(a.nrc - 1);
-    const unsigned long long gmask = a.nrc >= 64 ? ~0ull : ((1ull << a.nrc) - 1ull);
-    unsigned int mym = 0;
-    for (int q = 0; q < a.nrc; ++q) {
-        const unsigned long long b = __ballot(send && tgt == q);
-        if (r == q) mym = static_cast<unsigned int>((b >> gbase) & gmask);
+    const int gbase = lane & ~(G - 1);
+    const unsigned long long gmaskG = G >= 64 ? ~0ull : ((1ull << G) - 1ull);
+    for (int k = 0; k < K; ++k) {
+        const unsigned long long b = __ballot(send && ((cmw >> k) & 1ull));
+        if (valid && (k % G) == o) a.dl_wr[j * K + k] = static_cast<DT>((b >> gbase) & gmaskG);
     }
+    const bool offdiag = __ballot(send && tgt != r) & (gmaskG << gbase);
     if (valid) {
         Bin4<R> w;
         w.x = dx;
@@ -901,10 +1020,16 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R> a) {
         w.z = dz;
         w.n = nn;
         a.pk_wr[s] = w;
-        a.pc_wr[s] = cn;
+        R2<R> wc;
+        wc.c = cn;
+        wc.s = send ? nn / static_cast<R>(nc) : R(0);
+        a.pc_wr[s] = wc;
         a.cm_wr[s] = cmw;
-        a.sm_wr[s] = mym;
-        if (o == 0) a.head_reset[j] = -1;
+        a.tg_wr[s] = static_cast<unsigned char>(tgt);
+        if (o == 0) {
+            a.nd_wr[j] = offdiag ? 1 : 0;
+            a.head_reset[j] = -1;
+        }
         if (vip) {
             const long long v = push_vip(a.vip_out, a.cnt, a.list_wr, a.vip_cap);
             if (v >= 0) {
@@ -947,7 +1072,8 @@ struct ChemArgs {
     long long N;
     int nf, mode, isothermal, freeze, rr_on;
     double dt, frac;
-    const double* A;
+    double* A;
+    long long* dep;
     const double* eps;
     const double* nH;
     const double* NH;
@@ -969,6 +1095,13 @@ __global__ __launch_bounds__(256) void k_chem(ChemArgs a) {
     const long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (j >= a.N) return;
     const double nH = a.nH[j], NH = a.NH[j];
+    for (int nu = 0; nu < a.nf; ++nu) {
+        long long* d = a.dep + 2 * (j * a.nf + nu);
+        if (d[0] != 0 || d[1] != 0)
+            a.A[j * a.nf + nu] += (static_cast<double>(d[0]) * kDepositCoarse + static_cast<double>(d[1]) * kDepositFine) * NH;
+        d[0] = 0;
+        d[1] = 0;
+    }
     double y = a.xHI[j];
     double Tc = a.T[j];
     double rr = 0.0;

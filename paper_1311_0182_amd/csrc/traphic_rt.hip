@@ -43,7 +43,6 @@ struct rt_ctx {
     int* inst_of = nullptr;
     double* box_d = nullptr;
     double* pos = nullptr;
-    float4* posf = nullptr;
     double *nH = nullptr, *NH = nullptr, *xHI = nullptr, *T = nullptr, *h = nullptr;
     void* floor_b = nullptr;
     float* kappa = nullptr;
@@ -80,9 +79,17 @@ struct rt_ctx {
     void* pk[2] = {nullptr, nullptr};
     void* pc[2] = {nullptr, nullptr};
     unsigned long long* cm[2] = {nullptr, nullptr};
-    unsigned int* sm[2] = {nullptr, nullptr};
+    unsigned char* tg[2] = {nullptr, nullptr};
+    void* dl[2] = {nullptr, nullptr};
+    unsigned char* nd[2] = {nullptr, nullptr};
+    unsigned int* rev_ik = nullptr;
+    void* rev_v = nullptr;
+    void* fwd_v = nullptr;
+    int tileT = 1;         // particles per forward-step workgroup
+    bool dl64 = false;     // delivery masks need 64 bits (N_RC * N_freq > 32)
     int cur = 0;
     double *A = nullptr, *P = nullptr;
+    long long* dep = nullptr;  // fixed-point deposits of virtual particles
     double* nrr[2] = {nullptr, nullptr};
     int nrr_cur = 0;
     double *xs = nullptr, *rs = nullptr;
@@ -186,26 +193,26 @@ void direction_set(int n, std::vector<double>& u) {
 
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
-template <typename R>
+template <typename R, typename DT>
 rt_status launch_hop(rt_ctx* c, int hop, int base) {
-    HopArgs<R> a{};
+    HopArgs<R, DT> a{};
     a.N = c->N;
     a.B = c->B;
     a.G = c->G;
     a.nrc = c->nrc;
     a.nf = c->nf;
     a.K = c->K;
+    a.T = c->tileT;
     a.rr_bin = c->p.rr_bin;
     a.rr_on = c->rr_on ? 1 : 0;
     a.hop = hop;
     a.hop0 = hop == 0;
     a.max_hops = c->p.max_hops;
     a.pos = c->pos;
-    a.posf = c->posf;
-    a.ngb = c->ngb;
     a.rev_off = c->rev_off;
-    a.rev_src = c->rev_src;
-    a.rev_pos = c->rev_pos;
+    a.rev_ik = c->rev_ik;
+    a.rev_v = c->rev_v;
+    a.fwd_v = c->fwd_v;
     a.inst_of = c->inst_of;
     a.xHI = c->xHI;
     a.nH = c->nH;
@@ -215,10 +222,10 @@ rt_status launch_hop(rt_ctx* c, int hop, int base) {
     a.sigma = c->sigma_d;
     a.sigmaf = c->sigmaf_d;
     a.c2 = static_cast<R>(c->c2);
+    a.cosc = static_cast<R>(1.0 - 2.0 / static_cast<double>(c->p.n_tc));
     a.dtc = c->f32 ? R(1) : static_cast<R>(c->p.dt);
     a.clf = c->clf_d;
     a.U = c->U_d;
-    a.Linst = c->L_d;
     a.scale = c->scale;
     a.nrr_prev = c->nrr[c->nrr_cur];
     a.wrc = c->rot + 9;
@@ -226,13 +233,16 @@ rt_status launch_hop(rt_ctx* c, int hop, int base) {
     a.dt = c->p.dt;
     const int rd = (base + hop) & 1, wr = rd ^ 1;
     a.pk_rd = static_cast<const Bin4<R>*>(c->pk[rd]);
-    a.pc_rd = static_cast<const R*>(c->pc[rd]);
-    a.cm_rd = c->cm[rd];
-    a.sm_rd = c->sm[rd];
+    a.pc_rd = static_cast<const R2<R>*>(c->pc[rd]);
+    a.tg_rd = c->tg[rd];
+    a.dl_rd = static_cast<const DT*>(c->dl[rd]);
+    a.nd_rd = c->nd[rd];
     a.pk_wr = static_cast<Bin4<R>*>(c->pk[wr]);
-    a.pc_wr = static_cast<R*>(c->pc[wr]);
+    a.pc_wr = static_cast<R2<R>*>(c->pc[wr]);
     a.cm_wr = c->cm[wr];
-    a.sm_wr = c->sm[wr];
+    a.tg_wr = c->tg[wr];
+    a.dl_wr = static_cast<DT*>(c->dl[wr]);
+    a.nd_wr = c->nd[wr];
     a.A = c->A;
     a.P = c->P;
     a.rec = c->rec;
@@ -245,9 +255,15 @@ rt_status launch_hop(rt_ctx* c, int hop, int base) {
     a.cnt = c->cnt;
     a.act_rd = hop & 1;
     a.act_wr = (hop + 1) & 1;
-    hipLaunchKernelGGL(k_hop<R>, dim3(grid_for(c->B, 256)), dim3(256), 0, c->stream, a);
+    const size_t lds = static_cast<size_t>(c->tileT) * c->K * 4 * sizeof(R);
+    hipLaunchKernelGGL((k_hop<R, DT>), dim3(grid_for(c->N, c->tileT)), dim3(256), lds, c->stream, a);
     HIPCHK(c, hipGetLastError());
     return RT_OK;
+}
+
+rt_status launch_hop_any(rt_ctx* c, int hop, int base) {
+    if (c->f32) return c->dl64 ? launch_hop<float, unsigned long long>(c, hop, base) : launch_hop<float, unsigned int>(c, hop, base);
+    return c->dl64 ? launch_hop<double, unsigned long long>(c, hop, base) : launch_hop<double, unsigned int>(c, hop, base);
 }
 
 rt_status launch_vip(rt_ctx* c, int hop) {
@@ -260,6 +276,7 @@ rt_status launch_vip(rt_ctx* c, int hop) {
     a.nrc = c->nrc;
     a.nec = c->nec;
     a.max_depth = c->p.max_vip_depth;
+    a.dep = c->dep;
     a.seed = c->p.seed;
     a.step = static_cast<uint32_t>(c->step);
     a.c2 = c->c2;
@@ -289,7 +306,7 @@ rt_status launch_vip(rt_ctx* c, int hop) {
     a.act_wr = (hop + 1) & 1;
     a.list_rd = hop & 1;
     a.list_wr = (hop + 1) & 1;
-    hipLaunchKernelGGL(k_vip, dim3(256), dim3(64), 0, c->stream, a);
+    hipLaunchKernelGGL(k_vip, dim3(1024), dim3(256), 0, c->stream, a);
     HIPCHK(c, hipGetLastError());
     return RT_OK;
 }
@@ -413,10 +430,7 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
     TRY(launch_vip(c, 0));
     TRY(time_end(c, 0));
     TRY(time_begin(c, 3));
-    if (c->f32)
-        TRY(launch_hop<float>(c, 0, base));
-    else
-        TRY(launch_hop<double>(c, 0, base));
+    TRY(launch_hop_any(c, 0, base));
     TRY(time_end(c, 3));
     // Forward steps are enqueued in batches between host checks of the device
     // counters.  Automatic batching starts with the previous step's count less
@@ -434,10 +448,7 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
                 TRY(launch_vip(c, q));
                 TRY(time_end(c, 2 + 2 * q));
                 TRY(time_begin(c, 3 + 2 * q));
-                if (c->f32)
-                    TRY(launch_hop<float>(c, q, base));
-                else
-                    TRY(launch_hop<double>(c, q, base));
+                TRY(launch_hop_any(c, q, base));
                 TRY(time_end(c, 3 + 2 * q));
             }
             h = hend + 1;
@@ -466,6 +477,7 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
     ca.dt = c->p.dt;
     ca.frac = c->p.chem_frac;
     ca.A = c->A;
+    ca.dep = c->dep;
     ca.eps = c->eps_d;
     ca.nH = c->nH;
     ca.NH = c->NH;
@@ -570,7 +582,10 @@ rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, cons
         }
     }
     const long long N = inst_off[n_inst];
-    if (N >= (1ll << 31) - 1 || N * static_cast<long long>(p->n_ngb) >= (1ll << 31) - 1) return RT_EINVAL;
+    // particle indices are packed into 26 bits of the edge lists; the slots of
+    // one particle (N_RC x N_freq) form an aligned power-of-two lane group
+    if (N >= (1ll << 26) || N * static_cast<long long>(p->n_ngb) >= (1ll << 31) - 1) return RT_EINVAL;
+    if (!pow2(p->n_rc * p->n_freq) || p->n_rc * p->n_freq > 64) return RT_EINVAL;
     rt_ctx* c = new rt_ctx();
     c->p = *p;
     c->stream = static_cast<hipStream_t>(hip_stream);
@@ -583,6 +598,13 @@ rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, cons
     c->K = p->n_ngb;
     c->B = N * c->G;
     c->f32 = p->precision == RT_FP32;
+    c->dl64 = c->G > 32;
+    {
+        const size_t v4 = c->f32 ? 16 : 32;
+        int T = 256 / c->G;
+        while (T > 1 && static_cast<size_t>(T) * c->K * v4 > 48 * 1024) T /= 2;
+        c->tileT = T;
+    }
     c->rr_on = p->recomb_mode == RT_RR_TRANSPORT;
     const double cc = 1.0 - 2.0 / static_cast<double>(p->n_tc);
     c->c2 = cc * cc;
@@ -637,14 +659,6 @@ rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, cons
         ncell += static_cast<long long>(g.nc[0]) * g.nc[1] * g.nc[2];
     }
     // FP32 positions in units of the instance's box side, relative to its corner
-    std::vector<float4> posf(c->f32 ? N : 1);
-    if (c->f32)
-        for (long long i = 0; i < N; ++i) {
-            const int k = inst_of[i];
-            posf[i] = make_float4(static_cast<float>((pos[3 * i] - box[6 * k]) / c->L[k]),
-                                  static_cast<float>((pos[3 * i + 1] - box[6 * k + 1]) / c->L[k]),
-                                  static_cast<float>((pos[3 * i + 2] - box[6 * k + 2]) / c->L[k]), 0.f);
-        }
     std::vector<double> floor_d(N);
     std::vector<float> floor_f(c->f32 ? N : 1);
     for (long long i = 0; i < N; ++i) {
@@ -674,7 +688,6 @@ rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, cons
     ITRY(upload(c, &c->u_ec, uec.data(), 3ll * c->nec));
     ITRY(upload(c, &c->grid_d, grid.data(), n_inst));
     if (c->f32) {
-        ITRY(upload(c, &c->posf, posf.data(), N));
         float* fb = nullptr;
         ITRY(upload(c, &fb, floor_f.data(), N));
         c->floor_b = fb;
@@ -719,17 +732,34 @@ rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, cons
     hipLaunchKernelGGL(k_rev_sort, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, c->rev_off, c->rev_src,
                        c->rev_pos);
     HIPCHK(c, hipGetLastError());
+    // packed reverse edges and the offsets the forward step needs
+    ITRY(alloc_n(c, &c->rev_ik, N * c->K));
+    ITRY(dalloc(c, &c->rev_v, (c->f32 ? 16 : 32) * static_cast<size_t>(N * c->K)));
+    ITRY(dalloc(c, &c->fwd_v, (c->f32 ? 16 : 32) * static_cast<size_t>(N * c->K)));
+    if (c->f32)
+        hipLaunchKernelGGL(k_edge_vectors<float4>, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, c->K, c->pos,
+                           c->ngb, c->rev_off, c->rev_src, c->rev_pos, c->inst_of, c->L_d, c->rev_ik,
+                           static_cast<float4*>(c->rev_v), static_cast<float4*>(c->fwd_v));
+    else
+        hipLaunchKernelGGL(k_edge_vectors<double4>, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, c->K, c->pos,
+                           c->ngb, c->rev_off, c->rev_src, c->rev_pos, c->inst_of, c->L_d, c->rev_ik,
+                           static_cast<double4*>(c->rev_v), static_cast<double4*>(c->fwd_v));
+    HIPCHK(c, hipGetLastError());
     // bins and work buffers
     const size_t rsz = c->f32 ? sizeof(float) : sizeof(double);
     for (int b = 0; b < 2; ++b) {
         ITRY(dalloc(c, &c->pk[b], 4 * rsz * c->B));
-        ITRY(dalloc(c, &c->pc[b], rsz * c->B));
+        ITRY(dalloc(c, &c->pc[b], 2 * rsz * c->B));
         ITRY(alloc_n(c, &c->cm[b], c->B));
-        ITRY(alloc_n(c, &c->sm[b], c->B));
+        ITRY(alloc_n(c, &c->tg[b], c->B));
+        ITRY(dalloc(c, &c->dl[b], (c->dl64 ? 8 : 4) * static_cast<size_t>(N * c->K)));
+        ITRY(alloc_n(c, &c->nd[b], N));
         HIPCHK(c, hipMemsetAsync(c->pk[b], 0, 4 * rsz * c->B, c->stream));
-        HIPCHK(c, hipMemsetAsync(c->pc[b], 0, rsz * c->B, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->pc[b], 0, 2 * rsz * c->B, c->stream));
         HIPCHK(c, hipMemsetAsync(c->cm[b], 0, 8 * c->B, c->stream));
-        HIPCHK(c, hipMemsetAsync(c->sm[b], 0, 4 * c->B, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->tg[b], 0, c->B, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->dl[b], 0, (c->dl64 ? 8 : 4) * static_cast<size_t>(N * c->K), c->stream));
+        HIPCHK(c, hipMemsetAsync(c->nd[b], 0, N, c->stream));
         ITRY(alloc_n(c, &c->nrr[b], N));
         ITRY(fill_f64(c, c->nrr[b], N, 0.0));
         ITRY(alloc_n(c, &c->head[b], N));
@@ -737,6 +767,8 @@ rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, cons
     ITRY(alloc_n(c, &c->A, N * c->nf));
     ITRY(alloc_n(c, &c->P, N * c->nf));
     ITRY(fill_f64(c, c->A, N * c->nf, 0.0));
+    ITRY(alloc_n(c, &c->dep, 2 * N * c->nf));
+    HIPCHK(c, hipMemsetAsync(c->dep, 0, sizeof(long long) * 2 * N * c->nf, c->stream));
     ITRY(fill_f64(c, c->P, N * c->nf, 0.0));
     ITRY(alloc_n(c, &c->xs, c->B));
     ITRY(alloc_n(c, &c->rs, c->B));
@@ -927,9 +959,9 @@ rt_status rt_get_bins(rt_ctx* c, double* N, double* dir, double* clock) {
     HIPCHK(c, hipMemcpy(inst_of.data(), c->inst_of, sizeof(int) * c->N, hipMemcpyDeviceToHost));
     if (c->f32) {
         std::vector<Bin4<float>> pk(B);
-        std::vector<float> pc(B);
+        std::vector<float> pc(2 * B);
         HIPCHK(c, hipMemcpy(pk.data(), c->pk[c->cur], sizeof(Bin4<float>) * B, hipMemcpyDeviceToHost));
-        HIPCHK(c, hipMemcpy(pc.data(), c->pc[c->cur], sizeof(float) * B, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(pc.data(), c->pc[c->cur], sizeof(float) * 2 * B, hipMemcpyDeviceToHost));
         for (long long b = 0; b < B; ++b) {
             const int k = inst_of[b / c->G];
             if (N) N[b] = static_cast<double>(pk[b].n) * c->U[k];
@@ -938,13 +970,13 @@ rt_status rt_get_bins(rt_ctx* c, double* N, double* dir, double* clock) {
                 dir[3 * b + 1] = pk[b].y;
                 dir[3 * b + 2] = pk[b].z;
             }
-            if (clock) clock[b] = static_cast<double>(pc[b]) * c->p.dt;
+            if (clock) clock[b] = static_cast<double>(pc[2 * b]) * c->p.dt;
         }
     } else {
         std::vector<Bin4<double>> pk(B);
-        std::vector<double> pc(B);
+        std::vector<double> pc(2 * B);
         HIPCHK(c, hipMemcpy(pk.data(), c->pk[c->cur], sizeof(Bin4<double>) * B, hipMemcpyDeviceToHost));
-        HIPCHK(c, hipMemcpy(pc.data(), c->pc[c->cur], sizeof(double) * B, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(pc.data(), c->pc[c->cur], sizeof(double) * 2 * B, hipMemcpyDeviceToHost));
         for (long long b = 0; b < B; ++b) {
             if (N) N[b] = pk[b].n;
             if (dir) {
@@ -952,7 +984,7 @@ rt_status rt_get_bins(rt_ctx* c, double* N, double* dir, double* clock) {
                 dir[3 * b + 1] = pk[b].y;
                 dir[3 * b + 2] = pk[b].z;
             }
-            if (clock) clock[b] = pc[b];
+            if (clock) clock[b] = pc[2 * b];
         }
     }
     return RT_OK;
@@ -1005,12 +1037,15 @@ rt_status rt_get_timing(rt_ctx* c, double* out, int32_t n) {
     if (!c || !out || n < 0) return RT_EINVAL;
     const double rsz = c->f32 ? 4.0 : 8.0;
     // algorithmic bytes of one forward-step launch, counting only what every
-    // launch moves whatever the activity: each slot's packet and clock read,
-    // its sender mask read once, and packet, clock, cone mask and sender mask
-    // written; per particle its incoming edge list (4 + 1 bytes per edge), its
-    // position and its absorbed and passing photons (read + write).
-    const double per_slot = (4.0 * rsz + rsz) + 4.0 + (4.0 * rsz + rsz + 8.0 + 4.0);
-    const double per_part = 5.0 * c->K + (c->f32 ? 16.0 : 24.0) + 2.0 * 2.0 * 8.0 * c->nf;
+    // launch moves whatever the activity: each slot's packet and {clock, N/n_c}
+    // read and written, its cone mask and downstream cone written; per particle,
+    // for each incoming edge the packed edge word, the sender's delivery word
+    // and flag read, its own delivery words written, and its absorbed and
+    // passing photons read and written.  Packets of moving senders and the
+    // neighbour offsets of tiles with moving packets come on top.
+    const double dsz = c->dl64 ? 8.0 : 4.0;
+    const double per_slot = 2.0 * (6.0 * rsz) + 8.0 + 1.0;
+    const double per_part = c->K * (5.0 + 2.0 * dsz) + 2.0 * 2.0 * 8.0 * c->nf;
     const double bytes = per_slot * static_cast<double>(c->B) + per_part * static_cast<double>(c->N);
     double v[8] = {c->tm[0], c->tm[1], c->tm[2], c->tm[3], c->tm[4], c->tm[5], bytes, 0.0};
     for (int k = 0; k < n && k < 8; ++k) out[k] = v[k];
@@ -1027,7 +1062,7 @@ rt_status rt_get_state_blob(rt_ctx* c, void* blob, size_t* bytes) {
     if (!c || !bytes) return RT_EINVAL;
     if (c->sticky) return RT_EDEVICE;
     const size_t rsz = c->f32 ? 4 : 8;
-    const size_t need = sizeof(BlobHeader) + 5 * rsz * c->B + 3 * 8 * c->N + 8 * 5 * c->n_inst * c->nf +
+    const size_t need = sizeof(BlobHeader) + 6 * rsz * c->B + 3 * 8 * c->N + 8 * 5 * c->n_inst * c->nf +
                         8 * c->n_inst * c->nf + 8 * kCntN;
     if (!blob) {
         *bytes = need;
@@ -1041,8 +1076,8 @@ rt_status rt_get_state_blob(rt_ctx* c, void* blob, size_t* bytes) {
     q += sizeof hd;
     HIPCHK(c, hipMemcpy(q, c->pk[c->cur], 4 * rsz * c->B, hipMemcpyDeviceToHost));
     q += 4 * rsz * c->B;
-    HIPCHK(c, hipMemcpy(q, c->pc[c->cur], rsz * c->B, hipMemcpyDeviceToHost));
-    q += rsz * c->B;
+    HIPCHK(c, hipMemcpy(q, c->pc[c->cur], 2 * rsz * c->B, hipMemcpyDeviceToHost));
+    q += 2 * rsz * c->B;
     HIPCHK(c, hipMemcpy(q, c->xHI, 8 * c->N, hipMemcpyDeviceToHost));
     q += 8 * c->N;
     HIPCHK(c, hipMemcpy(q, c->T, 8 * c->N, hipMemcpyDeviceToHost));
@@ -1076,8 +1111,8 @@ rt_status rt_set_state_blob(rt_ctx* c, const void* blob, size_t bytes) {
     c->nrr_cur = 0;
     HIPCHK(c, hipMemcpy(c->pk[0], q, 4 * rsz * c->B, hipMemcpyHostToDevice));
     q += 4 * rsz * c->B;
-    HIPCHK(c, hipMemcpy(c->pc[0], q, rsz * c->B, hipMemcpyHostToDevice));
-    q += rsz * c->B;
+    HIPCHK(c, hipMemcpy(c->pc[0], q, 2 * rsz * c->B, hipMemcpyHostToDevice));
+    q += 2 * rsz * c->B;
     HIPCHK(c, hipMemcpy(c->xHI, q, 8 * c->N, hipMemcpyHostToDevice));
     q += 8 * c->N;
     HIPCHK(c, hipMemcpy(c->T, q, 8 * c->N, hipMemcpyHostToDevice));
