@@ -241,12 +241,16 @@ __device__ inline double knn_query(const GridInfo& g, const int* __restrict__ ce
 // ---------------------------------------------------------------------------
 // Wavefront-cooperative exact kNN.  The 64 lanes scan the cells of one
 // Chebyshev shell at a time and append candidates (d^2, index) to an LDS
-// buffer; once there are K candidates, each candidate's rank in (d^2, index)
-// order is counted against all others, and the search stops when the K-th
-// smallest d^2 cannot be beaten by unvisited cells.  Same result as the
-// serial query (the K smallest pairs are unique).
+// buffer.  Once there are at least K, the K-th smallest pair in (d^2, index)
+// order is found by bisection on the bits of d^2 (non-negative doubles order
+// like their bit patterns), counting with one ballot per register slot; the
+// search stops when that distance cannot be beaten by unvisited cells, and
+// otherwise the buffer is cut to the K best and later shells only add
+// candidates no farther than the current K-th.  Same result as the serial
+// query (the K smallest pairs are unique).
 // ---------------------------------------------------------------------------
 constexpr int kWaveCand = 640;
+constexpr int kWavePer = kWaveCand / 64;
 
 struct WaveKnn {
     double d2[kWaveCand];
@@ -267,6 +271,81 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
+// Number of register-held candidates (over the wave) that satisfy pred.
+template <typename P>
+__device__ inline int wave_count(P pred) {
+    int c = 0;
+#pragma unroll
+    for (int i = 0; i < kWavePer; ++i) c += __popcll(__ballot(pred(i)));
+    return c;
+}
+
+// Selects the K smallest of the n candidates in L.d2/L.idx (K <= n <=
+// kWaveCand) and writes them, compacted in arbitrary order, to L.d2/L.idx
+// [0, K).  Returns the K-th smallest d^2.
+__device__ inline double wave_select(WaveKnn& L, int n, int K, int lane) {
+    unsigned long long kb[kWavePer];
+    int ki[kWavePer];
+#pragma unroll
+    for (int i = 0; i < kWavePer; ++i) {
+        const int e = i * 64 + lane;
+        kb[i] = e < n ? static_cast<unsigned long long>(__double_as_longlong(L.d2[e])) : ~0ull;
+        ki[i] = e < n ? L.idx[e] : 0x7fffffff;
+    }
+    wave_sync();
+    // smallest t with #{d2 <= t} >= K
+    unsigned long long lo = ~0ull, hi = 0;
+#pragma unroll
+    for (int i = 0; i < kWavePer; ++i)
+        if (kb[i] != ~0ull) {
+            lo = kb[i] < lo ? kb[i] : lo;
+            hi = kb[i] > hi ? kb[i] : hi;
+        }
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long ol = __shfl_xor(lo, off, 64), oh = __shfl_xor(hi, off, 64);
+        lo = ol < lo ? ol : lo;
+        hi = oh > hi ? oh : hi;
+    }
+    while (lo < hi) {
+        const unsigned long long mid = lo + ((hi - lo) >> 1);
+        if (wave_count([&](int i) { return kb[i] <= mid; }) >= K)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    const unsigned long long t = lo;
+    const int nlt = wave_count([&](int i) { return kb[i] < t; });
+    const int neq = wave_count([&](int i) { return kb[i] == t; });
+    // among the pairs at distance t, the (K - nlt) smallest indices
+    int umax = 0x7fffffff;
+    if (neq > K - nlt) {
+        int ulo = 0, uhi = 0x7ffffffe;
+        while (ulo < uhi) {
+            const int mid = ulo + ((uhi - ulo) >> 1);
+            if (wave_count([&](int i) { return kb[i] == t && ki[i] <= mid; }) >= K - nlt)
+                uhi = mid;
+            else
+                ulo = mid + 1;
+        }
+        umax = ulo;
+    }
+    int base = 0;
+    const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int i = 0; i < kWavePer; ++i) {
+        const bool sel = kb[i] < t || (kb[i] == t && ki[i] <= umax);
+        const unsigned long long b = __ballot(sel);
+        if (sel) {
+            const int at = base + __popcll(b & below);
+            L.d2[at] = __longlong_as_double(static_cast<long long>(kb[i]));
+            L.idx[at] = ki[i];
+        }
+        base += __popcll(b);
+    }
+    wave_sync();
+    return __longlong_as_double(static_cast<long long>(t));
+}
+
 // Returns false if the candidate buffer overflowed (the caller then falls
 // back to the serial query).  On success res_idx/res_d2[0..K) are sorted and
 // kth = res_d2[K-1].
@@ -285,6 +364,7 @@ __device__ inline bool knn_wave(const GridInfo& g, const int* __restrict__ cell_
     csmin = csmin < g.cs[2] ? csmin : g.cs[2];
     int smax = g.nc[0] > g.nc[1] ? g.nc[0] : g.nc[1];
     smax = smax > g.nc[2] ? smax : g.nc[2];
+    double bound = __longlong_as_double(0x7ff0000000000000ll);  // +inf: keep every candidate
     for (int s = 0; s <= smax; ++s) {
         const int side = 2 * s + 1;
         const int ncube = side * side * side;
@@ -302,6 +382,7 @@ __device__ inline bool knn_wave(const GridInfo& g, const int* __restrict__ cell_
                 const double ey = pos[3 * static_cast<long long>(j) + 1] - qy;
                 const double ez = pos[3 * static_cast<long long>(j) + 2] - qz;
                 const double d2 = ex * ex + ey * ey + ez * ez;
+                if (!(d2 <= bound)) continue;
                 const int slot = atomicAdd(&L.n, 1);
                 if (slot < kWaveCand) {
                     L.d2[slot] = d2;
@@ -312,28 +393,31 @@ __device__ inline bool knn_wave(const GridInfo& g, const int* __restrict__ cell_
         wave_sync();
         const int n = L.n;
         if (n > kWaveCand) return false;
-        if (n >= K) {
-            for (int cc = lane; cc < n; cc += 64) {
-                const double dc = L.d2[cc];
-                const int ic = L.idx[cc];
+        if (n < K) continue;
+        const double kth = wave_select(L, n, K, lane);
+        const double reach = static_cast<double>(s) * csmin;
+        if (kth <= reach * reach || s == smax) {
+            // sort the K selected pairs by (d^2, index)
+            if (lane < K) {
+                const double dc = L.d2[lane];
+                const int ic = L.idx[lane];
                 int rank = 0;
-                for (int u = 0; u < n; ++u) {
+                for (int u = 0; u < K; ++u) {
                     const double du = L.d2[u];
                     rank += (du < dc) || (du == dc && L.idx[u] < ic);
                 }
-                if (rank < K) {
-                    L.res_d2[rank] = dc;
-                    L.res_idx[rank] = ic;
-                }
-                if (rank == K - 1) L.kth = dc;
+                L.res_d2[rank] = dc;
+                L.res_idx[rank] = ic;
             }
+            if (lane == 0) L.kth = kth;
             wave_sync();
-            const double reach = static_cast<double>(s) * csmin;
-            if (L.kth <= reach * reach) return true;
+            return true;
         }
+        bound = kth;
+        if (lane == 0) L.n = K;
         wave_sync();
     }
-    return true;  // every cell visited
+    return true;  // fewer than K particles in the instance
 }
 
 }  // namespace trt
