@@ -312,6 +312,7 @@ struct or_sim {
     double *u_rc, *u_ec;
     double *bN, *bd, *bc;       /* packet bins [N][n_freq][n_rc] */
     double *aN, *aS, *aC;       /* merge accumulators, same layout */
+    unsigned char *keep;        /* 1 while a bin holds only its own staying packet */
     double *A, *P;              /* absorbed / passing photons of the current step */
     double *nrr;                /* RR photons awaiting emission at the next step */
     double *led;                /* [n_inst][n_freq][4] cumulative E, A, X, R */
@@ -523,6 +524,7 @@ or_sim *or_create(const or_params *p, const double *sigma, const double *eps, in
     S->aN = xcalloc((size_t)B, sizeof(double));
     S->aS = xcalloc((size_t)B * 3, sizeof(double));
     S->aC = xcalloc((size_t)B, sizeof(double));
+    S->keep = xcalloc((size_t)B, 1);
     S->A = xcalloc((size_t)N * S->nf, sizeof(double));
     S->P = xcalloc((size_t)N * S->nf, sizeof(double));
     S->nrr = xcalloc((size_t)N, sizeof(double));
@@ -565,6 +567,7 @@ void or_destroy(or_sim *S)
     free(S->aN);
     free(S->aS);
     free(S->aC);
+    free(S->keep);
     free(S->A);
     free(S->P);
     free(S->nrr);
@@ -656,6 +659,7 @@ static int64_t slot_of(const or_sim *S, int64_t i, int nu, int q)
  * Reading: clocks merge luminosity-weighted too. */
 static void merge_in(or_sim *S, int64_t t, double N, const double d[3], double c)
 {
+    S->keep[t] = 0;
     S->aN[t] += N;
     S->aS[3 * t + 0] += N * d[0];
     S->aS[3 * t + 1] += N * d[1];
@@ -897,11 +901,13 @@ void or_merge_packets(int32_t n, const double *N, const double *d, const double 
 
 /* Convert the merge accumulators back into packets, then deposit packets that
  * fell below the floor (reading: floor_rel * N_H of the holding particle) as
- * absorbed at their particle. */
+ * absorbed at their particle.  Reading: merging combines the packets that
+ * meet in a bin, so a bin that received nothing keeps its packet as it is. */
 static void finalize_bins(or_sim *S)
 {
     int64_t B = S->N * S->G;
     for (int64_t t = 0; t < B; ++t) {
+        if (S->keep[t]) continue;
         int q = (int)(t % S->p.n_rc);
         merged_packet(S->aN[t], S->aS + 3 * t, S->aC[t], S->w_rc + 3 * q, &S->bN[t], S->bd + 3 * t,
                       &S->bc[t]);
@@ -921,6 +927,7 @@ static void finalize_bins(or_sim *S)
 static void stay(or_sim *S, int64_t t)
 {
     double N = S->bN[t];
+    S->keep[t] = 1;
     S->aN[t] = N;
     S->aS[3 * t + 0] = N * S->bd[3 * t + 0];
     S->aS[3 * t + 1] = N * S->bd[3 * t + 1];
@@ -1090,6 +1097,7 @@ static int one_step(or_sim *S)
         for (int64_t t = 0; t < B; ++t) {
             if (active(S, t)) {
                 S->aN[t] = 0.0;
+                S->keep[t] = 0;
                 S->aS[3 * t] = S->aS[3 * t + 1] = S->aS[3 * t + 2] = 0.0;
                 S->aC[t] = 0.0;
             } else {
