@@ -136,8 +136,11 @@ def main():
     E, A, X, R, F = np.moveaxis(led, -1, 0)
     resid = float(np.max(np.abs(E - A - X - R - F) / np.maximum(E, 1e-300)))
     tm = r32["timing"]
-    avg_ms = tm["hop_ms"] / max(tm["hop_launches"], 1)
-    achieved = tm["hop_bytes"] / (avg_ms * 1e-3) / 1e9
+    launches = max(tm["hop_launches"], 1)
+    avg_ms = tm["hop_ms"] / launches
+    bytes_per_launch = tm["hop_bytes_total"] / launches
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    n_tiles = -(-int(cfg["pos"].shape[0]) // 16)
     out = {
         "metric": "particle-packet updates/s per RT step, FP32-batched vs FP64 at x_HI err<=1e-3",
         "value": value,
@@ -169,7 +172,10 @@ def main():
             "traffic": measured_traffic(),
             "avg_launch_ms": avg_ms,
             "launches": int(tm["hop_launches"]),
-            "bytes_per_launch": tm["hop_bytes"],
+            "bytes_per_launch": bytes_per_launch,
+            "tiles_per_launch": tm["hop_tiles_total"] / launches,
+            "tiles": n_tiles,
+            "dense_bytes_per_hop": tm["dense_bytes_per_hop"],
         },
         "fp32_vs_fp64": None,
         "ledger_residual_fp32": resid,

@@ -147,11 +147,13 @@ rt_status rt_get_cone_masks(rt_ctx *ctx, uint64_t *mask);
 /* Recombination photons waiting to be emitted at the start of the next step, [N]. */
 rt_status rt_get_pending_rr(rt_ctx *ctx, double *nrr);
 
-/* Timing of the last rt_step, in ms, accumulated over its kernels (only when
- * timing is on): out[0] transport kernel total, out[1] launches of it, out[2]
- * virtual-particle kernel total, out[3] chemistry, out[4] emission, out[5]
- * ledger, out[6] bytes the transport kernel must move per launch on average
- * (algorithmic, from the packets it handled). */
+/* Timing of the last rt_step (only when timing is on; synchronises), up to
+ * n values: out[0] forward-step kernel total in ms, out[1] its launches,
+ * out[2] virtual-particle kernel total ms, out[3] chemistry ms, out[4]
+ * emission ms, out[5] ledger ms, out[6] algorithmic bytes the forward-step
+ * kernel moved over all its launches (counted on the device from the tiles,
+ * edges and packets it handled), out[7] tiles it processed, out[8] bytes of
+ * one forward step in the dense model (every slot read and written). */
 rt_status rt_set_timing(rt_ctx *ctx, int32_t on);
 rt_status rt_get_timing(rt_ctx *ctx, double *out, int32_t n);
 

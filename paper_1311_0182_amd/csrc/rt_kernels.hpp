@@ -30,6 +30,9 @@ enum : int {
     kCntVipCnt0 = 8,  // ViP list fill, ping-pong [8], [9]
     kCntRec = 10,
     kCntDone = 11,    // set once a forward step finds no active packet; later launches of the step exit
+    kCntBytes = 12,   // algorithmic bytes moved by forward steps (for the roofline)
+    kCntTiles = 13,   // forward-step tiles processed
+    kCntRan = 14,     // stamp of the last forward step that ran
     kCntN = 16
 };
 enum : long long { kFlagHopCap = 1, kFlagVipOverflow = 2, kFlagRecOverflow = 4, kFlagNonFinite = 8 };
@@ -194,6 +197,12 @@ __global__ void k_edge_vectors(long long N, int K, const double* __restrict__ po
     for (int e = rev_off[j]; e < rev_off[j + 1]; ++e) {
         const long long i = rev_src[e];
         rev_ik[e] = (static_cast<unsigned int>(i) << 6) | rev_pos[e];
+        // the forward edge (i, k) learns its receiver-sorted index e in its
+        // fourth component (the sender's thread writes only the first three)
+        if constexpr (f32)
+            fwd_v[i * K + rev_pos[e]].w = __int_as_float(e);
+        else
+            fwd_v[i * K + rev_pos[e]].w = __longlong_as_double(static_cast<long long>(e));
         const double vx = xj - pos[3 * i], vy = yj - pos[3 * i + 1], vz = zj - pos[3 * i + 2];
         V4 w;
         w.x = vx * Li;
@@ -205,7 +214,7 @@ __global__ void k_edge_vectors(long long N, int K, const double* __restrict__ po
     for (int k = 0; k < K; ++k) {
         const long long n = ngb[j * K + k];
         const double vx = pos[3 * n] - xj, vy = pos[3 * n + 1] - yj, vz = pos[3 * n + 2] - zj;
-        V4 w;
+        V4& w = fwd_v[j * K + k];
         if (f32) {
             const double len = sqrt(vx * vx + vy * vy + vz * vz);
             w.x = vx / len;
@@ -216,8 +225,6 @@ __global__ void k_edge_vectors(long long N, int K, const double* __restrict__ po
             w.y = vy;
             w.z = vz;
         }
-        w.w = 0;
-        fwd_v[j * K + k] = w;
     }
 }
 
@@ -454,6 +461,8 @@ struct VipArgs {
     int* rec_next;
     int* head;
     long long rec_cap;
+    int* hot;        // tiles that receive records in this forward step
+    int stamp, lgT;
     long long* cnt;
     int act_rd, act_wr, list_rd, list_wr;
 };
@@ -609,6 +618,7 @@ __global__ __launch_bounds__(256) void k_vip(VipArgs a) {
                     rc.j = static_cast<int>(jk);
                     rc.o = q.nu * a.nrc + r;
                     push_record(a.rec, a.rec_next, a.head, idx1 + w8, rc);
+                    a.hot[jk >> a.lgT] = a.stamp;
                 }
                 break;
             }
@@ -628,29 +638,45 @@ __global__ __launch_bounds__(256) void k_vip(VipArgs a) {
 
 // --------------------------------------------------------- forward step --
 
-// Per-step working arrays of a forward step, double-buffered:
-//   pk[b] = {dx, dy, dz, N}            packet of slot b
-//   pc[b] = {clock, N / n_c}            clock; photons per cone member if it moves
-//   cm[b] = cone mask over the neighbours of its particle (next step)
-//   tg[b] = reception cone it arrives in downstream (next step)
-//   dl[j*K + k] = bit (nu*N_RC + p) set: packet (j, nu, p) moves next step and
-//                 neighbour k of j is in its cone (delivery mask)
-//   nd[j] = 1 if a moving packet of j arrives in a cone other than its own index
+// Working arrays of the forward steps.
+// Resting state, updated in place by the workgroup that owns the particle:
+//   pk[b]  = {dx, dy, dz, N}, pcl[b] = clock    packet of slot b
+//   cm[b]  = cone mask over the neighbours of its particle, written when the
+//            packet becomes active
+// Moving packets, double-buffered by forward-step parity and read only in the
+// forward step after the one that wrote them:
+//   mv[b]  = {dx, dy, dz, N / n_c}, mvc[b] = {clock, downstream reception cone}
+//   inbox[e], e a receiver-sorted edge i -> j, written by the sender i:
+//     tag  = stamp << 1 | 1 if a moving packet of i arrives in a reception
+//            cone other than its own index
+//     mask = bit (nu*N_RC + p) set: packet (i, nu, p) moves and j is in its cone
+// Work marks: hot[tile] = stamp of the forward step in which the tile
+// receives packets or records, or has packets leaving.  A stamp numbers the
+// forward steps of the whole run, so inboxes and marks are never cleared.
 template <typename R>
 struct R2 {
     R c, s;
 };
 
+template <typename DT>
+struct Inbox {
+    unsigned int tag;
+    DT mask;
+};
+
 template <typename R, typename DT>
 struct HopArgs {
-    long long N, B;
-    int G, nrc, nf, K, rr_bin, rr_on, T;
+    long long N;
+    int G, nrc, nf, K, rr_bin, rr_on, T, lgT;
     int hop, hop0, max_hops;
+    int stamp;                    // of this forward step
     const double* pos;
     const int* rev_off;
     const unsigned int* rev_ik;   // receiver-sorted edges: sender << 6 | position in the sender's list
     const void* rev_v;            // their offsets x_receiver - x_sender (FP32: box units)
-    const void* fwd_v;            // offsets x_neighbour - x_particle (FP32: unit vectors)
+    const void* fwd_v;            // offsets x_neighbour - x_particle (FP32: unit vectors); fourth
+                                  // component: bits of the edge's receiver-sorted index
+    const int* ngb;
     const int* inst_of;
     const double* xHI;
     const double* nH;
@@ -669,27 +695,27 @@ struct HopArgs {
     const double* wrc;
     const float* wrcf;
     double dt;
-    const Bin4<R>* pk_rd;
-    const R2<R>* pc_rd;
-    const unsigned char* tg_rd;
-    const DT* dl_rd;
-    const unsigned char* nd_rd;
-    Bin4<R>* pk_wr;
-    R2<R>* pc_wr;
-    unsigned long long* cm_wr;
-    unsigned char* tg_wr;
-    DT* dl_wr;
-    unsigned char* nd_wr;
+    Bin4<R>* pk;
+    R* pcl;
+    unsigned long long* cm;
+    const Bin4<R>* mv_rd;
+    const R2<R>* mvc_rd;
+    const Inbox<DT>* in_rd;
+    const int* hot_rd;
+    Bin4<R>* mv_wr;
+    R2<R>* mvc_wr;
+    Inbox<DT>* in_wr;
+    int* hot_wr;
     double* A;
     double* P;
     const Rec* rec;
     const int* rec_next;
-    const int* head_rd;
-    int* head_reset;
+    int* head;               // record lists of this forward step, emptied once read
     Vip* vip_out;
     long long vip_cap;
     int list_wr;
     long long* cnt;
+    unsigned long long* part;  // [tile][3]: packets active next, packets moved, bytes
     int act_rd, act_wr;
 };
 
@@ -741,21 +767,57 @@ __device__ inline R group_sum(R v, int width) {
     return v;
 }
 
-// One forward step (section 2.1), receiver-sorted.  A workgroup owns a tile
-// of T = 256 / G consecutive particles, one lane per slot (particle j, bin nu,
-// reception cone r).  The tile's incoming edges and their senders' delivery
-// masks are staged in LDS; a lane finds the packets that move this step from
-// a neighbour into its cone (split equally among the packet's cone members,
-// attenuated by exp(-tau)) from LDS alone and loads only those packets.  It
-// merges them with the packet that stays and the records of emission and
-// virtual particles (photons add, direction and clock luminosity-weighted).
-// For the next step it finds its packet's cone members among j's neighbours
-// (offsets staged in LDS) and its downstream reception cone, and the tile
-// publishes them as delivery masks.  Hop 0 of a step merges what stays
-// (clocks carried over by -dt), the recombination photons of the last
-// chemistry step (section 2.2) and the emission records.
-constexpr int kEdgeChunk = 512;
+__device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
 
+// LDS of a forward-step workgroup (bytes from the start of its dynamic LDS).
+// While gathering: a chunk of the tile's incoming edges (their inboxes and
+// sender words), the queue of (edge, packet, receiving slot) pairs with
+// their contributions, and per particle the two values the attenuation needs.
+// Afterwards the same bytes hold, for the particles with active packets, the
+// neighbour offsets (receiver-sorted edge index in the fourth component), the
+// neighbours and the delivery words.
+template <typename R, typename DT>
+struct HopLds {
+    static constexpr int kEdges = 1024;                         // edges staged at a time
+    static constexpr int kPairs = sizeof(R) == 4 ? 512 : 256;   // pairs gathered at a time
+    static constexpr size_t ik = 0;
+    static constexpr size_t dl = ik + 4 * kEdges;
+    static constexpr size_t nd = dl + sizeof(DT) * kEdges;
+    static constexpr size_t desc = (nd + kEdges + 31) / 32 * 32;
+    static constexpr size_t val = desc + 4 * kPairs;
+    static constexpr size_t part = val + 7 * sizeof(R) * kPairs;
+    __host__ __device__ static constexpr int fstride(int K) { return K + 1; }  // padded against bank conflicts
+    __host__ __device__ static constexpr size_t ngb_off(int T, int K) {
+        return static_cast<size_t>(T) * fstride(K) * 4 * sizeof(R);
+    }
+    __host__ __device__ static constexpr size_t dw_off(int T, int K) { return ngb_off(T, K) + 4 * static_cast<size_t>(T) * K; }
+    __host__ __device__ static constexpr size_t bytes(int T, int K) {
+        const size_t g = part + 2 * sizeof(R) * static_cast<size_t>(T);
+        const size_t f = dw_off(T, K) + sizeof(DT) * static_cast<size_t>(T) * K;
+        return g > f ? g : f;
+    }
+};
+
+// One forward step (section 2.1), receiver-sorted.  A workgroup owns a tile
+// of T consecutive particles, one lane per slot (particle j, bin nu, reception
+// cone r), and runs only if the tile is marked for this step (hop 0 of an RT
+// step runs every tile).  Gathering: the inboxes of the tile's incoming edges
+// are staged in LDS; each slot counts the packets that arrive in its cone
+// (from LDS alone), a prefix sum lays the (edge, packet, slot) pairs out in
+// one queue, and all lanes load and attenuate the queued packets together
+// (split equally among the packet's cone members, absorbed 1 - exp(-tau));
+// each slot then adds its contributions in edge order.  It merges them with
+// the packet that stays and with the records of emission and virtual
+// particles (photons add, direction and clock luminosity-weighted); a bin that
+// receives nothing keeps its packet as it is.  For a packet that becomes
+// active it finds the cone members among j's neighbours and the downstream
+// reception cone, writes the delivery masks into the receivers' inboxes and
+// marks the tiles that will receive it.  Hop 0 of a step also merges what
+// stays (clocks carried over by -dt), the recombination photons of the last
+// chemistry step (section 2.2) and the emission records.
 template <typename R, typename DT>
 __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
     if (!a.hop0) {
@@ -769,23 +831,27 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
             return;
         }
     }
-    constexpr bool f32 = sizeof(R) == 4;
-    using V4 = typename std::conditional<f32, float4, double4>::type;
-    __shared__ unsigned int e_ik[kEdgeChunk];
-    __shared__ DT e_dl[kEdgeChunk];
-    __shared__ unsigned char e_nd[kEdgeChunk];
-    extern __shared__ __align__(32) unsigned char dyn_lds[];
-    V4* fv = reinterpret_cast<V4*>(dyn_lds);   // [T][K] offsets of the tile's neighbours
-
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (!a.hop0) {
-            atomicAdd(reinterpret_cast<unsigned long long*>(&a.cnt[kCntHops]), 1ull);
-            atomicAdd(reinterpret_cast<unsigned long long*>(&a.cnt[kCntHopsStep]), 1ull);
+            a.cnt[kCntHops] += 1;
+            a.cnt[kCntHopsStep] += 1;
         }
         a.cnt[kCntRec] = 0;  // records of this step were all linked before launch
+        a.cnt[kCntRan] = a.stamp;
     }
-    const int G = a.G, nrc = a.nrc, K = a.K, T = a.T;
     const long long tile = xcd_block(blockIdx.x, gridDim.x);
+    if (!a.hop0 && a.hot_rd[tile] != a.stamp) return;
+
+    constexpr bool f32 = sizeof(R) == 4;
+    constexpr unsigned long long rsz = sizeof(R);
+    using V4 = typename std::conditional<f32, float4, double4>::type;
+    using L = HopLds<R, DT>;
+    constexpr int kP = L::kPairs;
+    extern __shared__ __align__(32) unsigned char lds[];
+    __shared__ int s_scan[4];
+    __shared__ unsigned long long s_tally[3][4];
+
+    const int G = a.G, nrc = a.nrc, K = a.K, T = a.T;
     const long long j0 = tile * T;
     const int jl = threadIdx.x / G;
     const int o = threadIdx.x - jl * G;
@@ -797,24 +863,33 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
     const int inst = valid ? a.inst_of[j] : 0;
     const double U = f32 ? a.U[inst] : 1.0;
     const long long jend = (j0 + T < a.N) ? j0 + T : a.N;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    // algorithmic bytes this lane moves (slot state, gathered packets, edges)
+    unsigned long long nbytes = 0;
 
     Acc<R> acc = {};
+    int narr = 0;            // packets merged into the bin besides the one that stays
     R asum = 0, aerr = 0, psum = 0, perr = 0;
-    bool old_active = false;
+    Bin4<R> q0 = {};
+    R c0 = 0;
+    bool have_stay = false, departed = false;
     if (valid) {
-        Bin4<R> q = a.pk_rd[s];
-        R c = a.pc_rd[s].c;
-        if (q.n > R(0)) {
+        q0 = a.pk[s];
+        c0 = a.pcl[s];
+        nbytes += 5 * rsz;
+        if (q0.n > R(0)) {
             if (a.hop0) {
-                if constexpr (f32) q.n = static_cast<R>(static_cast<double>(q.n) * a.scale[inst * a.nf + nu]);
-                c = c - a.dtc;
-                acc_add(acc, q.n, q.x, q.y, q.z, c);
-            } else if (!(c < a.dtc)) {
-                acc_add(acc, q.n, q.x, q.y, q.z, c);
+                if constexpr (f32) q0.n = static_cast<R>(static_cast<double>(q0.n) * a.scale[inst * a.nf + nu]);
+                c0 = c0 - a.dtc;
+                have_stay = q0.n > R(0);
+            } else if (!(c0 < a.dtc)) {
+                have_stay = true;
             } else {
-                old_active = true;
+                departed = true;  // it moved on in this forward step
             }
         }
+        if (have_stay) acc_add(acc, q0.n, q0.x, q0.y, q0.z, c0);
         if (a.hop0 && a.rr_on && nu == a.rr_bin) {
             const double nr = a.nrr_prev[j];
             if (nr > 0.0) {
@@ -823,90 +898,162 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
                     acc_add(acc, per, a.wrcf[3 * r], a.wrcf[3 * r + 1], a.wrcf[3 * r + 2], R(0));
                 else
                     acc_add(acc, per, R(a.wrc[3 * r]), R(a.wrc[3 * r + 1]), R(a.wrc[3 * r + 2]), R(0));
+                ++narr;
             }
         }
     }
     if (!a.hop0) {
-        const long long e_t0 = a.rev_off[j0], e_t1 = a.rev_off[jend];
-        const long long my0 = valid ? a.rev_off[j] : 0, my1 = valid ? a.rev_off[j + 1] : 0;
-        R kap = 0, clf = 0, sg = 0;
-        if constexpr (f32) {
-            if (valid) {
-                kap = a.kappa[j];
-                clf = a.clf[inst];
-                sg = a.sigmaf[nu];
+        unsigned int* e_ik = reinterpret_cast<unsigned int*>(lds + L::ik);
+        DT* e_dl = reinterpret_cast<DT*>(lds + L::dl);
+        unsigned char* e_nd = lds + L::nd;
+        unsigned int* pdesc = reinterpret_cast<unsigned int*>(lds + L::desc);
+        R* pval = reinterpret_cast<R*>(lds + L::val);  // [7][kP]
+        R* pa = reinterpret_cast<R*>(lds + L::part);   // per particle: FP32 kappa, FP64 x_HI
+        R* pb = pa + T;                                 // per particle: FP32 L/(c dt), FP64 n_H
+        if (threadIdx.x < T && j0 + threadIdx.x < a.N) {
+            const long long jj = j0 + threadIdx.x;
+            if constexpr (f32) {
+                pa[threadIdx.x] = a.kappa[jj];
+                pb[threadIdx.x] = a.clf[a.inst_of[jj]];
+            } else {
+                pa[threadIdx.x] = a.xHI[jj];
+                pb[threadIdx.x] = a.nH[jj];
             }
         }
+        const long long e_t0 = a.rev_off[j0], e_t1 = a.rev_off[jend];
+        const long long my0 = valid ? a.rev_off[j] : 0, my1 = valid ? a.rev_off[j + 1] : 0;
+        const unsigned int prev = static_cast<unsigned int>(a.stamp - 1);
         const DT gm = static_cast<DT>(nrc >= 8 * static_cast<int>(sizeof(DT)) ? ~DT(0) : ((DT(1) << nrc) - DT(1)));
-        for (long long cb = e_t0; cb < e_t1; cb += kEdgeChunk) {
+        for (long long cb = e_t0; cb < e_t1; cb += L::kEdges) {
             __syncthreads();
-            const long long ne = (e_t1 - cb < kEdgeChunk) ? e_t1 - cb : kEdgeChunk;
+            const long long ne = (e_t1 - cb < L::kEdges) ? e_t1 - cb : L::kEdges;
             for (long long t = threadIdx.x; t < ne; t += 256) {
-                const unsigned int ik = a.rev_ik[cb + t];
-                const long long i = ik >> 6;
-                e_ik[t] = ik;
-                e_dl[t] = a.dl_rd[i * K + (ik & 63u)];
-                e_nd[t] = a.nd_rd[i];
+                const Inbox<DT> w = a.in_rd[cb + t];
+                e_ik[t] = a.rev_ik[cb + t];
+                e_dl[t] = (w.tag >> 1) == prev ? w.mask : DT(0);
+                e_nd[t] = static_cast<unsigned char>(w.tag & 1u);
+                nbytes += sizeof(Inbox<DT>) + 4;
             }
             __syncthreads();
             const long long lo = my0 > cb ? my0 : cb;
             const long long hi = my1 < cb + ne ? my1 : cb + ne;
-            for (long long seg = lo; seg < hi; seg += 64) {
-                const int nseg = static_cast<int>((hi - seg) < 64 ? hi - seg : 64);
-                // pass 1 (LDS only): edges that bring something into this slot
-                unsigned long long hit = 0;
-                for (int u = 0; u < nseg; ++u) {
-                    const int t = static_cast<int>(seg - cb) + u;
-                    const DT m = (e_dl[t] >> (nu * nrc)) & gm;
-                    if (m == DT(0)) continue;
-                    if (e_nd[t] ? true : ((m >> r) & DT(1)) != DT(0)) hit |= 1ull << u;
-                }
-                // pass 2: load and add the arriving packets, in edge order
-                while (hit) {
-                    const int u = __builtin_ctzll(hit);
-                    hit &= hit - 1ull;
-                    const int t = static_cast<int>(seg - cb) + u;
-                    const unsigned int ik = e_ik[t];
-                    const long long i = ik >> 6;
-                    const long long base = i * G + static_cast<long long>(nu) * nrc;
+            // this slot's arriving (edge, packet) pairs, in edge order
+            auto each_pair = [&](auto&& f) {
+                for (long long e = lo; e < hi; ++e) {
+                    const int t = static_cast<int>(e - cb);
                     DT m = (e_dl[t] >> (nu * nrc)) & gm;
-                    if (!e_nd[t]) m = DT(1) << r;
-                    V4 v;
-                    if constexpr (f32)
-                        v = static_cast<const float4*>(a.rev_v)[cb + t];
-                    else
-                        v = static_cast<const double4*>(a.rev_v)[cb + t];
+                    if (m == DT(0)) continue;
+                    if (!e_nd[t]) {
+                        if (((m >> r) & DT(1)) == DT(0)) continue;
+                        m = DT(1) << r;
+                    }
                     while (m != DT(0)) {
                         const int pp = static_cast<int>(__builtin_ctzll(static_cast<unsigned long long>(m)));
                         m &= m - DT(1);
-                        const long long tt = base + pp;
-                        if (e_nd[t] && a.tg_rd[tt] != r) continue;
-                        const Bin4<R> q = a.pk_rd[tt];
-                        const R2<R> qc = a.pc_rd[tt];
-                        const R aa = static_cast<R>(v.x) * q.x + static_cast<R>(v.y) * q.y + static_cast<R>(v.z) * q.z;
-                        const R l = aa / sqrt(q.x * q.x + q.y * q.y + q.z * q.z);
-                        const R nin = qc.s;
-                        R tau, cl;
-                        if constexpr (f32) {
-                            tau = sg * kap * l;
-                            cl = qc.c + l * clf;
-                        } else {
-                            tau = a.sigma[nu] * a.xHI[j] * a.nH[j] * l;
-                            cl = qc.c + l / kCLight;
-                        }
-                        R nabs, nout;
-                        attenuate(nin, tau, nabs, nout);
-                        sum_add(asum, aerr, nabs);
-                        sum_add(psum, perr, nin);
-                        acc_add(acc, nout, q.x, q.y, q.z, cl);
+                        f(t, pp);
                     }
                 }
+            };
+            int np = 0;
+            each_pair([&](int, int) { ++np; });
+            // exclusive prefix sum over the workgroup
+            int incl = np;
+            for (int off = 1; off < 64; off <<= 1) {
+                const int v = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += v;
+            }
+            if (lane == 63) s_scan[wave] = incl;
+            __syncthreads();
+            int M = 0, wbase = 0;
+            for (int w = 0; w < 4; ++w) {
+                if (w < wave) wbase += s_scan[w];
+                M += s_scan[w];
+            }
+            const int off0 = wbase + incl - np;
+            for (int base = 0; base < M; base += kP) {
+                if (np) {
+                    int q = off0;
+                    each_pair([&](int t, int pp) {
+                        if (q >= base && q < base + kP)
+                            pdesc[q - base] = (static_cast<unsigned int>(t) << 14) | (static_cast<unsigned int>(pp) << 8) | threadIdx.x;
+                        ++q;
+                    });
+                }
+                __syncthreads();
+                const int nr = (M - base < kP) ? M - base : kP;
+                // load and attenuate the queued packets (all lanes; loads first)
+                constexpr int kPer = kP / 256;
+                Bin4<R> q[kPer];
+                R2<R> qc[kPer];
+                V4 v[kPer];
+#pragma unroll
+                for (int i = 0; i < kPer; ++i) {
+                    const int u = threadIdx.x + 256 * i;
+                    if (u < nr) {
+                        const unsigned int d = pdesc[u];
+                        const int t = static_cast<int>(d >> 14), pp = static_cast<int>(d >> 8) & 63, sl = static_cast<int>(d & 255u);
+                        const int so = sl % G;
+                        const long long tt = static_cast<long long>(e_ik[t] >> 6) * G + (so / nrc) * nrc + pp;
+                        qc[i] = a.mvc_rd[tt];
+                        q[i] = a.mv_rd[tt];
+                        v[i] = static_cast<const V4*>(a.rev_v)[cb + t];
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < kPer; ++i) {
+                    const int u = threadIdx.x + 256 * i;
+                    if (u < nr) {
+                        const unsigned int d = pdesc[u];
+                        const int t = static_cast<int>(d >> 14), sl = static_cast<int>(d & 255u);
+                        const int sjl = sl / G, so = sl - sjl * G, snu = so / nrc, sr = so - snu * nrc;
+                        nbytes += 10 * rsz;
+                        if (e_nd[t] && static_cast<int>(qc[i].s) != sr) {
+                            pval[6 * kP + u] = R(-1);  // arrives in another cone of the particle
+                            continue;
+                        }
+                        const R aa = static_cast<R>(v[i].x) * q[i].x + static_cast<R>(v[i].y) * q[i].y +
+                                     static_cast<R>(v[i].z) * q[i].z;
+                        const R l = aa / sqrt(q[i].x * q[i].x + q[i].y * q[i].y + q[i].z * q[i].z);
+                        R tau, cl;
+                        if constexpr (f32) {
+                            tau = a.sigmaf[snu] * pa[sjl] * l;
+                            cl = qc[i].c + l * pb[sjl];
+                        } else {
+                            tau = a.sigma[snu] * pa[sjl] * pb[sjl] * l;
+                            cl = qc[i].c + l / kCLight;
+                        }
+                        R nabs, nout;
+                        attenuate(q[i].n, tau, nabs, nout);
+                        pval[u] = nout;
+                        pval[kP + u] = q[i].x;
+                        pval[2 * kP + u] = q[i].y;
+                        pval[3 * kP + u] = q[i].z;
+                        pval[4 * kP + u] = cl;
+                        pval[5 * kP + u] = nabs;
+                        pval[6 * kP + u] = q[i].n;
+                    }
+                }
+                __syncthreads();
+                // this slot's contributions, in order
+                const int qa = off0 > base ? off0 : base;
+                const int qb = (off0 + np < base + nr) ? off0 + np : base + nr;
+                for (int qq = qa; qq < qb; ++qq) {
+                    const int u = qq - base;
+                    const R nin = pval[6 * kP + u];
+                    if (nin < R(0)) continue;
+                    sum_add(asum, aerr, pval[5 * kP + u]);
+                    sum_add(psum, perr, nin);
+                    acc_add(acc, pval[u], pval[kP + u], pval[2 * kP + u], pval[3 * kP + u], pval[4 * kP + u]);
+                    ++narr;
+                }
+                __syncthreads();
             }
         }
     }
+    int hd = -1;
     if (valid) {
         // records of emission and virtual particles, in key order
-        const int hd = a.head_rd[j];
+        hd = a.head[j];
         if (hd >= 0) {
             unsigned long long last = 0;
             bool first = true;
@@ -925,6 +1072,7 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
                 }
                 if (bidx < 0) break;
                 const Rec rc = a.rec[bidx];
+                nbytes += sizeof(Rec);
                 last = best;
                 first = false;
                 sum_add(asum, aerr, static_cast<R>(rc.nabs / U));
@@ -932,63 +1080,90 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
                     sum_add(psum, perr, static_cast<R>(rc.nin / U));
                     acc_add(acc, static_cast<R>(rc.nout / U), static_cast<R>(rc.dx), static_cast<R>(rc.dy),
                             static_cast<R>(rc.dz), static_cast<R>(f32 ? rc.clk / a.dt : rc.clk));
+                    ++narr;
                 }
             }
         }
     }
-    // merged packet
-    R nn = acc.n + acc.en, sx = acc.sx + acc.ex, sy = acc.sy + acc.ey, sz = acc.sz + acc.ez, sc = acc.sc + acc.ec;
-    R dx = 0, dy = 0, dz = 0, cn = 0;
-    if (nn > R(0)) {
-        const R s2 = sx * sx + sy * sy + sz * sz;
-        if (s2 > R(0)) {
-            const R nr = sqrt(s2);
-            dx = sx / nr;
-            dy = sy / nr;
-            dz = sz / nr;
-        } else {
-            if constexpr (f32) {
-                dx = a.wrcf[3 * r];
-                dy = a.wrcf[3 * r + 1];
-                dz = a.wrcf[3 * r + 2];
-            } else {
-                dx = a.wrc[3 * r];
-                dy = a.wrc[3 * r + 1];
-                dz = a.wrc[3 * r + 2];
-            }
+    // the bin's packet: merged if anything arrived, otherwise the one that stays
+    R nn = 0, dx = 0, dy = 0, dz = 0, cn = 0;
+    if (narr == 0) {
+        if (have_stay) {
+            nn = q0.n;
+            dx = q0.x;
+            dy = q0.y;
+            dz = q0.z;
+            cn = c0;
         }
-        cn = sc / nn;
     } else {
-        nn = 0;
+        const R an = acc.n + acc.en, sx = acc.sx + acc.ex, sy = acc.sy + acc.ey, sz = acc.sz + acc.ez,
+                sc = acc.sc + acc.ec;
+        if (an > R(0)) {
+            nn = an;
+            const R s2 = sx * sx + sy * sy + sz * sz;
+            if (s2 > R(0)) {
+                const R nr = sqrt(s2);
+                dx = sx / nr;
+                dy = sy / nr;
+                dz = sz / nr;
+            } else {
+                if constexpr (f32) {
+                    dx = a.wrcf[3 * r];
+                    dy = a.wrcf[3 * r + 1];
+                    dz = a.wrcf[3 * r + 2];
+                } else {
+                    dx = a.wrc[3 * r];
+                    dy = a.wrc[3 * r + 1];
+                    dz = a.wrc[3 * r + 2];
+                }
+            }
+            cn = sc / an;
+        }
     }
+    bool floored = false;
     if (valid && nn > R(0) && nn < a.floor_b[j]) {
         sum_add(asum, aerr, nn);
         nn = 0;
         dx = dy = dz = cn = 0;
+        floored = true;
     }
     // absorbed / passing photons of (j, nu): sum over the n_rc lanes
     const R ag = group_sum(asum + aerr, nrc);
     const R pg = group_sum(psum + perr, nrc);
-    if (valid && r == 0) {
+    if (valid && r == 0 && (ag != R(0) || pg != R(0))) {
         const long long ia = j * a.nf + nu;
         a.A[ia] += static_cast<double>(ag) * U;
         a.P[ia] += static_cast<double>(pg) * U;
+        nbytes += 32;
     }
     // next forward step: cone members and downstream reception cone.  The
-    // tile's neighbour offsets are staged only if some packet of it moves.
+    // lanes of a particle with an active packet stage its neighbour offsets
+    // (with the receiver-sorted index of each edge) and its neighbours.
     const bool act = valid && nn > R(0) && cn < a.dtc;
-    if (__syncthreads_or(act)) {
-        const long long nfv = (jend - j0) * K;
-        const V4* src = static_cast<const V4*>(a.fwd_v) + j0 * K;
-        for (long long t = threadIdx.x; t < nfv; t += 256) fv[t] = src[t];
-        __syncthreads();
+    const bool tile_act = __syncthreads_or(act);  // also: the gather's LDS is free again
+    if (valid && o == 0 && hd >= 0) a.head[j] = -1;  // every lane of j has read its records
+    if (tile_act && threadIdx.x == 0) a.hot_wr[tile] = a.stamp + 1;  // its leaving packets empty their bins
+    const int gbase = lane & ~(G - 1);
+    const unsigned long long gmaskG = G >= 64 ? ~0ull : ((1ull << G) - 1ull);
+    const bool pact = ((__ballot(act) >> gbase) & gmaskG) != 0;
+    V4* fj = reinterpret_cast<V4*>(lds) + static_cast<long long>(jl) * L::fstride(K);
+    int* nj = reinterpret_cast<int*>(lds + L::ngb_off(T, K)) + static_cast<long long>(jl) * K;
+    DT* dw = reinterpret_cast<DT*>(lds + L::dw_off(T, K)) + static_cast<long long>(jl) * K;
+    if (pact) {
+        const V4* src = static_cast<const V4*>(a.fwd_v) + j * K;
+        const int* sn = a.ngb + j * K;
+        for (int k = o; k < K; k += G) {
+            fj[k] = src[k];
+            nj[k] = sn[k];
+        }
+        if (o == 0) nbytes += static_cast<unsigned long long>(K) * (4 * rsz + 4);
     }
+    wave_sync();  // a particle's lanes lie in one wavefront
     unsigned long long cmw = 0;
     int tgt = r;
     if (act) {
-        const V4* f = fv + static_cast<long long>(jl) * K;
         for (int k = 0; k < K; ++k) {
-            const V4 w = f[k];
+            const V4 w = fj[k];
             bool in;
             if constexpr (f32)
                 in = w.x * dx + w.y * dy + w.z * dz >= a.cosc;
@@ -1004,31 +1179,63 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
     const bool send = act && cmw != 0;
     const bool vip = act && cmw == 0;
     const int nc = __popcll(cmw);
-    // delivery masks: for each neighbour k, the packets of the particle that reach it
-    const int lane = threadIdx.x & 63;
-    const int gbase = lane & ~(G - 1);
-    const unsigned long long gmaskG = G >= 64 ? ~0ull : ((1ull << G) - 1ull);
-    for (int k = 0; k < K; ++k) {
-        const unsigned long long b = __ballot(send && ((cmw >> k) & 1ull));
-        if (valid && (k % G) == o) a.dl_wr[j * K + k] = static_cast<DT>((b >> gbase) & gmaskG);
-    }
+    // delivery words: for each neighbour k, the packets of the particle that
+    // reach it; written into the receivers' inboxes, whose tiles are marked
+    // for the next forward step
+    const unsigned long long wsend = __ballot(send);
+    const bool psend = ((wsend >> gbase) & gmaskG) != 0;
     const bool offdiag = __ballot(send && tgt != r) & (gmaskG << gbase);
+    if (wsend) {
+        for (int k = 0; k < K; ++k) {
+            const unsigned long long b = __ballot(send && ((cmw >> k) & 1ull));
+            if (psend && (k % G) == o) dw[k] = static_cast<DT>((b >> gbase) & gmaskG);
+        }
+        wave_sync();
+        if (psend) {
+            Inbox<DT> ib;
+            ib.tag = (static_cast<unsigned int>(a.stamp) << 1) | (offdiag ? 1u : 0u);
+            for (int k = o; k < K; k += G) {
+                const DT w = dw[k];
+                if (w == DT(0)) continue;
+                ib.mask = w;
+                long long e;
+                if constexpr (f32)
+                    e = __float_as_int(fj[k].w);
+                else
+                    e = __double_as_longlong(fj[k].w);
+                a.in_wr[e] = ib;
+                a.hot_wr[nj[k] >> a.lgT] = a.stamp + 1;
+                nbytes += sizeof(Inbox<DT>) + 4;
+            }
+        }
+    }
     if (valid) {
-        Bin4<R> w;
-        w.x = dx;
-        w.y = dy;
-        w.z = dz;
-        w.n = nn;
-        a.pk_wr[s] = w;
-        R2<R> wc;
-        wc.c = cn;
-        wc.s = send ? nn / static_cast<R>(nc) : R(0);
-        a.pc_wr[s] = wc;
-        a.cm_wr[s] = cmw;
-        a.tg_wr[s] = static_cast<unsigned char>(tgt);
-        if (o == 0) {
-            a.nd_wr[j] = offdiag ? 1 : 0;
-            a.head_reset[j] = -1;
+        if (a.hop0 || narr > 0 || departed || floored) {
+            Bin4<R> w;
+            w.x = dx;
+            w.y = dy;
+            w.z = dz;
+            w.n = nn;
+            a.pk[s] = w;
+            a.pcl[s] = cn;
+            nbytes += 5 * rsz;
+        }
+        if (act) {
+            a.cm[s] = cmw;
+            nbytes += 8;
+        }
+        if (send) {
+            Bin4<R> w;
+            w.x = dx;
+            w.y = dy;
+            w.z = dz;
+            w.n = nn / static_cast<R>(nc);
+            a.mv_wr[s] = w;
+            R2<R> wc;
+            wc.c = cn;
+            wc.s = static_cast<R>(tgt);
+            a.mvc_wr[s] = wc;
+            nbytes += 6 * rsz;
         }
         if (vip) {
             const long long v = push_vip(a.vip_out, a.cnt, a.list_wr, a.vip_cap);
@@ -1057,12 +1264,49 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
             }
         }
     }
-    // counters: packets active next step, packets moved this step
+    // the tile's tally (packets active next step, packets moved this step,
+    // bytes), summed over the marked tiles by k_hop_tally: no global atomics
     const unsigned long long nact = __popcll(__ballot(act));
-    const unsigned long long nupd = __popcll(__ballot(old_active));
+    const unsigned long long nupd = __popcll(__ballot(departed));
+    const unsigned long long wb = wave_sum_u64(nbytes);
     if (lane == 0) {
-        if (nact) atomicAdd(reinterpret_cast<unsigned long long*>(&a.cnt[kCntAct0 + a.act_wr]), nact);
-        if (nupd) atomicAdd(reinterpret_cast<unsigned long long*>(&a.cnt[kCntUpdates]), nupd);
+        s_tally[0][wave] = nact;
+        s_tally[1][wave] = nupd;
+        s_tally[2][wave] = wb;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const unsigned long long* v = s_tally[threadIdx.x];
+        a.part[3 * tile + threadIdx.x] = v[0] + v[1] + v[2] + v[3];
+    }
+}
+
+// Sums the tallies of the tiles that ran in the last forward step (all tiles
+// at hop 0, the marked ones otherwise); nothing if that step exited early.
+__global__ __launch_bounds__(1024) void k_hop_tally(long long* cnt, const unsigned long long* part, const int* hot,
+                                                    long long ntiles, int stamp, int hop0, int act_wr) {
+    __shared__ unsigned long long s[4][1024];
+    if (cnt[kCntRan] != stamp) return;
+    unsigned long long v[4] = {0, 0, 0, 0};
+    for (long long t = threadIdx.x; t < ntiles; t += 1024) {
+        if (!hop0 && hot[t] != stamp) continue;
+        v[0] += part[3 * t];
+        v[1] += part[3 * t + 1];
+        v[2] += part[3 * t + 2];
+        v[3] += 1;
+    }
+    for (int c = 0; c < 4; ++c) s[c][threadIdx.x] = v[c];
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int c = 0; c < 4; ++c) s[c][threadIdx.x] += s[c][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        cnt[kCntAct0 + act_wr] = static_cast<long long>(s[0][0]);
+        cnt[kCntUpdates] += static_cast<long long>(s[1][0]);
+        cnt[kCntBytes] += static_cast<long long>(s[2][0]);
+        cnt[kCntTiles] += static_cast<long long>(s[3][0]);
     }
 }
 

@@ -75,19 +75,26 @@ struct rt_ctx {
     double* ers = nullptr;
     std::vector<int> h_em_inst;
     double* E_src = nullptr;
-    // dynamic state
-    void* pk[2] = {nullptr, nullptr};
-    void* pc[2] = {nullptr, nullptr};
-    unsigned long long* cm[2] = {nullptr, nullptr};
-    unsigned char* tg[2] = {nullptr, nullptr};
-    void* dl[2] = {nullptr, nullptr};
-    unsigned char* nd[2] = {nullptr, nullptr};
+    // dynamic state: resting packets (in place), moving packets and delivery
+    // masks (by forward-step parity), work marks of the tiles
+    void* pk = nullptr;
+    void* pcl = nullptr;
+    unsigned long long* cm = nullptr;
+    void* mv[2] = {nullptr, nullptr};
+    void* mvc[2] = {nullptr, nullptr};
+    void* inbox[2] = {nullptr, nullptr};
+    int* hot[2] = {nullptr, nullptr};
+    unsigned long long* part = nullptr;  // per-tile tallies of a forward step
     unsigned int* rev_ik = nullptr;
     void* rev_v = nullptr;
     void* fwd_v = nullptr;
-    int tileT = 1;         // particles per forward-step workgroup
+    int tileT = 1;         // particles per forward-step workgroup (a power of two)
+    int lgT = 0;
+    long long ntiles = 0;
+    size_t inbox_bytes = 0;
     bool dl64 = false;     // delivery masks need 64 bits (N_RC * N_freq > 32)
-    int cur = 0;
+    long long serial = 0;  // stamp of hop 0 of the next RT step
+    long long last_stamp = -1;  // stamp of the last forward step that ran
     double *A = nullptr, *P = nullptr;
     long long* dep = nullptr;  // fixed-point deposits of virtual particles
     double* nrr[2] = {nullptr, nullptr};
@@ -194,10 +201,9 @@ void direction_set(int n, std::vector<double>& u) {
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 template <typename R, typename DT>
-rt_status launch_hop(rt_ctx* c, int hop, int base) {
+rt_status launch_hop(rt_ctx* c, int hop) {
     HopArgs<R, DT> a{};
     a.N = c->N;
-    a.B = c->B;
     a.G = c->G;
     a.nrc = c->nrc;
     a.nf = c->nf;
@@ -231,39 +237,49 @@ rt_status launch_hop(rt_ctx* c, int hop, int base) {
     a.wrc = c->rot + 9;
     a.wrcf = c->wrcf;
     a.dt = c->p.dt;
-    const int rd = (base + hop) & 1, wr = rd ^ 1;
-    a.pk_rd = static_cast<const Bin4<R>*>(c->pk[rd]);
-    a.pc_rd = static_cast<const R2<R>*>(c->pc[rd]);
-    a.tg_rd = c->tg[rd];
-    a.dl_rd = static_cast<const DT*>(c->dl[rd]);
-    a.nd_rd = c->nd[rd];
-    a.pk_wr = static_cast<Bin4<R>*>(c->pk[wr]);
-    a.pc_wr = static_cast<R2<R>*>(c->pc[wr]);
-    a.cm_wr = c->cm[wr];
-    a.tg_wr = c->tg[wr];
-    a.dl_wr = static_cast<DT*>(c->dl[wr]);
-    a.nd_wr = c->nd[wr];
+    a.lgT = c->lgT;
+    a.stamp = static_cast<int>(c->serial + hop);
+    a.ngb = c->ngb;
+    const int rd = (hop + 1) & 1, wr = hop & 1;
+    a.pk = static_cast<Bin4<R>*>(c->pk);
+    a.pcl = static_cast<R*>(c->pcl);
+    a.cm = c->cm;
+    a.mv_rd = static_cast<const Bin4<R>*>(c->mv[rd]);
+    a.mvc_rd = static_cast<const R2<R>*>(c->mvc[rd]);
+    a.in_rd = static_cast<const Inbox<DT>*>(c->inbox[rd]);
+    a.hot_rd = c->hot[hop & 1];
+    a.mv_wr = static_cast<Bin4<R>*>(c->mv[wr]);
+    a.mvc_wr = static_cast<R2<R>*>(c->mvc[wr]);
+    a.in_wr = static_cast<Inbox<DT>*>(c->inbox[wr]);
+    a.hot_wr = c->hot[(hop + 1) & 1];
     a.A = c->A;
     a.P = c->P;
     a.rec = c->rec;
     a.rec_next = c->rec_next;
-    a.head_rd = c->head[hop & 1];
-    a.head_reset = c->head[(hop + 1) & 1];
+    a.head = c->head[hop & 1];
     a.vip_out = c->vip[(hop + 1) & 1];
     a.vip_cap = c->vip_cap;
     a.list_wr = (hop + 1) & 1;
     a.cnt = c->cnt;
+    a.part = c->part;
     a.act_rd = hop & 1;
     a.act_wr = (hop + 1) & 1;
-    const size_t lds = static_cast<size_t>(c->tileT) * c->K * 4 * sizeof(R);
-    hipLaunchKernelGGL((k_hop<R, DT>), dim3(grid_for(c->N, c->tileT)), dim3(256), lds, c->stream, a);
+    const size_t lds = HopLds<R, DT>::bytes(c->tileT, c->K);
+    hipLaunchKernelGGL((k_hop<R, DT>), dim3(static_cast<unsigned>(c->ntiles)), dim3(256), lds, c->stream, a);
     HIPCHK(c, hipGetLastError());
     return RT_OK;
 }
 
-rt_status launch_hop_any(rt_ctx* c, int hop, int base) {
-    if (c->f32) return c->dl64 ? launch_hop<float, unsigned long long>(c, hop, base) : launch_hop<float, unsigned int>(c, hop, base);
-    return c->dl64 ? launch_hop<double, unsigned long long>(c, hop, base) : launch_hop<double, unsigned int>(c, hop, base);
+rt_status launch_tally(rt_ctx* c, int hop) {
+    hipLaunchKernelGGL(k_hop_tally, dim3(1), dim3(1024), 0, c->stream, c->cnt, c->part, c->hot[hop & 1], c->ntiles,
+                       static_cast<int>(c->serial + hop), hop == 0 ? 1 : 0, (hop + 1) & 1);
+    HIPCHK(c, hipGetLastError());
+    return RT_OK;
+}
+
+rt_status launch_hop_any(rt_ctx* c, int hop) {
+    if (c->f32) return c->dl64 ? launch_hop<float, unsigned long long>(c, hop) : launch_hop<float, unsigned int>(c, hop);
+    return c->dl64 ? launch_hop<double, unsigned long long>(c, hop) : launch_hop<double, unsigned int>(c, hop);
 }
 
 rt_status launch_vip(rt_ctx* c, int hop) {
@@ -301,6 +317,9 @@ rt_status launch_vip(rt_ctx* c, int hop) {
     a.rec_next = c->rec_next;
     a.head = c->head[hop & 1];
     a.rec_cap = c->rec_cap;
+    a.hot = c->hot[hop & 1];
+    a.stamp = static_cast<int>(c->serial + hop);
+    a.lgT = c->lgT;
     a.cnt = c->cnt;
     a.act_rd = hop & 1;
     a.act_wr = (hop + 1) & 1;
@@ -370,7 +389,14 @@ float elapsed(rt_ctx* c, size_t slot) {
 // One RT step (sections 2.1 and 2.2): rotations, emission, forward steps
 // until no packet is active, chemistry, ledger.
 rt_status one_step(rt_ctx* c, bool* hopcap) {
-    const int base = c->cur;
+    // stamps are 30-bit: restart them (and forget every old mark) long before they wrap
+    if (c->serial + c->p.max_hops + 2 >= (1ll << 30)) {
+        for (int b = 0; b < 2; ++b) {
+            HIPCHK(c, hipMemsetAsync(c->inbox[b], 0xff, c->inbox_bytes, c->stream));
+            TRY(fill_i32(c, c->hot[b], c->ntiles, -1));
+        }
+        c->serial = 0;
+    }
     // timing slots: 0 emission, 1 chemistry, 2 ledger, 3.. hops (vip then hop)
     TRY(fill_i32(c, c->head[0], c->N, -1));
     TRY(fill_i32(c, c->head[1], c->N, -1));
@@ -430,8 +456,9 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
     TRY(launch_vip(c, 0));
     TRY(time_end(c, 0));
     TRY(time_begin(c, 3));
-    TRY(launch_hop_any(c, 0, base));
+    TRY(launch_hop_any(c, 0));
     TRY(time_end(c, 3));
+    TRY(launch_tally(c, 0));
     // Forward steps are enqueued in batches between host checks of the device
     // counters.  Automatic batching starts with the previous step's count less
     // a margin, then goes one step at a time, so that almost no launch finds
@@ -448,8 +475,9 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
                 TRY(launch_vip(c, q));
                 TRY(time_end(c, 2 + 2 * q));
                 TRY(time_begin(c, 3 + 2 * q));
-                TRY(launch_hop_any(c, q, base));
+                TRY(launch_hop_any(c, q));
                 TRY(time_end(c, 3 + 2 * q));
+                TRY(launch_tally(c, q));
             }
             h = hend + 1;
         }
@@ -463,7 +491,9 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
             break;
         }
     }
-    c->cur = static_cast<int>((base + H + 1) & 1);
+    // stamps of this step were serial .. serial + h - 1 (launched forward steps)
+    c->last_stamp = c->serial + H;
+    c->serial += h;
     c->last_hops = H;
     // chemistry
     TRY(time_begin(c, 1));
@@ -507,7 +537,7 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
     la.nrr_prev = c->nrr[c->nrr_cur];
     la.xs = c->xs;
     la.rs = c->rs;
-    la.pk = c->pk[c->cur];
+    la.pk = c->pk;
     la.U = c->U_d;
     la.partial = c->partial;
     hipLaunchKernelGGL(k_ledger_partial, dim3(static_cast<unsigned>(c->n_chunks)), dim3(256), 0, c->stream, la);
@@ -600,10 +630,16 @@ rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, cons
     c->f32 = p->precision == RT_FP32;
     c->dl64 = c->G > 32;
     {
-        const size_t v4 = c->f32 ? 16 : 32;
+        // the forward step's LDS (at most 48 KiB) bounds the particles per tile
+        auto hop_lds = [&](int t) {
+            if (c->f32)
+                return c->dl64 ? HopLds<float, unsigned long long>::bytes(t, c->K) : HopLds<float, unsigned int>::bytes(t, c->K);
+            return c->dl64 ? HopLds<double, unsigned long long>::bytes(t, c->K) : HopLds<double, unsigned int>::bytes(t, c->K);
+        };
         int T = 256 / c->G;
-        while (T > 1 && static_cast<size_t>(T) * c->K * v4 > 48 * 1024) T /= 2;
+        while (T > 1 && hop_lds(T) > 48 * 1024) T /= 2;
         c->tileT = T;
+        while ((1 << c->lgT) < T) ++c->lgT;
     }
     c->rr_on = p->recomb_mode == RT_RR_TRANSPORT;
     const double cc = 1.0 - 2.0 / static_cast<double>(p->n_tc);
@@ -747,19 +783,24 @@ rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, cons
     HIPCHK(c, hipGetLastError());
     // bins and work buffers
     const size_t rsz = c->f32 ? sizeof(float) : sizeof(double);
+    c->ntiles = (N + c->tileT - 1) / c->tileT;
+    ITRY(dalloc(c, &c->pk, 4 * rsz * c->B));
+    ITRY(dalloc(c, &c->pcl, rsz * c->B));
+    ITRY(alloc_n(c, &c->cm, c->B));
+    HIPCHK(c, hipMemsetAsync(c->pk, 0, 4 * rsz * c->B, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->pcl, 0, rsz * c->B, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->cm, 0, 8 * c->B, c->stream));
     for (int b = 0; b < 2; ++b) {
-        ITRY(dalloc(c, &c->pk[b], 4 * rsz * c->B));
-        ITRY(dalloc(c, &c->pc[b], 2 * rsz * c->B));
-        ITRY(alloc_n(c, &c->cm[b], c->B));
-        ITRY(alloc_n(c, &c->tg[b], c->B));
-        ITRY(dalloc(c, &c->dl[b], (c->dl64 ? 8 : 4) * static_cast<size_t>(N * c->K)));
-        ITRY(alloc_n(c, &c->nd[b], N));
-        HIPCHK(c, hipMemsetAsync(c->pk[b], 0, 4 * rsz * c->B, c->stream));
-        HIPCHK(c, hipMemsetAsync(c->pc[b], 0, 2 * rsz * c->B, c->stream));
-        HIPCHK(c, hipMemsetAsync(c->cm[b], 0, 8 * c->B, c->stream));
-        HIPCHK(c, hipMemsetAsync(c->tg[b], 0, c->B, c->stream));
-        HIPCHK(c, hipMemsetAsync(c->dl[b], 0, (c->dl64 ? 8 : 4) * static_cast<size_t>(N * c->K), c->stream));
-        HIPCHK(c, hipMemsetAsync(c->nd[b], 0, N, c->stream));
+        ITRY(dalloc(c, &c->mv[b], 4 * rsz * c->B));
+        ITRY(dalloc(c, &c->mvc[b], 2 * rsz * c->B));
+        // inbox tags start all-ones: no stamp matches
+        c->inbox_bytes = (c->dl64 ? sizeof(Inbox<unsigned long long>) : sizeof(Inbox<unsigned int>)) *
+                         static_cast<size_t>(N * c->K);
+        ITRY(dalloc(c, &c->inbox[b], c->inbox_bytes));
+        HIPCHK(c, hipMemsetAsync(c->inbox[b], 0xff, c->inbox_bytes, c->stream));
+        ITRY(alloc_n(c, &c->hot[b], c->ntiles));
+        ITRY(fill_i32(c, c->hot[b], c->ntiles, -1));
+        if (b == 0) ITRY(alloc_n(c, &c->part, 3 * c->ntiles));
         ITRY(alloc_n(c, &c->nrr[b], N));
         ITRY(fill_f64(c, c->nrr[b], N, 0.0));
         ITRY(alloc_n(c, &c->head[b], N));
@@ -917,6 +958,7 @@ rt_status rt_step(rt_ctx* c, int32_t n_steps) {
     if (c->sticky) return RT_EDEVICE;
     if (n_steps < 0) return fail(c, RT_EINVAL, "n_steps < 0");
     for (int k = 0; k < 8; ++k) c->tm[k] = 0.0;
+    if (c->timing) HIPCHK(c, hipMemsetAsync(c->cnt + kCntBytes, 0, 2 * sizeof(long long), c->stream));
     bool hopcap = false;
     for (int s = 0; s < n_steps; ++s) {
         TRY(one_step(c, &hopcap));
@@ -959,9 +1001,9 @@ rt_status rt_get_bins(rt_ctx* c, double* N, double* dir, double* clock) {
     HIPCHK(c, hipMemcpy(inst_of.data(), c->inst_of, sizeof(int) * c->N, hipMemcpyDeviceToHost));
     if (c->f32) {
         std::vector<Bin4<float>> pk(B);
-        std::vector<float> pc(2 * B);
-        HIPCHK(c, hipMemcpy(pk.data(), c->pk[c->cur], sizeof(Bin4<float>) * B, hipMemcpyDeviceToHost));
-        HIPCHK(c, hipMemcpy(pc.data(), c->pc[c->cur], sizeof(float) * 2 * B, hipMemcpyDeviceToHost));
+        std::vector<float> pc(B);
+        HIPCHK(c, hipMemcpy(pk.data(), c->pk, sizeof(Bin4<float>) * B, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(pc.data(), c->pcl, sizeof(float) * B, hipMemcpyDeviceToHost));
         for (long long b = 0; b < B; ++b) {
             const int k = inst_of[b / c->G];
             if (N) N[b] = static_cast<double>(pk[b].n) * c->U[k];
@@ -970,13 +1012,13 @@ rt_status rt_get_bins(rt_ctx* c, double* N, double* dir, double* clock) {
                 dir[3 * b + 1] = pk[b].y;
                 dir[3 * b + 2] = pk[b].z;
             }
-            if (clock) clock[b] = static_cast<double>(pc[2 * b]) * c->p.dt;
+            if (clock) clock[b] = static_cast<double>(pc[b]) * c->p.dt;
         }
     } else {
         std::vector<Bin4<double>> pk(B);
-        std::vector<double> pc(2 * B);
-        HIPCHK(c, hipMemcpy(pk.data(), c->pk[c->cur], sizeof(Bin4<double>) * B, hipMemcpyDeviceToHost));
-        HIPCHK(c, hipMemcpy(pc.data(), c->pc[c->cur], sizeof(double) * 2 * B, hipMemcpyDeviceToHost));
+        std::vector<double> pc(B);
+        HIPCHK(c, hipMemcpy(pk.data(), c->pk, sizeof(Bin4<double>) * B, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(pc.data(), c->pcl, sizeof(double) * B, hipMemcpyDeviceToHost));
         for (long long b = 0; b < B; ++b) {
             if (N) N[b] = pk[b].n;
             if (dir) {
@@ -984,7 +1026,7 @@ rt_status rt_get_bins(rt_ctx* c, double* N, double* dir, double* clock) {
                 dir[3 * b + 1] = pk[b].y;
                 dir[3 * b + 2] = pk[b].z;
             }
-            if (clock) clock[b] = pc[2 * b];
+            if (clock) clock[b] = pc[b];
         }
     }
     return RT_OK;
@@ -1015,7 +1057,29 @@ rt_status rt_get_cone_masks(rt_ctx* c, uint64_t* mask) {
     if (!c || !mask) return RT_EINVAL;
     if (c->sticky) return RT_EDEVICE;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    HIPCHK(c, hipMemcpy(mask, c->cm[c->cur], sizeof(uint64_t) * c->B, hipMemcpyDeviceToHost));
+    // a mask is kept for every packet that became active; report those of the
+    // packets still active (in flight after the last forward step)
+    const long long B = c->B;
+    HIPCHK(c, hipMemcpy(mask, c->cm, sizeof(uint64_t) * B, hipMemcpyDeviceToHost));
+    const double lim = c->f32 ? 1.0 : c->p.dt;
+    std::vector<double> n(B), clk(B);
+    if (c->f32) {
+        std::vector<Bin4<float>> pk(B);
+        std::vector<float> pc(B);
+        HIPCHK(c, hipMemcpy(pk.data(), c->pk, sizeof(Bin4<float>) * B, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(pc.data(), c->pcl, sizeof(float) * B, hipMemcpyDeviceToHost));
+        for (long long b = 0; b < B; ++b) {
+            n[b] = pk[b].n;
+            clk[b] = pc[b];
+        }
+    } else {
+        std::vector<Bin4<double>> pk(B);
+        HIPCHK(c, hipMemcpy(pk.data(), c->pk, sizeof(Bin4<double>) * B, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(clk.data(), c->pcl, sizeof(double) * B, hipMemcpyDeviceToHost));
+        for (long long b = 0; b < B; ++b) n[b] = pk[b].n;
+    }
+    for (long long b = 0; b < B; ++b)
+        if (!(n[b] > 0.0 && clk[b] < lim)) mask[b] = 0;
     return RT_OK;
 }
 
@@ -1035,26 +1099,25 @@ rt_status rt_set_timing(rt_ctx* c, int32_t on) {
 
 rt_status rt_get_timing(rt_ctx* c, double* out, int32_t n) {
     if (!c || !out || n < 0) return RT_EINVAL;
-    const double rsz = c->f32 ? 4.0 : 8.0;
-    // algorithmic bytes of one forward-step launch, counting only what every
-    // launch moves whatever the activity: each slot's packet and {clock, N/n_c}
-    // read and written, its cone mask and downstream cone written; per particle,
-    // for each incoming edge the packed edge word, the sender's delivery word
-    // and flag read, its own delivery words written, and its absorbed and
-    // passing photons read and written.  Packets of moving senders and the
-    // neighbour offsets of tiles with moving packets come on top.
-    const double dsz = c->dl64 ? 8.0 : 4.0;
-    const double per_slot = 2.0 * (6.0 * rsz) + 8.0 + 1.0;
-    const double per_part = c->K * (5.0 + 2.0 * dsz) + 2.0 * 2.0 * 8.0 * c->nf;
-    const double bytes = per_slot * static_cast<double>(c->B) + per_part * static_cast<double>(c->N);
-    double v[8] = {c->tm[0], c->tm[1], c->tm[2], c->tm[3], c->tm[4], c->tm[5], bytes, 0.0};
-    for (int k = 0; k < n && k < 8; ++k) out[k] = v[k];
+    if (c->sticky) return RT_EDEVICE;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    long long h[kCntN];
+    HIPCHK(c, hipMemcpy(h, c->cnt, sizeof(h), hipMemcpyDeviceToHost));
+    // Dense model of one forward step, for comparison: every slot's packet and
+    // clock read and written; per edge its sender word and inbox read and its
+    // inbox written; per particle and bin A and P read and written.
+    const double rsz = c->f32 ? 4.0 : 8.0, isz = c->dl64 ? 16.0 : 8.0;
+    const double dense = 2.0 * 5.0 * rsz * static_cast<double>(c->B) +
+                         (c->K * (4.0 + 2.0 * isz) + 2.0 * 2.0 * 8.0 * c->nf) * static_cast<double>(c->N);
+    double v[9] = {c->tm[0], c->tm[1], c->tm[2], c->tm[3], c->tm[4], c->tm[5], static_cast<double>(h[kCntBytes]),
+                   static_cast<double>(h[kCntTiles]), dense};
+    for (int k = 0; k < n && k < 9; ++k) out[k] = v[k];
     return RT_OK;
 }
 
 namespace {
 struct BlobHeader {
-    long long magic, N, B, nf, n_inst, f32, step, cur, nrr_cur;
+    long long magic, N, B, nf, n_inst, f32, step, serial, last_hops;
 };
 }  // namespace
 
@@ -1062,7 +1125,7 @@ rt_status rt_get_state_blob(rt_ctx* c, void* blob, size_t* bytes) {
     if (!c || !bytes) return RT_EINVAL;
     if (c->sticky) return RT_EDEVICE;
     const size_t rsz = c->f32 ? 4 : 8;
-    const size_t need = sizeof(BlobHeader) + 6 * rsz * c->B + 3 * 8 * c->N + 8 * 5 * c->n_inst * c->nf +
+    const size_t need = sizeof(BlobHeader) + 5 * rsz * c->B + 3 * 8 * c->N + 8 * 5 * c->n_inst * c->nf +
                         8 * c->n_inst * c->nf + 8 * kCntN;
     if (!blob) {
         *bytes = need;
@@ -1071,13 +1134,16 @@ rt_status rt_get_state_blob(rt_ctx* c, void* blob, size_t* bytes) {
     if (*bytes < need) return fail(c, RT_ESTATE, "blob too small");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     char* q = static_cast<char*>(blob);
-    BlobHeader hd{0x54524150ll, c->N, c->B, c->nf, c->n_inst, c->f32, c->step, 0, 0};
+    // the stamp counter and the last step's forward-step count travel too, so
+    // that a restored context numbers and batches its forward steps as the
+    // original would have
+    BlobHeader hd{0x54524150ll, c->N, c->B, c->nf, c->n_inst, c->f32, c->step, c->serial, c->last_hops};
     std::memcpy(q, &hd, sizeof hd);
     q += sizeof hd;
-    HIPCHK(c, hipMemcpy(q, c->pk[c->cur], 4 * rsz * c->B, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(q, c->pk, 4 * rsz * c->B, hipMemcpyDeviceToHost));
     q += 4 * rsz * c->B;
-    HIPCHK(c, hipMemcpy(q, c->pc[c->cur], 2 * rsz * c->B, hipMemcpyDeviceToHost));
-    q += 2 * rsz * c->B;
+    HIPCHK(c, hipMemcpy(q, c->pcl, rsz * c->B, hipMemcpyDeviceToHost));
+    q += rsz * c->B;
     HIPCHK(c, hipMemcpy(q, c->xHI, 8 * c->N, hipMemcpyDeviceToHost));
     q += 8 * c->N;
     HIPCHK(c, hipMemcpy(q, c->T, 8 * c->N, hipMemcpyDeviceToHost));
@@ -1107,12 +1173,11 @@ rt_status rt_set_state_blob(rt_ctx* c, const void* blob, size_t bytes) {
     const size_t rsz = c->f32 ? 4 : 8;
     const char* q = static_cast<const char*>(blob) + sizeof hd;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    c->cur = 0;
     c->nrr_cur = 0;
-    HIPCHK(c, hipMemcpy(c->pk[0], q, 4 * rsz * c->B, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->pk, q, 4 * rsz * c->B, hipMemcpyHostToDevice));
     q += 4 * rsz * c->B;
-    HIPCHK(c, hipMemcpy(c->pc[0], q, 2 * rsz * c->B, hipMemcpyHostToDevice));
-    q += 2 * rsz * c->B;
+    HIPCHK(c, hipMemcpy(c->pcl, q, rsz * c->B, hipMemcpyHostToDevice));
+    q += rsz * c->B;
     HIPCHK(c, hipMemcpy(c->xHI, q, 8 * c->N, hipMemcpyHostToDevice));
     q += 8 * c->N;
     HIPCHK(c, hipMemcpy(c->T, q, 8 * c->N, hipMemcpyHostToDevice));
@@ -1125,6 +1190,12 @@ rt_status rt_set_state_blob(rt_ctx* c, const void* blob, size_t bytes) {
     q += 8 * c->n_inst * c->nf;
     HIPCHK(c, hipMemcpy(c->cnt, q, 8 * kCntN, hipMemcpyHostToDevice));
     c->step = hd.step;
+    c->serial = hd.serial;
+    c->last_hops = hd.last_hops;
+    for (int b = 0; b < 2; ++b) {  // forget the marks of this context's own earlier steps
+        HIPCHK(c, hipMemsetAsync(c->inbox[b], 0xff, c->inbox_bytes, c->stream));
+        TRY(fill_i32(c, c->hot[b], c->ntiles, -1));
+    }
     if (c->f32) {
         hipLaunchKernelGGL(k_kappa_init, dim3(grid_for(c->N, 256)), dim3(256), 0, c->stream, c->N, c->xHI, c->nH,
                            c->L_d, c->inst_of, c->kappa);

@@ -231,9 +231,10 @@ class Context:
         self._check(load().rt_set_timing(self.h, 1 if on else 0))
 
     def timing(self):
-        out = np.zeros(8)
-        self._check(load().rt_get_timing(self.h, _p(out, C.c_double), 8))
-        keys = ["hop_ms", "hop_launches", "vip_ms", "chem_ms", "emit_ms", "ledger_ms", "hop_bytes"]
+        out = np.zeros(9)
+        self._check(load().rt_get_timing(self.h, _p(out, C.c_double), 9))
+        keys = ["hop_ms", "hop_launches", "vip_ms", "chem_ms", "emit_ms", "ledger_ms", "hop_bytes_total",
+                "hop_tiles_total", "dense_bytes_per_hop"]
         return {k: float(out[i]) for i, k in enumerate(keys)}
 
     def get_blob(self):
