@@ -785,7 +785,8 @@ struct HopLds {
     static constexpr int kPairs = sizeof(R) == 4 ? 512 : 256;   // pairs gathered at a time
     static constexpr size_t ik = 0;
     static constexpr size_t dl = ik + 4 * kEdges;
-    static constexpr size_t nd = dl + sizeof(DT) * kEdges;
+    static constexpr size_t eff = dl + sizeof(DT) * kEdges;
+    static constexpr size_t nd = eff + sizeof(DT) * kEdges;
     static constexpr size_t desc = (nd + kEdges + 31) / 32 * 32;
     static constexpr size_t val = desc + 4 * kPairs;
     static constexpr size_t part = val + 7 * sizeof(R) * kPairs;
@@ -905,6 +906,7 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
     if (!a.hop0) {
         unsigned int* e_ik = reinterpret_cast<unsigned int*>(lds + L::ik);
         DT* e_dl = reinterpret_cast<DT*>(lds + L::dl);
+        DT* e_ef = reinterpret_cast<DT*>(lds + L::eff);
         unsigned char* e_nd = lds + L::nd;
         unsigned int* pdesc = reinterpret_cast<unsigned int*>(lds + L::desc);
         R* pval = reinterpret_cast<R*>(lds + L::val);  // [7][kP]
@@ -924,38 +926,81 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
         const long long my0 = valid ? a.rev_off[j] : 0, my1 = valid ? a.rev_off[j + 1] : 0;
         const unsigned int prev = static_cast<unsigned int>(a.stamp - 1);
         const DT gm = static_cast<DT>(nrc >= 8 * static_cast<int>(sizeof(DT)) ? ~DT(0) : ((DT(1) << nrc) - DT(1)));
+        const int gbase_s = lane & ~(G - 1);
+        const unsigned long long gmask_s = G >= 64 ? ~0ull : ((1ull << G) - 1ull);
         for (long long cb = e_t0; cb < e_t1; cb += L::kEdges) {
             __syncthreads();
             const long long ne = (e_t1 - cb < L::kEdges) ? e_t1 - cb : L::kEdges;
+            bool snd = false;
             for (long long t = threadIdx.x; t < ne; t += 256) {
                 const Inbox<DT> w = a.in_rd[cb + t];
+                const DT m = (w.tag >> 1) == prev ? w.mask : DT(0);
+                const bool nd = (w.tag & 1u) != 0;
+                // effective mask: bit (nu, r) set if the edge may bring a packet
+                // into reception cone r; a sender with packets arriving off
+                // their own index may reach any cone of a bin it delivers in
+                DT ef = m;
+                if (nd && m != DT(0)) {
+                    ef = DT(0);
+                    for (int f = 0; f < a.nf; ++f)
+                        if ((m >> (f * nrc)) & gm) ef |= gm << (f * nrc);
+                    snd = true;
+                }
                 e_ik[t] = a.rev_ik[cb + t];
-                e_dl[t] = (w.tag >> 1) == prev ? w.mask : DT(0);
-                e_nd[t] = static_cast<unsigned char>(w.tag & 1u);
+                e_dl[t] = m;
+                e_ef[t] = ef;
+                e_nd[t] = static_cast<unsigned char>(nd);
                 nbytes += sizeof(Inbox<DT>) + 4;
             }
-            __syncthreads();
+            const bool any_nd = __syncthreads_or(snd);
             const long long lo = my0 > cb ? my0 : cb;
             const long long hi = my1 < cb + ne ? my1 : cb + ne;
+            // hit mask of this slot over a segment of up to 64 of its particle's
+            // edges: the particle's lanes read its edges G at a time and one
+            // ballot per mask bit hands each slot lane its bit (a transpose)
+            int nseg = hi > lo ? static_cast<int>((hi - lo + 63) >> 6) : 0;
+            for (int off = 32; off > 0; off >>= 1) nseg = max(nseg, __shfl_xor(nseg, off, 64));
+            auto seg_hit = [&](int sg) {
+                const long long sb = lo + 64ll * sg;
+                const int len = static_cast<int>(hi - sb < 0 ? 0 : (hi - sb < 64 ? hi - sb : 64));
+                unsigned long long h = 0;
+                for (int k = 0; k * G < 64; ++k) {
+                    const int idx = k * G + o;
+                    const DT v = idx < len ? e_ef[sb - cb + idx] : DT(0);
+                    for (int b = 0; b < G; ++b) {
+                        const unsigned long long bal = __ballot(((v >> b) & DT(1)) != DT(0));
+                        if (b == o) h |= ((bal >> gbase_s) & gmask_s) << (k * G);
+                    }
+                }
+                return h;
+            };
             // this slot's arriving (edge, packet) pairs, in edge order
             auto each_pair = [&](auto&& f) {
-                for (long long e = lo; e < hi; ++e) {
-                    const int t = static_cast<int>(e - cb);
-                    DT m = (e_dl[t] >> (nu * nrc)) & gm;
-                    if (m == DT(0)) continue;
-                    if (!e_nd[t]) {
-                        if (((m >> r) & DT(1)) == DT(0)) continue;
-                        m = DT(1) << r;
-                    }
-                    while (m != DT(0)) {
-                        const int pp = static_cast<int>(__builtin_ctzll(static_cast<unsigned long long>(m)));
-                        m &= m - DT(1);
-                        f(t, pp);
+                for (int sg = 0; sg < nseg; ++sg) {
+                    unsigned long long h = seg_hit(sg);
+                    while (h) {
+                        const int u = __builtin_ctzll(h);
+                        h &= h - 1ull;
+                        const int t = static_cast<int>(lo + 64ll * sg - cb) + u;
+                        if (!e_nd[t]) {
+                            f(t, r);
+                            continue;
+                        }
+                        DT m = (e_dl[t] >> (nu * nrc)) & gm;
+                        while (m != DT(0)) {
+                            const int pp = static_cast<int>(__builtin_ctzll(static_cast<unsigned long long>(m)));
+                            m &= m - DT(1);
+                            f(t, pp);
+                        }
                     }
                 }
             };
             int np = 0;
-            each_pair([&](int, int) { ++np; });
+            if (any_nd) {
+                each_pair([&](int, int) { ++np; });
+            } else {
+                for (int sg = 0; sg < nseg; ++sg) np += __popcll(seg_hit(sg));
+            }
             // exclusive prefix sum over the workgroup
             int incl = np;
             for (int off = 1; off < 64; off <<= 1) {
@@ -971,7 +1016,8 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
             }
             const int off0 = wbase + incl - np;
             for (int base = 0; base < M; base += kP) {
-                if (np) {
+                {
+                    // every lane takes part: the transpose needs all of a particle's lanes
                     int q = off0;
                     each_pair([&](int t, int pp) {
                         if (q >= base && q < base + kP)
@@ -1162,6 +1208,7 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
     unsigned long long cmw = 0;
     int tgt = r;
     if (act) {
+#pragma unroll 8
         for (int k = 0; k < K; ++k) {
             const V4 w = fj[k];
             bool in;
