@@ -33,6 +33,7 @@ enum : int {
     kCntBytes = 12,   // algorithmic bytes moved by forward steps (for the roofline)
     kCntTiles = 13,   // forward-step tiles processed
     kCntRan = 14,     // stamp of the last forward step that ran
+    kCntDeep = 15,    // virtual particles of this forward step that landed inside their box
     kCntN = 16
 };
 enum : long long { kFlagHopCap = 1, kFlagVipOverflow = 2, kFlagRecOverflow = 4, kFlagNonFinite = 8 };
@@ -463,75 +464,151 @@ struct VipArgs {
     long long rec_cap;
     int* hot;        // tiles that receive records in this forward step
     int stamp, lgT;
+    Vip* deep;       // virtual particles that landed inside their box, with their points
+    double* deep_x;
     long long* cnt;
     int act_rd, act_wr, list_rd, list_wr;
 };
 
-// Virtual particles (section 2.1): one wavefront per packet with an empty
-// cone.  The particle is drawn uniformly in the cone inside the ball of radius
-// h around the origin (64 rejection attempts per round, the lowest accepted
-// attempt wins, as if drawn one by one); outside the box the packet escapes;
-// otherwise it takes SPH-interpolated properties from its own N_ngb
-// neighbours (one lane each), the leg's absorptions go to those neighbours in
-// proportion to W_k N_H,k / n_H,k, and it forwards the rest into its own
-// transmission cone (chaining up to max_depth).
-__global__ __launch_bounds__(256) void k_vip(VipArgs a) {
+// Virtual particles (section 2.1).  The particle is drawn uniformly in the
+// cone inside the ball of radius h around the origin (rejection from the cube
+// [-1,1]^3, Philox draws numbered by attempt, the lowest accepted attempt
+// wins); outside the box the packet escapes; otherwise it takes
+// SPH-interpolated properties from its own N_ngb neighbours, the leg's
+// absorptions go to those neighbours in proportion to W_k N_H,k / n_H,k, and
+// it forwards the rest into its own transmission cone (chaining up to
+// max_depth).  k_vip_sample draws the first point of every chain, one lane
+// each, and settles those that escape; the rest go on to k_vip_chain.
+
+// One lane, attempts in order.  False if no attempt is accepted.
+__device__ inline bool vip_draw_lane(const VipArgs& a, const Vip& q, int depth, double p[3]) {
+    const double* ecs = (q.ec >= 0 && depth == 1) ? a.ecd + 3 * (static_cast<long long>(q.ec) * a.nec) : nullptr;
+    for (uint32_t att = 0; att < kVipAttempts; ++att) {
+        double u[4];
+        uniforms4(a.seed, q.tag, att, a.step, q.ida, q.idb | static_cast<uint32_t>(depth), u);
+        if (!(u[0] * u[0] + u[1] * u[1] + u[2] * u[2] <= 1.0)) continue;
+        if (ecs ? nearest_direction(ecs, a.nec, u[0], u[1], u[2]) != q.ek
+                : !in_cone(u[0], u[1], u[2], q.d[0], q.d[1], q.d[2], a.c2))
+            continue;
+        p[0] = u[0];
+        p[1] = u[1];
+        p[2] = u[2];
+        return true;
+    }
+    return false;
+}
+
+__global__ __launch_bounds__(256) void k_vip_sample(VipArgs a) {
+    const long long gid = blockIdx.x * 256LL + threadIdx.x;
+    const long long stride = gridDim.x * 256LL;
+    if (!a.hop0) {
+        // Once one forward step has found nothing to move, every later launch
+        // of this step must exit: the ping-pong counters it would read are stale.
+        if (a.cnt[kCntDone] != 0 || a.cnt[kCntAct0 + a.act_rd] == 0 || a.hop > a.max_hops) {
+            if (gid == 0) a.cnt[kCntDone] = 1;
+            return;
+        }
+    }
+    long long n = a.cnt[kCntVipCnt0 + a.list_rd];
+    if (n > a.vip_cap) n = a.vip_cap;
+    if (gid == 0) {
+        a.cnt[kCntAct0 + a.act_wr] = 0;
+        a.cnt[kCntVipCnt0 + a.list_wr] = 0;
+        a.cnt[kCntVips] += n;  // the first leg of every chain
+    }
+    const int lane = threadIdx.x & 63;
+    for (long long v = gid; v < n; v += stride) {
+        const Vip q = a.list[v];
+        double* X = q.xr_emis ? a.exs : a.xs;
+        double* Rm = q.xr_emis ? a.ers : a.rs;
+        const double* bx = a.box + 6 * q.inst;
+        double p[3];
+        bool inside = false;
+        double xv[3] = {0.0, 0.0, 0.0};
+        if (!vip_draw_lane(a, q, 1, p)) {
+            Rm[q.xr] += q.N;
+        } else {
+            xv[0] = q.x[0] + q.h * p[0];
+            xv[1] = q.x[1] + q.h * p[1];
+            xv[2] = q.x[2] + q.h * p[2];
+            if (xv[0] < bx[0] || xv[0] > bx[3] || xv[1] < bx[1] || xv[1] > bx[4] || xv[2] < bx[2] || xv[2] > bx[5])
+                X[q.xr] += q.N;
+            else
+                inside = true;
+        }
+        // append the inside ones, one atomic per wavefront
+        const unsigned long long b = __ballot(inside);
+        if (b) {
+            const int leader = __ffsll(static_cast<long long>(__ballot(true))) - 1;
+            long long base = 0;
+            if (lane == leader) base = atomicAdd(reinterpret_cast<unsigned long long*>(&a.cnt[kCntDeep]), static_cast<unsigned long long>(__popcll(b)));
+            base = __shfl(base, leader, 64);
+            if (inside) {
+                const long long d = base + __popcll(b & ((1ull << lane) - 1ull));
+                if (d < a.vip_cap) {
+                    a.deep[d] = q;
+                    a.deep_x[3 * d] = xv[0];
+                    a.deep_x[3 * d + 1] = xv[1];
+                    a.deep_x[3 * d + 2] = xv[2];
+                } else {
+                    atomicOr(reinterpret_cast<unsigned long long*>(&a.cnt[kCntFlags]), static_cast<unsigned long long>(kFlagVipOverflow));
+                }
+            }
+        }
+    }
+}
+
+// One wavefront per chain that landed inside its box: its neighbours (one
+// lane each), the leg, and further legs if the cone is empty again (their
+// points drawn by the whole wavefront, 64 attempts at a time).
+__global__ __launch_bounds__(256) void k_vip_chain(VipArgs a) {
     __shared__ WaveKnn lds[4];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const long long gw = blockIdx.x * 4LL + wv;
     const long long nw = gridDim.x * 4LL;
-    if (!a.hop0) {
-        // Once one forward step has found nothing to move, every later launch
-        // of this step must exit: the ping-pong counters it would read are stale.
-        if (a.cnt[kCntDone] != 0 || a.cnt[kCntAct0 + a.act_rd] == 0 || a.hop > a.max_hops) {
-            if (gw == 0 && lane == 0) a.cnt[kCntDone] = 1;
-            return;
-        }
-    }
-    if (gw == 0 && lane == 0) {
-        a.cnt[kCntAct0 + a.act_wr] = 0;
-        a.cnt[kCntVipCnt0 + a.list_wr] = 0;
-    }
-    long long n = a.cnt[kCntVipCnt0 + a.list_rd];
+    long long n = a.cnt[kCntDeep];
     if (n > a.vip_cap) n = a.vip_cap;
     WaveKnn& L = lds[wv];
     const int K = a.K;
     for (long long v = gw; v < n; v += nw) {
-        Vip q = a.list[v];
+        Vip q = a.deep[v];
         const double* bx = a.box + 6 * q.inst;
         double* X = q.xr_emis ? a.exs : a.xs;
         double* Rm = q.xr_emis ? a.ers : a.rs;
         const GridInfo g = a.grid[q.inst];
+        double xv[3] = {a.deep_x[3 * v], a.deep_x[3 * v + 1], a.deep_x[3 * v + 2]};
         for (int depth = 1;; ++depth) {
-            if (lane == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&a.cnt[kCntVips]), 1ull);
-            const double* ecs = (q.ec >= 0 && depth == 1) ? a.ecd + 3 * (static_cast<long long>(q.ec) * a.nec) : nullptr;
-            double p0 = 0.0, p1 = 0.0, p2 = 0.0;
-            bool found = false;
-            for (uint32_t base = 0; base < kVipAttempts; base += 64) {
-                double u[4];
-                uniforms4(a.seed, q.tag, base + lane, a.step, q.ida, q.idb | static_cast<uint32_t>(depth), u);
-                bool ok = u[0] * u[0] + u[1] * u[1] + u[2] * u[2] <= 1.0;
-                if (ok) ok = ecs ? nearest_direction(ecs, a.nec, u[0], u[1], u[2]) == q.ek
-                                 : in_cone(u[0], u[1], u[2], q.d[0], q.d[1], q.d[2], a.c2);
-                const unsigned long long b = __ballot(ok);
-                if (b) {
-                    const int f = __ffsll(static_cast<long long>(b)) - 1;
-                    p0 = __shfl(u[0], f, 64);
-                    p1 = __shfl(u[1], f, 64);
-                    p2 = __shfl(u[2], f, 64);
-                    found = true;
+            if (depth > 1) {
+                if (lane == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&a.cnt[kCntVips]), 1ull);
+                double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+                bool found = false;
+                for (uint32_t base = 0; base < kVipAttempts; base += 64) {
+                    double u[4];
+                    uniforms4(a.seed, q.tag, base + lane, a.step, q.ida, q.idb | static_cast<uint32_t>(depth), u);
+                    bool ok = u[0] * u[0] + u[1] * u[1] + u[2] * u[2] <= 1.0;
+                    if (ok) ok = in_cone(u[0], u[1], u[2], q.d[0], q.d[1], q.d[2], a.c2);
+                    const unsigned long long b = __ballot(ok);
+                    if (b) {
+                        const int f = __ffsll(static_cast<long long>(b)) - 1;
+                        p0 = __shfl(u[0], f, 64);
+                        p1 = __shfl(u[1], f, 64);
+                        p2 = __shfl(u[2], f, 64);
+                        found = true;
+                        break;
+                    }
+                }
+                if (!found) {
+                    if (lane == 0) Rm[q.xr] += q.N;
                     break;
                 }
-            }
-            if (!found) {
-                if (lane == 0) Rm[q.xr] += q.N;
-                break;
-            }
-            const double xv[3] = {q.x[0] + q.h * p0, q.x[1] + q.h * p1, q.x[2] + q.h * p2};
-            if (xv[0] < bx[0] || xv[0] > bx[3] || xv[1] < bx[1] || xv[1] > bx[4] || xv[2] < bx[2] || xv[2] > bx[5]) {
-                if (lane == 0) X[q.xr] += q.N;
-                break;
+                xv[0] = q.x[0] + q.h * p0;
+                xv[1] = q.x[1] + q.h * p1;
+                xv[2] = q.x[2] + q.h * p2;
+                if (xv[0] < bx[0] || xv[0] > bx[3] || xv[1] < bx[1] || xv[1] > bx[4] || xv[2] < bx[2] || xv[2] > bx[5]) {
+                    if (lane == 0) X[q.xr] += q.N;
+                    break;
+                }
             }
             if (!knn_wave(g, a.cell_start, a.cell_idx, a.pos, xv[0], xv[1], xv[2], -1, K, L, lane)) {
                 // candidate buffer overflow (very clustered cells): serial query on one lane
@@ -837,7 +914,8 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
             a.cnt[kCntHops] += 1;
             a.cnt[kCntHopsStep] += 1;
         }
-        a.cnt[kCntRec] = 0;  // records of this step were all linked before launch
+        a.cnt[kCntRec] = 0;   // records of this step were all linked before launch
+        a.cnt[kCntDeep] = 0;  // and its virtual particles all handled
         a.cnt[kCntRan] = a.stamp;
     }
     const long long tile = xcd_block(blockIdx.x, gridDim.x);
@@ -875,6 +953,19 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
     Bin4<R> q0 = {};
     R c0 = 0;
     bool have_stay = false, departed = false;
+    // everything the slot reads of its own particle, issued up front
+    const long long ia = j * a.nf + nu;
+    R flo = 0;
+    int hd = -1;
+    double A0 = 0.0, P0 = 0.0;
+    if (valid) {
+        flo = a.floor_b[j];
+        hd = a.head[j];
+        if (r == 0) {
+            A0 = a.A[ia];
+            P0 = a.P[ia];
+        }
+    }
     if (valid) {
         q0 = a.pk[s];
         c0 = a.pcl[s];
@@ -929,7 +1020,6 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
         const int gbase_s = lane & ~(G - 1);
         const unsigned long long gmask_s = G >= 64 ? ~0ull : ((1ull << G) - 1ull);
         for (long long cb = e_t0; cb < e_t1; cb += L::kEdges) {
-            __syncthreads();
             const long long ne = (e_t1 - cb < L::kEdges) ? e_t1 - cb : L::kEdges;
             bool snd = false;
             for (long long t = threadIdx.x; t < ne; t += 256) {
@@ -1092,14 +1182,12 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
                     acc_add(acc, pval[u], pval[kP + u], pval[2 * kP + u], pval[3 * kP + u], pval[4 * kP + u]);
                     ++narr;
                 }
-                __syncthreads();
+                if (base + kP < M || cb + L::kEdges < e_t1) __syncthreads();  // the LDS is reused
             }
         }
     }
-    int hd = -1;
     if (valid) {
         // records of emission and virtual particles, in key order
-        hd = a.head[j];
         if (hd >= 0) {
             unsigned long long last = 0;
             bool first = true;
@@ -1167,7 +1255,7 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
         }
     }
     bool floored = false;
-    if (valid && nn > R(0) && nn < a.floor_b[j]) {
+    if (valid && nn > R(0) && nn < flo) {
         sum_add(asum, aerr, nn);
         nn = 0;
         dx = dy = dz = cn = 0;
@@ -1177,9 +1265,8 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
     const R ag = group_sum(asum + aerr, nrc);
     const R pg = group_sum(psum + perr, nrc);
     if (valid && r == 0 && (ag != R(0) || pg != R(0))) {
-        const long long ia = j * a.nf + nu;
-        a.A[ia] += static_cast<double>(ag) * U;
-        a.P[ia] += static_cast<double>(pg) * U;
+        a.A[ia] = A0 + static_cast<double>(ag) * U;
+        a.P[ia] = P0 + static_cast<double>(pg) * U;
         nbytes += 32;
     }
     // next forward step: cone members and downstream reception cone.  The

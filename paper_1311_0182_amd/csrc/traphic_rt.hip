@@ -101,6 +101,8 @@ struct rt_ctx {
     int nrr_cur = 0;
     double *xs = nullptr, *rs = nullptr;
     Vip* vip[2] = {nullptr, nullptr};
+    Vip* deep = nullptr;        // chains that landed inside their box, and their points
+    double* deep_x = nullptr;
     long long vip_cap = 0;
     Rec* rec = nullptr;
     int* rec_next = nullptr;
@@ -320,12 +322,16 @@ rt_status launch_vip(rt_ctx* c, int hop) {
     a.hot = c->hot[hop & 1];
     a.stamp = static_cast<int>(c->serial + hop);
     a.lgT = c->lgT;
+    a.deep = c->deep;
+    a.deep_x = c->deep_x;
     a.cnt = c->cnt;
     a.act_rd = hop & 1;
     a.act_wr = (hop + 1) & 1;
     a.list_rd = hop & 1;
     a.list_wr = (hop + 1) & 1;
-    hipLaunchKernelGGL(k_vip, dim3(1024), dim3(256), 0, c->stream, a);
+    const unsigned nsb = static_cast<unsigned>(std::min<long long>(1024, (c->vip_cap + 255) / 256));
+    hipLaunchKernelGGL(k_vip_sample, dim3(nsb), dim3(256), 0, c->stream, a);
+    hipLaunchKernelGGL(k_vip_chain, dim3(1024), dim3(256), 0, c->stream, a);
     HIPCHK(c, hipGetLastError());
     return RT_OK;
 }
@@ -339,6 +345,7 @@ __global__ void k_step_reset(long long* cnt) {
         cnt[kCntRec] = 0;
         cnt[kCntHopsStep] = 0;
         cnt[kCntDone] = 0;
+        cnt[kCntDeep] = 0;
         cnt[kCntSteps] += 1;
     }
 }
@@ -819,6 +826,8 @@ rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, cons
     c->rec_cap = p->record_capacity > 0 ? p->record_capacity : std::max<long long>(1 << 20, c->vip_cap * 4);
     if (c->rec_cap >= (1ll << 31)) c->rec_cap = (1ll << 31) - 1;
     for (int b = 0; b < 2; ++b) ITRY(alloc_n(c, &c->vip[b], c->vip_cap));
+    ITRY(alloc_n(c, &c->deep, c->vip_cap));
+    ITRY(alloc_n(c, &c->deep_x, 3 * c->vip_cap));
     ITRY(alloc_n(c, &c->rec, c->rec_cap));
     ITRY(alloc_n(c, &c->rec_next, c->rec_cap));
     ITRY(alloc_n(c, &c->cnt, kCntN));
