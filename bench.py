@@ -140,7 +140,8 @@ def main():
     avg_ms = tm["hop_ms"] / launches
     bytes_per_launch = tm["hop_bytes_total"] / launches
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    n_tiles = -(-int(cfg["pos"].shape[0]) // 16)
+    G = cfg["params"]["n_rc"] * cfg["params"]["n_freq"]
+    n_tiles = -(-int(cfg["pos"].shape[0]) // max(1, 64 // G))  # one wavefront of slots per tile
     out = {
         "metric": "particle-packet updates/s per RT step, FP32-batched vs FP64 at x_HI err<=1e-3",
         "value": value,

@@ -239,24 +239,30 @@ __device__ inline double knn_query(const GridInfo& g, const int* __restrict__ ce
 }
 
 // ---------------------------------------------------------------------------
-// Wavefront-cooperative exact kNN.  The 64 lanes scan the cells of one
-// Chebyshev shell at a time and append candidates (d^2, index) to an LDS
-// buffer.  Once there are at least K, the K-th smallest pair in (d^2, index)
-// order is found by bisection on the bits of d^2 (non-negative doubles order
-// like their bit patterns), counting with one ballot per register slot; the
-// search stops when that distance cannot be beaten by unvisited cells, and
-// otherwise the buffer is cut to the K best and later shells only add
-// candidates no farther than the current K-th.  Same result as the serial
-// query (the K smallest pairs are unique).
+// Wavefront-cooperative exact kNN.  Shell by Chebyshev shell of grid cells,
+// the 64 lanes list the shell's cells with their particle ranges (four cells
+// per lane per round, loads issued together), a prefix sum over the ranges
+// numbers the candidates, and the lanes take four candidates each per round
+// (index and position loads issued together), appending (d^2, index) to an
+// LDS buffer.  Once there are at least K, the K-th smallest pair in
+// (d^2, index) order is found by bisection on the bits of d^2 (non-negative
+// doubles order like their bit patterns), counting with one ballot per
+// register slot; the search stops when that distance cannot be beaten by
+// unvisited cells, and otherwise the buffer is cut to the K best and later
+// shells only add candidates no farther than the current K-th.  Same result
+// as the serial query (the K smallest pairs are unique).
 // ---------------------------------------------------------------------------
 constexpr int kWaveCand = 640;
 constexpr int kWavePer = kWaveCand / 64;
+constexpr int kWaveCells = 256;
 
 struct WaveKnn {
     double d2[kWaveCand];
     int idx[kWaveCand];
     double res_d2[kMaxNgb];
     int res_idx[kMaxNgb];
+    int cfirst[kWaveCells];    // listed cells: first entry in the cell index
+    int cpre[kWaveCells + 1];  // prefix sums of their particle counts
     double kth;
     int n;
 };
@@ -269,6 +275,33 @@ __device__ inline void wave_sync() {
 __device__ inline double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
+}
+
+// Offset of the q-th cell of the Chebyshev shell s (q < number of cells in it).
+__device__ inline void shell_cell(int s, int q, int& dx, int& dy, int& dz) {
+    if (s == 0) {
+        dx = dy = dz = 0;
+        return;
+    }
+    const int side = 2 * s + 1, inner = side - 2;
+    const int fa = side * side, fb = side * inner;
+    if (q < 2 * fa) {  // the two faces |dz| = s
+        const int f = q / fa, m = q - f * fa;
+        dz = f ? s : -s;
+        dx = m / side - s;
+        dy = m - (m / side) * side - s;
+    } else if (q < 2 * fa + 2 * fb) {  // |dy| = s, |dz| < s
+        const int qq = q - 2 * fa, f = qq / fb, m = qq - f * fb;
+        dy = f ? s : -s;
+        dx = m / inner - s;
+        dz = m - (m / inner) * inner - (s - 1);
+    } else {  // |dx| = s, |dy| < s, |dz| < s
+        const int fc = inner * inner;
+        const int qq = q - 2 * fa - 2 * fb, f = qq / fc, m = qq - f * fc;
+        dx = f ? s : -s;
+        dy = m / inner - (s - 1);
+        dz = m - (m / inner) * inner - (s - 1);
+    }
 }
 
 // Number of register-held candidates (over the wave) that satisfy pred.
@@ -352,8 +385,6 @@ __device__ inline double wave_select(WaveKnn& L, int n, int K, int lane) {
 __device__ inline bool knn_wave(const GridInfo& g, const int* __restrict__ cell_start,
                                 const int* __restrict__ cell_idx, const double* __restrict__ pos,
                                 double qx, double qy, double qz, int self, int K, WaveKnn& L, int lane) {
-    if (lane == 0) L.n = 0;
-    wave_sync();
     int c[3];
     const double q[3] = {qx, qy, qz};
     for (int a = 0; a < 3; ++a) {
@@ -364,35 +395,103 @@ __device__ inline bool knn_wave(const GridInfo& g, const int* __restrict__ cell_
     csmin = csmin < g.cs[2] ? csmin : g.cs[2];
     int smax = g.nc[0] > g.nc[1] ? g.nc[0] : g.nc[1];
     smax = smax > g.nc[2] ? smax : g.nc[2];
+    const unsigned long long below = (1ull << lane) - 1ull;
     double bound = __longlong_as_double(0x7ff0000000000000ll);  // +inf: keep every candidate
+    int n = 0;                                                   // candidates in the buffer
+    bool over = false;
     for (int s = 0; s <= smax; ++s) {
-        const int side = 2 * s + 1;
-        const int ncube = side * side * side;
-        for (int t = lane; t < ncube; t += 64) {
-            const int dx = t % side - s, dy = (t / side) % side - s, dz = t / (side * side) - s;
-            if (max(abs(dx), max(abs(dy), abs(dz))) != s) continue;
-            const int ix = c[0] + dx, iy = c[1] + dy, iz = c[2] + dz;
-            if (ix < 0 || ix >= g.nc[0] || iy < 0 || iy >= g.nc[1] || iz < 0 || iz >= g.nc[2]) continue;
-            const long long cell = g.cell0 + (static_cast<long long>(ix) * g.nc[1] + iy) * g.nc[2] + iz;
-            const int t1 = cell_start[cell + 1];
-            for (int u = cell_start[cell]; u < t1; ++u) {
-                const int j = cell_idx[u];
-                if (j == self) continue;
-                const double ex = pos[3 * static_cast<long long>(j) + 0] - qx;
-                const double ey = pos[3 * static_cast<long long>(j) + 1] - qy;
-                const double ez = pos[3 * static_cast<long long>(j) + 2] - qz;
-                const double d2 = ex * ex + ey * ey + ez * ez;
-                if (!(d2 <= bound)) continue;
-                const int slot = atomicAdd(&L.n, 1);
-                if (slot < kWaveCand) {
-                    L.d2[slot] = d2;
-                    L.idx[slot] = j;
+        const int ncell = s == 0 ? 1 : 24 * s * s + 2;  // (2s+1)^3 - (2s-1)^3
+        for (int c0 = 0; c0 < ncell; c0 += kWaveCells) {
+            // the chunk's cells inside the grid that hold particles
+            int first[4], cnt[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int qc = c0 + 64 * i + lane;
+                first[i] = 0;
+                cnt[i] = 0;
+                if (qc < ncell) {
+                    int dx, dy, dz;
+                    shell_cell(s, qc, dx, dy, dz);
+                    const int ix = c[0] + dx, iy = c[1] + dy, iz = c[2] + dz;
+                    if (ix >= 0 && ix < g.nc[0] && iy >= 0 && iy < g.nc[1] && iz >= 0 && iz < g.nc[2]) {
+                        const long long cell = g.cell0 + (static_cast<long long>(ix) * g.nc[1] + iy) * g.nc[2] + iz;
+                        first[i] = cell_start[cell];
+                        cnt[i] = cell_start[cell + 1] - first[i];
+                    }
                 }
             }
+            int m = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const bool ok = cnt[i] > 0;
+                const unsigned long long b = __ballot(ok);
+                if (ok) L.cfirst[m + __popcll(b & below)] = first[i];
+                // counts go through cpre, turned into prefix sums below
+                if (ok) L.cpre[m + __popcll(b & below) + 1] = cnt[i];
+                m += __popcll(b);
+            }
+            if (lane == 0) L.cpre[0] = 0;
+            wave_sync();
+            // inclusive prefix sums of the m counts, 64 at a time
+            int carry = 0;
+            for (int b0 = 0; b0 < m; b0 += 64) {
+                int v = b0 + lane < m ? L.cpre[b0 + lane + 1] : 0;
+                for (int off = 1; off < 64; off <<= 1) {
+                    const int w = __shfl_up(v, off, 64);
+                    if (lane >= off) v += w;
+                }
+                if (b0 + lane < m) L.cpre[b0 + lane + 1] = v + carry;
+                carry += __shfl(v, 63, 64);
+            }
+            wave_sync();
+            const int total = L.cpre[m];
+            // the candidates, four per lane per round
+            for (int k0 = 0; k0 < total; k0 += 256) {
+                int jj[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int k = k0 + 64 * i + lane;
+                    jj[i] = -1;
+                    if (k < total) {
+                        int lo = 0, hi = m - 1;  // the cell holding candidate k
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (L.cpre[mid] <= k)
+                                lo = mid;
+                            else
+                                hi = mid - 1;
+                        }
+                        jj[i] = cell_idx[L.cfirst[lo] + (k - L.cpre[lo])];
+                    }
+                }
+                double d2v[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    d2v[i] = 0.0;
+                    if (jj[i] >= 0) {
+                        const double ex = pos[3 * static_cast<long long>(jj[i]) + 0] - qx;
+                        const double ey = pos[3 * static_cast<long long>(jj[i]) + 1] - qy;
+                        const double ez = pos[3 * static_cast<long long>(jj[i]) + 2] - qz;
+                        d2v[i] = ex * ex + ey * ey + ez * ez;
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const bool keep = jj[i] >= 0 && jj[i] != self && d2v[i] <= bound;
+                    const unsigned long long b = __ballot(keep);
+                    const int at = n + __popcll(b & below);
+                    if (keep && at < kWaveCand) {
+                        L.d2[at] = d2v[i];
+                        L.idx[at] = jj[i];
+                    }
+                    n += __popcll(b);
+                }
+            }
+            wave_sync();  // the cell lists are reused
+            if (n > kWaveCand) over = true;
+            if (over) break;
         }
-        wave_sync();
-        const int n = L.n;
-        if (n > kWaveCand) return false;
+        if (over) return false;
         if (n < K) continue;
         const double kth = wave_select(L, n, K, lane);
         const double reach = static_cast<double>(s) * csmin;
@@ -414,8 +513,7 @@ __device__ inline bool knn_wave(const GridInfo& g, const int* __restrict__ cell_
             return true;
         }
         bound = kth;
-        if (lane == 0) L.n = K;
-        wave_sync();
+        n = K;
     }
     return true;  // fewer than K particles in the instance
 }

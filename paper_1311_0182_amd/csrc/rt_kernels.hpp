@@ -24,7 +24,7 @@ enum : int {
     kCntHops = 1,
     kCntVips = 2,
     kCntUpdates = 3,
-    kCntAct0 = 4,  // active packets for the next forward step, ping-pong [4], [5]
+    kCntAct0 = 4,  // nonzero if a packet is active for the next forward step, ping-pong [4], [5]
     kCntFlags = 6,
     kCntHopsStep = 7,
     kCntVipCnt0 = 8,  // ViP list fill, ping-pong [8], [9]
@@ -32,7 +32,6 @@ enum : int {
     kCntDone = 11,    // set once a forward step finds no active packet; later launches of the step exit
     kCntBytes = 12,   // algorithmic bytes moved by forward steps (for the roofline)
     kCntTiles = 13,   // forward-step tiles processed
-    kCntRan = 14,     // stamp of the last forward step that ran
     kCntDeep = 15,    // virtual particles of this forward step that landed inside their box
     kCntN = 16
 };
@@ -792,7 +791,7 @@ struct HopArgs {
     long long vip_cap;
     int list_wr;
     long long* cnt;
-    unsigned long long* part;  // [tile][3]: packets active next, packets moved, bytes
+    unsigned long long* part;  // [tile][3]: packets moved, bytes, forward steps run (summed per RT step)
     int act_rd, act_wr;
 };
 
@@ -858,8 +857,8 @@ __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
 // neighbours and the delivery words.
 template <typename R, typename DT>
 struct HopLds {
-    static constexpr int kEdges = 1024;                         // edges staged at a time
-    static constexpr int kPairs = sizeof(R) == 4 ? 512 : 256;   // pairs gathered at a time
+    static constexpr int kEdges = 256;                          // edges staged at a time
+    static constexpr int kPairs = sizeof(R) == 4 ? 128 : 64;    // pairs gathered at a time
     static constexpr size_t ik = 0;
     static constexpr size_t dl = ik + 4 * kEdges;
     static constexpr size_t eff = dl + sizeof(DT) * kEdges;
@@ -879,10 +878,10 @@ struct HopLds {
     }
 };
 
-// One forward step (section 2.1), receiver-sorted.  A workgroup owns a tile
-// of T consecutive particles, one lane per slot (particle j, bin nu, reception
-// cone r), and runs only if the tile is marked for this step (hop 0 of an RT
-// step runs every tile).  Gathering: the inboxes of the tile's incoming edges
+// One forward step (section 2.1), receiver-sorted.  A workgroup of one
+// wavefront owns a tile of T = 64 / G consecutive particles, one lane per slot
+// (particle j, bin nu, reception cone r), and runs only if the tile is marked
+// for this step (hop 0 of an RT step runs every tile).  Gathering: the inboxes of the tile's incoming edges
 // are staged in LDS; each slot counts the packets that arrive in its cone
 // (from LDS alone), a prefix sum lays the (edge, packet, slot) pairs out in
 // one queue, and all lanes load and attenuate the queued packets together
@@ -897,7 +896,7 @@ struct HopLds {
 // stays (clocks carried over by -dt), the recombination photons of the last
 // chemistry step (section 2.2) and the emission records.
 template <typename R, typename DT>
-__global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
+__global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
     if (!a.hop0) {
         if (a.cnt[kCntDone] != 0 || a.cnt[kCntAct0 + a.act_rd] == 0) {
             if (blockIdx.x == 0 && threadIdx.x == 0) a.cnt[kCntDone] = 1;
@@ -916,7 +915,6 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
         }
         a.cnt[kCntRec] = 0;   // records of this step were all linked before launch
         a.cnt[kCntDeep] = 0;  // and its virtual particles all handled
-        a.cnt[kCntRan] = a.stamp;
     }
     const long long tile = xcd_block(blockIdx.x, gridDim.x);
     if (!a.hop0 && a.hot_rd[tile] != a.stamp) return;
@@ -927,8 +925,6 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
     using L = HopLds<R, DT>;
     constexpr int kP = L::kPairs;
     extern __shared__ __align__(32) unsigned char lds[];
-    __shared__ int s_scan[4];
-    __shared__ unsigned long long s_tally[3][4];
 
     const int G = a.G, nrc = a.nrc, K = a.K, T = a.T;
     const long long j0 = tile * T;
@@ -942,10 +938,12 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
     const int inst = valid ? a.inst_of[j] : 0;
     const double U = f32 ? a.U[inst] : 1.0;
     const long long jend = (j0 + T < a.N) ? j0 + T : a.N;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x;
     // algorithmic bytes this lane moves (slot state, gathered packets, edges)
     unsigned long long nbytes = 0;
+    // the tile's running tallies (read early, written back at the end)
+    unsigned long long tally = 0;
+    if (lane < 3) tally = a.part[3 * tile + lane];
 
     Acc<R> acc = {};
     int narr = 0;            // packets merged into the bin besides the one that stays
@@ -1022,7 +1020,7 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
         for (long long cb = e_t0; cb < e_t1; cb += L::kEdges) {
             const long long ne = (e_t1 - cb < L::kEdges) ? e_t1 - cb : L::kEdges;
             bool snd = false;
-            for (long long t = threadIdx.x; t < ne; t += 256) {
+            for (long long t = lane; t < ne; t += 64) {
                 const Inbox<DT> w = a.in_rd[cb + t];
                 const DT m = (w.tag >> 1) == prev ? w.mask : DT(0);
                 const bool nd = (w.tag & 1u) != 0;
@@ -1042,7 +1040,8 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
                 e_nd[t] = static_cast<unsigned char>(nd);
                 nbytes += sizeof(Inbox<DT>) + 4;
             }
-            const bool any_nd = __syncthreads_or(snd);
+            wave_sync();
+            const bool any_nd = __ballot(snd) != 0;
             const long long lo = my0 > cb ? my0 : cb;
             const long long hi = my1 < cb + ne ? my1 : cb + ne;
             // hit mask of this slot over a segment of up to 64 of its particle's
@@ -1091,20 +1090,14 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
             } else {
                 for (int sg = 0; sg < nseg; ++sg) np += __popcll(seg_hit(sg));
             }
-            // exclusive prefix sum over the workgroup
+            // exclusive prefix sum over the wavefront
             int incl = np;
             for (int off = 1; off < 64; off <<= 1) {
                 const int v = __shfl_up(incl, off, 64);
                 if (lane >= off) incl += v;
             }
-            if (lane == 63) s_scan[wave] = incl;
-            __syncthreads();
-            int M = 0, wbase = 0;
-            for (int w = 0; w < 4; ++w) {
-                if (w < wave) wbase += s_scan[w];
-                M += s_scan[w];
-            }
-            const int off0 = wbase + incl - np;
+            const int M = __shfl(incl, 63, 64);
+            const int off0 = incl - np;
             for (int base = 0; base < M; base += kP) {
                 {
                     // every lane takes part: the transpose needs all of a particle's lanes
@@ -1115,16 +1108,16 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
                         ++q;
                     });
                 }
-                __syncthreads();
+                wave_sync();
                 const int nr = (M - base < kP) ? M - base : kP;
                 // load and attenuate the queued packets (all lanes; loads first)
-                constexpr int kPer = kP / 256;
+                constexpr int kPer = kP / 64;
                 Bin4<R> q[kPer];
                 R2<R> qc[kPer];
                 V4 v[kPer];
 #pragma unroll
                 for (int i = 0; i < kPer; ++i) {
-                    const int u = threadIdx.x + 256 * i;
+                    const int u = lane + 64 * i;
                     if (u < nr) {
                         const unsigned int d = pdesc[u];
                         const int t = static_cast<int>(d >> 14), pp = static_cast<int>(d >> 8) & 63, sl = static_cast<int>(d & 255u);
@@ -1137,7 +1130,7 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
                 }
 #pragma unroll
                 for (int i = 0; i < kPer; ++i) {
-                    const int u = threadIdx.x + 256 * i;
+                    const int u = lane + 64 * i;
                     if (u < nr) {
                         const unsigned int d = pdesc[u];
                         const int t = static_cast<int>(d >> 14), sl = static_cast<int>(d & 255u);
@@ -1169,7 +1162,7 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
                         pval[6 * kP + u] = q[i].n;
                     }
                 }
-                __syncthreads();
+                wave_sync();
                 // this slot's contributions, in order
                 const int qa = off0 > base ? off0 : base;
                 const int qb = (off0 + np < base + nr) ? off0 + np : base + nr;
@@ -1182,7 +1175,7 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
                     acc_add(acc, pval[u], pval[kP + u], pval[2 * kP + u], pval[3 * kP + u], pval[4 * kP + u]);
                     ++narr;
                 }
-                if (base + kP < M || cb + L::kEdges < e_t1) __syncthreads();  // the LDS is reused
+                wave_sync();  // the LDS is reused
             }
         }
     }
@@ -1273,7 +1266,8 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
     // lanes of a particle with an active packet stage its neighbour offsets
     // (with the receiver-sorted index of each edge) and its neighbours.
     const bool act = valid && nn > R(0) && cn < a.dtc;
-    const bool tile_act = __syncthreads_or(act);  // also: the gather's LDS is free again
+    wave_sync();  // the gather's LDS is free again
+    const bool tile_act = __ballot(act) != 0;
     if (valid && o == 0 && hd >= 0) a.head[j] = -1;  // every lane of j has read its records
     if (tile_act && threadIdx.x == 0) a.hot_wr[tile] = a.stamp + 1;  // its leaving packets empty their bins
     const int gbase = lane & ~(G - 1);
@@ -1398,49 +1392,34 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
             }
         }
     }
-    // the tile's tally (packets active next step, packets moved this step,
-    // bytes), summed over the marked tiles by k_hop_tally: no global atomics
-    const unsigned long long nact = __popcll(__ballot(act));
+    // whether a packet moves next step (a flag, no count: plain stores), and
+    // the tile's running tallies of packets moved, bytes and steps run
+    if (tile_act && lane == 0) a.cnt[kCntAct0 + a.act_wr] = 1;
     const unsigned long long nupd = __popcll(__ballot(departed));
     const unsigned long long wb = wave_sum_u64(nbytes);
-    if (lane == 0) {
-        s_tally[0][wave] = nact;
-        s_tally[1][wave] = nupd;
-        s_tally[2][wave] = wb;
-    }
-    __syncthreads();
-    if (threadIdx.x < 3) {
-        const unsigned long long* v = s_tally[threadIdx.x];
-        a.part[3 * tile + threadIdx.x] = v[0] + v[1] + v[2] + v[3];
-    }
+    if (lane < 3) a.part[3 * tile + lane] = tally + (lane == 0 ? nupd : (lane == 1 ? wb : 1ull));
 }
 
-// Sums the tallies of the tiles that ran in the last forward step (all tiles
-// at hop 0, the marked ones otherwise); nothing if that step exited early.
-__global__ __launch_bounds__(1024) void k_hop_tally(long long* cnt, const unsigned long long* part, const int* hot,
-                                                    long long ntiles, int stamp, int hop0, int act_wr) {
-    __shared__ unsigned long long s[4][1024];
-    if (cnt[kCntRan] != stamp) return;
-    unsigned long long v[4] = {0, 0, 0, 0};
-    for (long long t = threadIdx.x; t < ntiles; t += 1024) {
-        if (!hop0 && hot[t] != stamp) continue;
-        v[0] += part[3 * t];
-        v[1] += part[3 * t + 1];
-        v[2] += part[3 * t + 2];
-        v[3] += 1;
-    }
-    for (int c = 0; c < 4; ++c) s[c][threadIdx.x] = v[c];
+// Adds the tiles' running tallies of an RT step to the counters and clears them.
+__global__ __launch_bounds__(256) void k_step_tally(long long* cnt, unsigned long long* part, long long ntiles) {
+    __shared__ unsigned long long s[3][256];
+    unsigned long long v[3] = {0, 0, 0};
+    for (long long t = blockIdx.x * 256LL + threadIdx.x; t < ntiles; t += gridDim.x * 256LL)
+        for (int c = 0; c < 3; ++c) {
+            v[c] += part[3 * t + c];
+            part[3 * t + c] = 0;
+        }
+    for (int c = 0; c < 3; ++c) s[c][threadIdx.x] = v[c];
     __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
+    for (int w = 128; w > 0; w >>= 1) {
         if (threadIdx.x < w)
-            for (int c = 0; c < 4; ++c) s[c][threadIdx.x] += s[c][threadIdx.x + w];
+            for (int c = 0; c < 3; ++c) s[c][threadIdx.x] += s[c][threadIdx.x + w];
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        cnt[kCntAct0 + act_wr] = static_cast<long long>(s[0][0]);
-        cnt[kCntUpdates] += static_cast<long long>(s[1][0]);
-        cnt[kCntBytes] += static_cast<long long>(s[2][0]);
-        cnt[kCntTiles] += static_cast<long long>(s[3][0]);
+        if (s[0][0]) atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[kCntUpdates]), s[0][0]);
+        if (s[1][0]) atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[kCntBytes]), s[1][0]);
+        if (s[2][0]) atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[kCntTiles]), s[2][0]);
     }
 }
 

@@ -267,17 +267,11 @@ rt_status launch_hop(rt_ctx* c, int hop) {
     a.act_rd = hop & 1;
     a.act_wr = (hop + 1) & 1;
     const size_t lds = HopLds<R, DT>::bytes(c->tileT, c->K);
-    hipLaunchKernelGGL((k_hop<R, DT>), dim3(static_cast<unsigned>(c->ntiles)), dim3(256), lds, c->stream, a);
+    hipLaunchKernelGGL((k_hop<R, DT>), dim3(static_cast<unsigned>(c->ntiles)), dim3(64), lds, c->stream, a);
     HIPCHK(c, hipGetLastError());
     return RT_OK;
 }
 
-rt_status launch_tally(rt_ctx* c, int hop) {
-    hipLaunchKernelGGL(k_hop_tally, dim3(1), dim3(1024), 0, c->stream, c->cnt, c->part, c->hot[hop & 1], c->ntiles,
-                       static_cast<int>(c->serial + hop), hop == 0 ? 1 : 0, (hop + 1) & 1);
-    HIPCHK(c, hipGetLastError());
-    return RT_OK;
-}
 
 rt_status launch_hop_any(rt_ctx* c, int hop) {
     if (c->f32) return c->dl64 ? launch_hop<float, unsigned long long>(c, hop) : launch_hop<float, unsigned int>(c, hop);
@@ -465,7 +459,6 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
     TRY(time_begin(c, 3));
     TRY(launch_hop_any(c, 0));
     TRY(time_end(c, 3));
-    TRY(launch_tally(c, 0));
     // Forward steps are enqueued in batches between host checks of the device
     // counters.  Automatic batching starts with the previous step's count less
     // a margin, then goes one step at a time, so that almost no launch finds
@@ -484,7 +477,6 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
                 TRY(time_begin(c, 3 + 2 * q));
                 TRY(launch_hop_any(c, q));
                 TRY(time_end(c, 3 + 2 * q));
-                TRY(launch_tally(c, q));
             }
             h = hend + 1;
         }
@@ -498,6 +490,9 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
             break;
         }
     }
+    hipLaunchKernelGGL(k_step_tally, dim3(static_cast<unsigned>(std::min<long long>(64, (c->ntiles + 255) / 256))),
+                       dim3(256), 0, c->stream, c->cnt, c->part, c->ntiles);
+    HIPCHK(c, hipGetLastError());
     // stamps of this step were serial .. serial + h - 1 (launched forward steps)
     c->last_stamp = c->serial + H;
     c->serial += h;
@@ -637,14 +632,14 @@ rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, cons
     c->f32 = p->precision == RT_FP32;
     c->dl64 = c->G > 32;
     {
-        // the forward step's LDS (at most 48 KiB) bounds the particles per tile
+        // a tile is one wavefront; its LDS (at most 24 KiB) bounds the particles per tile
         auto hop_lds = [&](int t) {
             if (c->f32)
                 return c->dl64 ? HopLds<float, unsigned long long>::bytes(t, c->K) : HopLds<float, unsigned int>::bytes(t, c->K);
             return c->dl64 ? HopLds<double, unsigned long long>::bytes(t, c->K) : HopLds<double, unsigned int>::bytes(t, c->K);
         };
-        int T = 256 / c->G;
-        while (T > 1 && hop_lds(T) > 48 * 1024) T /= 2;
+        int T = 64 / c->G;
+        while (T > 1 && hop_lds(T) > 24 * 1024) T /= 2;
         c->tileT = T;
         while ((1 << c->lgT) < T) ++c->lgT;
     }
@@ -807,7 +802,10 @@ rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, cons
         HIPCHK(c, hipMemsetAsync(c->inbox[b], 0xff, c->inbox_bytes, c->stream));
         ITRY(alloc_n(c, &c->hot[b], c->ntiles));
         ITRY(fill_i32(c, c->hot[b], c->ntiles, -1));
-        if (b == 0) ITRY(alloc_n(c, &c->part, 3 * c->ntiles));
+        if (b == 0) {
+            ITRY(alloc_n(c, &c->part, 3 * c->ntiles));
+            HIPCHK(c, hipMemsetAsync(c->part, 0, sizeof(unsigned long long) * 3 * c->ntiles, c->stream));
+        }
         ITRY(alloc_n(c, &c->nrr[b], N));
         ITRY(fill_f64(c, c->nrr[b], N, 0.0));
         ITRY(alloc_n(c, &c->head[b], N));
