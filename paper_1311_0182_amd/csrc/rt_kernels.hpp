@@ -848,6 +848,28 @@ __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
     return v;
 }
 
+// Bit-matrix transpose inside each aligned group of G lanes (G a power of two
+// <= 64, the word type wide enough): lane o holds row o (bit c = entry (o, c),
+// c < G) and receives column o (bit e = entry (e, o)).  log2(G) rounds, each
+// exchanging the off-diagonal halves of 2j x 2j blocks between lanes o and o^j.
+template <typename W>
+__device__ inline W group_transpose(W x, int G, int o) {
+    for (int j = G >> 1; j > 0; j >>= 1) {
+        W m;  // bits c with (c & j) == 0
+        switch (j) {
+            case 32: m = static_cast<W>(0x00000000FFFFFFFFull); break;
+            case 16: m = static_cast<W>(0x0000FFFF0000FFFFull); break;
+            case 8: m = static_cast<W>(0x00FF00FF00FF00FFull); break;
+            case 4: m = static_cast<W>(0x0F0F0F0F0F0F0F0Full); break;
+            case 2: m = static_cast<W>(0x3333333333333333ull); break;
+            default: m = static_cast<W>(0x5555555555555555ull); break;
+        }
+        const W y = __shfl_xor(x, j, 64);
+        x = (o & j) ? static_cast<W>((x & ~m) | ((y & ~m) >> j)) : static_cast<W>((x & m) | ((y & m) << j));
+    }
+    return x;
+}
+
 // LDS of a forward-step workgroup (bytes from the start of its dynamic LDS).
 // While gathering: a chunk of the tile's incoming edges (their inboxes and
 // sender words), the queue of (edge, packet, receiving slot) pairs with
@@ -1045,28 +1067,28 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
             const long long lo = my0 > cb ? my0 : cb;
             const long long hi = my1 < cb + ne ? my1 : cb + ne;
             // hit mask of this slot over a segment of up to 64 of its particle's
-            // edges: the particle's lanes read its edges G at a time and one
-            // ballot per mask bit hands each slot lane its bit (a transpose)
-            int nseg = hi > lo ? static_cast<int>((hi - lo + 63) >> 6) : 0;
-            for (int off = 32; off > 0; off >>= 1) nseg = max(nseg, __shfl_xor(nseg, off, 64));
+            // edges: the particle's lanes read its edges G at a time (lane o:
+            // edge o's effective mask, a row) and a bit-matrix transpose hands
+            // each slot lane its bit of every edge (a column).  A particle's
+            // lanes share lo and hi, so they run the same rounds.
+            const int nseg = hi > lo ? static_cast<int>((hi - lo + 63) >> 6) : 0;
             auto seg_hit = [&](int sg) {
                 const long long sb = lo + 64ll * sg;
-                const int len = static_cast<int>(hi - sb < 0 ? 0 : (hi - sb < 64 ? hi - sb : 64));
+                const int len = static_cast<int>(hi - sb < 64 ? hi - sb : 64);
                 unsigned long long h = 0;
                 for (int k = 0; k * G < 64; ++k) {
                     const int idx = k * G + o;
-                    const DT v = idx < len ? e_ef[sb - cb + idx] : DT(0);
-                    for (int b = 0; b < G; ++b) {
-                        const unsigned long long bal = __ballot(((v >> b) & DT(1)) != DT(0));
-                        if (b == o) h |= ((bal >> gbase_s) & gmask_s) << (k * G);
-                    }
+                    DT v = idx < len ? static_cast<DT>(e_ef[sb - cb + idx] & static_cast<DT>(gmask_s)) : DT(0);
+                    v = group_transpose(v, G, o);
+                    h |= (static_cast<unsigned long long>(v) & gmask_s) << (k * G);
                 }
                 return h;
             };
+            const unsigned long long h0 = nseg > 0 ? seg_hit(0) : 0ull;  // usually the only segment
             // this slot's arriving (edge, packet) pairs, in edge order
             auto each_pair = [&](auto&& f) {
                 for (int sg = 0; sg < nseg; ++sg) {
-                    unsigned long long h = seg_hit(sg);
+                    unsigned long long h = sg == 0 ? h0 : seg_hit(sg);
                     while (h) {
                         const int u = __builtin_ctzll(h);
                         h &= h - 1ull;
@@ -1088,7 +1110,7 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
             if (any_nd) {
                 each_pair([&](int, int) { ++np; });
             } else {
-                for (int sg = 0; sg < nseg; ++sg) np += __popcll(seg_hit(sg));
+                for (int sg = 0; sg < nseg; ++sg) np += __popcll(sg == 0 ? h0 : seg_hit(sg));
             }
             // exclusive prefix sum over the wavefront
             int incl = np;
@@ -1314,17 +1336,15 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
     const bool psend = ((wsend >> gbase) & gmaskG) != 0;
     const bool offdiag = __ballot(send && tgt != r) & (gmaskG << gbase);
     if (wsend) {
-        for (int k = 0; k < K; ++k) {
-            const unsigned long long b = __ballot(send && ((cmw >> k) & 1ull));
-            if (psend && (k % G) == o) dw[k] = static_cast<DT>((b >> gbase) & gmaskG);
-        }
-        wave_sync();
-        if (psend) {
-            Inbox<DT> ib;
-            ib.tag = (static_cast<unsigned int>(a.stamp) << 1) | (offdiag ? 1u : 0u);
-            for (int k = o; k < K; k += G) {
-                const DT w = dw[k];
-                if (w == DT(0)) continue;
+        // row o: the sending slot o's cone bits for neighbours k0..k0+G-1;
+        // transposed, lane o holds the delivery word of neighbour k0 + o
+        const unsigned long long cs = send ? cmw : 0ull;
+        Inbox<DT> ib;
+        ib.tag = (static_cast<unsigned int>(a.stamp) << 1) | (offdiag ? 1u : 0u);
+        for (int k0 = 0; k0 < K; k0 += G) {
+            const DT w = group_transpose(static_cast<DT>((cs >> k0) & gmaskG), G, o);
+            const int k = k0 + o;
+            if (psend && k < K && w != DT(0)) {
                 ib.mask = w;
                 long long e;
                 if constexpr (f32)
