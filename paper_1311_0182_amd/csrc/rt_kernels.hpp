@@ -12,6 +12,7 @@
 //   with the edge offsets rev_v; neighbour offsets fwd_v.
 #pragma once
 
+#include <cstddef>
 #include <type_traits>
 
 #include "rt_device.hpp"
@@ -882,7 +883,9 @@ struct HopLds {
     static constexpr int kEdges = 256;                          // edges staged at a time
     static constexpr int kPairs = sizeof(R) == 4 ? 128 : 64;    // pairs gathered at a time
     static constexpr size_t ik = 0;
-    static constexpr size_t dl = ik + 4 * kEdges;
+    static constexpr size_t tag = ik + 4 * kEdges;    // raw inbox words, loaded straight into LDS
+    static constexpr size_t mw = tag + 4 * kEdges;    // [sizeof(DT)/4][kEdges] mask words
+    static constexpr size_t dl = mw + sizeof(DT) * kEdges;
     static constexpr size_t eff = dl + sizeof(DT) * kEdges;
     static constexpr size_t nd = eff + sizeof(DT) * kEdges;
     static constexpr size_t desc = (nd + kEdges + 31) / 32 * 32;
@@ -1016,6 +1019,8 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
     }
     if (!a.hop0) {
         unsigned int* e_ik = reinterpret_cast<unsigned int*>(lds + L::ik);
+        unsigned int* e_tag = reinterpret_cast<unsigned int*>(lds + L::tag);
+        unsigned int* e_mw = reinterpret_cast<unsigned int*>(lds + L::mw);
         DT* e_dl = reinterpret_cast<DT*>(lds + L::dl);
         DT* e_ef = reinterpret_cast<DT*>(lds + L::eff);
         unsigned char* e_nd = lds + L::nd;
@@ -1042,10 +1047,27 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
         for (long long cb = e_t0; cb < e_t1; cb += L::kEdges) {
             const long long ne = (e_t1 - cb < L::kEdges) ? e_t1 - cb : L::kEdges;
             bool snd = false;
+            // inbox words and edge words go straight from memory into LDS (no
+            // registers held, all loads in flight together); lanes past the
+            // end load a copy of the last edge
+            const int nrd = static_cast<int>((ne + 63) >> 6);
+            for (int i = 0; i < nrd; ++i) {
+                const long long t = 64ll * i + lane;
+                const long long ts = cb + (t < ne ? t : ne - 1);
+                const unsigned int* ws = reinterpret_cast<const unsigned int*>(a.in_rd + ts);
+                __builtin_amdgcn_global_load_lds(ws, e_tag + 64 * i, 4, 0, 0);
+                for (int w = 0; w < static_cast<int>(sizeof(DT) / 4); ++w)
+                    __builtin_amdgcn_global_load_lds(ws + offsetof(Inbox<DT>, mask) / 4 + w, e_mw + w * L::kEdges + 64 * i, 4, 0, 0);
+                __builtin_amdgcn_global_load_lds(a.rev_ik + ts, e_ik + 64 * i, 4, 0, 0);
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            wave_sync();
             for (long long t = lane; t < ne; t += 64) {
-                const Inbox<DT> w = a.in_rd[cb + t];
-                const DT m = (w.tag >> 1) == prev ? w.mask : DT(0);
-                const bool nd = (w.tag & 1u) != 0;
+                const unsigned int wtag = e_tag[t];
+                DT wmask = static_cast<DT>(e_mw[t]);
+                if constexpr (sizeof(DT) == 8) wmask |= static_cast<DT>(e_mw[L::kEdges + t]) << 32;
+                const DT m = (wtag >> 1) == prev ? wmask : DT(0);
+                const bool nd = (wtag & 1u) != 0;
                 // effective mask: bit (nu, r) set if the edge may bring a packet
                 // into reception cone r; a sender with packets arriving off
                 // their own index may reach any cone of a bin it delivers in
@@ -1056,7 +1078,6 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
                         if ((m >> (f * nrc)) & gm) ef |= gm << (f * nrc);
                     snd = true;
                 }
-                e_ik[t] = a.rev_ik[cb + t];
                 e_dl[t] = m;
                 e_ef[t] = ef;
                 e_nd[t] = static_cast<unsigned char>(nd);
