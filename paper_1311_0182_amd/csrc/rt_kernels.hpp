@@ -480,27 +480,43 @@ struct VipArgs {
 // max_depth).  k_vip_sample draws the first point of every chain, one lane
 // each, and settles those that escape; the rest go on to k_vip_chain.
 
-// One lane, attempts in order.  False if no attempt is accepted.
-__device__ inline bool vip_draw_lane(const VipArgs& a, const Vip& q, int depth, double p[3]) {
+// A group of kVipLanes lanes draws attempts kVipLanes at a time (attempt
+// round*kVipLanes + sub-lane); the lowest accepted attempt wins, as if drawn
+// one by one.  Every lane of the group returns the point.  False if no attempt
+// is accepted.
+constexpr int kVipLanes = 16;
+
+__device__ inline bool vip_draw_group(const VipArgs& a, const Vip& q, bool live, int depth, int sub, int gshift,
+                                      double p[3]) {
     const double* ecs = (q.ec >= 0 && depth == 1) ? a.ecd + 3 * (static_cast<long long>(q.ec) * a.nec) : nullptr;
-    for (uint32_t att = 0; att < kVipAttempts; ++att) {
-        double u[4];
-        uniforms4(a.seed, q.tag, att, a.step, q.ida, q.idb | static_cast<uint32_t>(depth), u);
-        if (!(u[0] * u[0] + u[1] * u[1] + u[2] * u[2] <= 1.0)) continue;
-        if (ecs ? nearest_direction(ecs, a.nec, u[0], u[1], u[2]) != q.ek
-                : !in_cone(u[0], u[1], u[2], q.d[0], q.d[1], q.d[2], a.c2))
-            continue;
-        p[0] = u[0];
-        p[1] = u[1];
-        p[2] = u[2];
-        return true;
+    const unsigned long long gm = (kVipLanes >= 64 ? ~0ull : ((1ull << kVipLanes) - 1ull)) << gshift;
+    bool done = !live;
+    bool found = false;
+    for (uint32_t base = 0; base < kVipAttempts; base += kVipLanes) {
+        bool ok = false;
+        double u[4] = {0.0, 0.0, 0.0, 0.0};
+        if (!done) {
+            uniforms4(a.seed, q.tag, base + static_cast<uint32_t>(sub), a.step, q.ida, q.idb | static_cast<uint32_t>(depth), u);
+            ok = u[0] * u[0] + u[1] * u[1] + u[2] * u[2] <= 1.0;
+            if (ok) ok = ecs ? nearest_direction(ecs, a.nec, u[0], u[1], u[2]) == q.ek
+                             : in_cone(u[0], u[1], u[2], q.d[0], q.d[1], q.d[2], a.c2);
+        }
+        const unsigned long long b = __ballot(ok) & gm;
+        if (b && !done) {
+            const int f = __ffsll(static_cast<long long>(b)) - 1;  // lowest attempt of the group
+            p[0] = __shfl(u[0], f, 64);
+            p[1] = __shfl(u[1], f, 64);
+            p[2] = __shfl(u[2], f, 64);
+            found = true;
+            done = true;
+        }
+        if (__ballot(!done) == 0) break;
     }
-    return false;
+    return found;
 }
 
 __global__ __launch_bounds__(256) void k_vip_sample(VipArgs a) {
     const long long gid = blockIdx.x * 256LL + threadIdx.x;
-    const long long stride = gridDim.x * 256LL;
     if (!a.hop0) {
         // Once one forward step has found nothing to move, every later launch
         // of this step must exit: the ping-pong counters it would read are stale.
@@ -517,32 +533,43 @@ __global__ __launch_bounds__(256) void k_vip_sample(VipArgs a) {
         a.cnt[kCntVips] += n;  // the first leg of every chain
     }
     const int lane = threadIdx.x & 63;
-    for (long long v = gid; v < n; v += stride) {
-        const Vip q = a.list[v];
-        double* X = q.xr_emis ? a.exs : a.xs;
-        double* Rm = q.xr_emis ? a.ers : a.rs;
-        const double* bx = a.box + 6 * q.inst;
-        double p[3];
+    const int sub = lane % kVipLanes;
+    const int gshift = lane - sub;
+    const long long groups = gridDim.x * (256LL / kVipLanes);
+    const long long g0 = gid / kVipLanes;
+    // a uniform trip count per wavefront: its groups stay in step
+    const long long wbase = (gid - lane) / kVipLanes;
+    for (long long vb = wbase; vb < n; vb += groups) {
+        const long long v = vb + (g0 - wbase);
+        const bool live = v < n;
+        Vip q = {};
+        if (live) q = a.list[v];
+        double p[3] = {0.0, 0.0, 0.0};
+        const bool found = vip_draw_group(a, q, live, 1, sub, gshift, p);
         bool inside = false;
         double xv[3] = {0.0, 0.0, 0.0};
-        if (!vip_draw_lane(a, q, 1, p)) {
-            Rm[q.xr] += q.N;
-        } else {
-            xv[0] = q.x[0] + q.h * p[0];
-            xv[1] = q.x[1] + q.h * p[1];
-            xv[2] = q.x[2] + q.h * p[2];
-            if (xv[0] < bx[0] || xv[0] > bx[3] || xv[1] < bx[1] || xv[1] > bx[4] || xv[2] < bx[2] || xv[2] > bx[5])
-                X[q.xr] += q.N;
-            else
-                inside = true;
+        if (live && sub == 0) {
+            double* X = q.xr_emis ? a.exs : a.xs;
+            double* Rm = q.xr_emis ? a.ers : a.rs;
+            const double* bx = a.box + 6 * q.inst;
+            if (!found) {
+                Rm[q.xr] += q.N;
+            } else {
+                xv[0] = q.x[0] + q.h * p[0];
+                xv[1] = q.x[1] + q.h * p[1];
+                xv[2] = q.x[2] + q.h * p[2];
+                if (xv[0] < bx[0] || xv[0] > bx[3] || xv[1] < bx[1] || xv[1] > bx[4] || xv[2] < bx[2] || xv[2] > bx[5])
+                    X[q.xr] += q.N;
+                else
+                    inside = true;
+            }
         }
         // append the inside ones, one atomic per wavefront
         const unsigned long long b = __ballot(inside);
         if (b) {
-            const int leader = __ffsll(static_cast<long long>(__ballot(true))) - 1;
             long long base = 0;
-            if (lane == leader) base = atomicAdd(reinterpret_cast<unsigned long long*>(&a.cnt[kCntDeep]), static_cast<unsigned long long>(__popcll(b)));
-            base = __shfl(base, leader, 64);
+            if (lane == 0) base = atomicAdd(reinterpret_cast<unsigned long long*>(&a.cnt[kCntDeep]), static_cast<unsigned long long>(__popcll(b)));
+            base = __shfl(base, 0, 64);
             if (inside) {
                 const long long d = base + __popcll(b & ((1ull << lane) - 1ull));
                 if (d < a.vip_cap) {
