@@ -239,8 +239,9 @@ __device__ inline double knn_query(const GridInfo& g, const int* __restrict__ ce
 }
 
 // ---------------------------------------------------------------------------
-// Wavefront-cooperative exact kNN.  Shell by Chebyshev shell of grid cells,
-// the 64 lanes list the shell's cells with their particle ranges (four cells
+// Wavefront-cooperative exact kNN.  The cube of cells within Chebyshev
+// distance 2, then shell by Chebyshev shell, the 64 lanes list the cells with
+// their particle ranges (four cells
 // per lane per round, loads issued together), a prefix sum over the ranges
 // numbers the candidates, and the lanes take four candidates each per round
 // (index and position loads issued together), appending (d^2, index) to an
@@ -399,8 +400,13 @@ __device__ inline bool knn_wave(const GridInfo& g, const int* __restrict__ cell_
     double bound = __longlong_as_double(0x7ff0000000000000ll);  // +inf: keep every candidate
     int n = 0;                                                   // candidates in the buffer
     bool over = false;
-    for (int s = 0; s <= smax; ++s) {
-        const int ncell = s == 0 ? 1 : 24 * s * s + 2;  // (2s+1)^3 - (2s-1)^3
+    // the first pass takes the whole cube of Chebyshev radius s0 (the usual
+    // answer for an interior point), later passes one shell each
+    const int s0 = smax < 2 ? smax : 2;
+    for (int s = s0; s <= smax; ++s) {
+        const bool cube = s == s0;
+        const int side = 2 * s + 1;
+        const int ncell = cube ? side * side * side : 24 * s * s + 2;  // (2s+1)^3 - (2s-1)^3
         for (int c0 = 0; c0 < ncell; c0 += kWaveCells) {
             // the chunk's cells inside the grid that hold particles
             int first[4], cnt[4];
@@ -411,7 +417,13 @@ __device__ inline bool knn_wave(const GridInfo& g, const int* __restrict__ cell_
                 cnt[i] = 0;
                 if (qc < ncell) {
                     int dx, dy, dz;
-                    shell_cell(s, qc, dx, dy, dz);
+                    if (cube) {
+                        dx = qc / (side * side) - s;
+                        dy = (qc / side) % side - s;
+                        dz = qc % side - s;
+                    } else {
+                        shell_cell(s, qc, dx, dy, dz);
+                    }
                     const int ix = c[0] + dx, iy = c[1] + dy, iz = c[2] + dz;
                     if (ix >= 0 && ix < g.nc[0] && iy >= 0 && iy < g.nc[1] && iz >= 0 && iz < g.nc[2]) {
                         const long long cell = g.cell0 + (static_cast<long long>(ix) * g.nc[1] + iy) * g.nc[2] + iz;
