@@ -19,22 +19,31 @@
 
 namespace trt {
 
-// counters in device memory
+// counters in device memory, grouped by 64-byte line so that what every
+// wavefront reads at the start of a launch never shares a line with what many
+// wavefronts write during it
 enum : int {
+    kCntLine = 8,
+    // written once per launch (block 0) or per step
     kCntSteps = 0,
     kCntHops = 1,
     kCntVips = 2,
     kCntUpdates = 3,
-    kCntAct0 = 4,  // nonzero if a packet is active for the next forward step, ping-pong [4], [5]
-    kCntFlags = 6,
-    kCntHopsStep = 7,
-    kCntVipCnt0 = 8,  // ViP list fill, ping-pong [8], [9]
-    kCntRec = 10,
-    kCntDone = 11,    // set once a forward step finds no active packet; later launches of the step exit
-    kCntBytes = 12,   // algorithmic bytes moved by forward steps (for the roofline)
-    kCntTiles = 13,   // forward-step tiles processed
-    kCntDeep = 15,    // virtual particles of this forward step that landed inside their box
-    kCntN = 16
+    kCntFlags = 4,
+    kCntHopsStep = 5,
+    kCntRec = 6,
+    // lists filled during a launch
+    kCntVipCnt0 = 8,   // ViP list fill, ping-pong [8], [9]
+    kCntDeep = 10,     // virtual particles of this forward step that landed inside their box
+    // nonzero if a packet is active for the next forward step, ping-pong, a line each
+    kCntAct0 = 16,     // [16], [24]
+    // read at the start of every launch, written rarely
+    kCntDone = 32,     // set once a forward step finds no active packet; later launches of the step exit
+    kCntSerial = 33,   // stamp of hop 0 of the current RT step (stamps number the forward steps of the run)
+    // per-step tallies
+    kCntBytes = 40,    // algorithmic bytes moved by forward steps (for the roofline)
+    kCntTiles = 41,    // forward-step tiles processed
+    kCntN = 48
 };
 enum : long long { kFlagHopCap = 1, kFlagVipOverflow = 2, kFlagRecOverflow = 4, kFlagNonFinite = 8 };
 // units of the two fixed-point deposit accumulators, relative to the receiving particle's N_H
@@ -439,7 +448,6 @@ struct VipArgs {
     int hop, hop0, max_hops, K, nf, nrc, nec, max_depth;
     long long* dep;  // [N*nf][2] deposited photons of virtual-particle legs, fixed point
     uint64_t seed;
-    uint32_t step;
     double c2;
     const Vip* list;
     long long vip_cap;
@@ -463,7 +471,7 @@ struct VipArgs {
     int* head;
     long long rec_cap;
     int* hot;        // tiles that receive records in this forward step
-    int stamp, lgT;
+    int lgT;
     Vip* deep;       // virtual particles that landed inside their box, with their points
     double* deep_x;
     long long* cnt;
@@ -486,8 +494,8 @@ struct VipArgs {
 // is accepted.
 constexpr int kVipLanes = 16;
 
-__device__ inline bool vip_draw_group(const VipArgs& a, const Vip& q, bool live, int depth, int sub, int gshift,
-                                      double p[3]) {
+__device__ inline bool vip_draw_group(const VipArgs& a, uint32_t step, const Vip& q, bool live, int depth, int sub,
+                                      int gshift, double p[3]) {
     const double* ecs = (q.ec >= 0 && depth == 1) ? a.ecd + 3 * (static_cast<long long>(q.ec) * a.nec) : nullptr;
     const unsigned long long gm = (kVipLanes >= 64 ? ~0ull : ((1ull << kVipLanes) - 1ull)) << gshift;
     bool done = !live;
@@ -496,7 +504,7 @@ __device__ inline bool vip_draw_group(const VipArgs& a, const Vip& q, bool live,
         bool ok = false;
         double u[4] = {0.0, 0.0, 0.0, 0.0};
         if (!done) {
-            uniforms4(a.seed, q.tag, base + static_cast<uint32_t>(sub), a.step, q.ida, q.idb | static_cast<uint32_t>(depth), u);
+            uniforms4(a.seed, q.tag, base + static_cast<uint32_t>(sub), step, q.ida, q.idb | static_cast<uint32_t>(depth), u);
             ok = u[0] * u[0] + u[1] * u[1] + u[2] * u[2] <= 1.0;
             if (ok) ok = ecs ? nearest_direction(ecs, a.nec, u[0], u[1], u[2]) == q.ek
                              : in_cone(u[0], u[1], u[2], q.d[0], q.d[1], q.d[2], a.c2);
@@ -520,7 +528,7 @@ __global__ __launch_bounds__(256) void k_vip_sample(VipArgs a) {
     if (!a.hop0) {
         // Once one forward step has found nothing to move, every later launch
         // of this step must exit: the ping-pong counters it would read are stale.
-        if (a.cnt[kCntDone] != 0 || a.cnt[kCntAct0 + a.act_rd] == 0 || a.hop > a.max_hops) {
+        if (a.cnt[kCntDone] != 0 || a.cnt[kCntAct0 + kCntLine * a.act_rd] == 0 || a.hop > a.max_hops) {
             if (gid == 0) a.cnt[kCntDone] = 1;
             return;
         }
@@ -528,10 +536,11 @@ __global__ __launch_bounds__(256) void k_vip_sample(VipArgs a) {
     long long n = a.cnt[kCntVipCnt0 + a.list_rd];
     if (n > a.vip_cap) n = a.vip_cap;
     if (gid == 0) {
-        a.cnt[kCntAct0 + a.act_wr] = 0;
+        a.cnt[kCntAct0 + kCntLine * a.act_wr] = 0;
         a.cnt[kCntVipCnt0 + a.list_wr] = 0;
         a.cnt[kCntVips] += n;  // the first leg of every chain
     }
+    const uint32_t step = static_cast<uint32_t>(a.cnt[kCntSteps] - 1);  // the step counter counts this step
     const int lane = threadIdx.x & 63;
     const int sub = lane % kVipLanes;
     const int gshift = lane - sub;
@@ -545,7 +554,7 @@ __global__ __launch_bounds__(256) void k_vip_sample(VipArgs a) {
         Vip q = {};
         if (live) q = a.list[v];
         double p[3] = {0.0, 0.0, 0.0};
-        const bool found = vip_draw_group(a, q, live, 1, sub, gshift, p);
+        const bool found = vip_draw_group(a, step, q, live, 1, sub, gshift, p);
         bool inside = false;
         double xv[3] = {0.0, 0.0, 0.0};
         if (live && sub == 0) {
@@ -596,6 +605,8 @@ __global__ __launch_bounds__(256) void k_vip_chain(VipArgs a) {
     const long long nw = gridDim.x * 4LL;
     long long n = a.cnt[kCntDeep];
     if (n > a.vip_cap) n = a.vip_cap;
+    const uint32_t step = static_cast<uint32_t>(a.cnt[kCntSteps] - 1);
+    const int stamp = static_cast<int>(a.cnt[kCntSerial]) + a.hop;
     WaveKnn& L = lds[wv];
     const int K = a.K;
     for (long long v = gw; v < n; v += nw) {
@@ -612,7 +623,7 @@ __global__ __launch_bounds__(256) void k_vip_chain(VipArgs a) {
                 bool found = false;
                 for (uint32_t base = 0; base < kVipAttempts; base += 64) {
                     double u[4];
-                    uniforms4(a.seed, q.tag, base + lane, a.step, q.ida, q.idb | static_cast<uint32_t>(depth), u);
+                    uniforms4(a.seed, q.tag, base + lane, step, q.ida, q.idb | static_cast<uint32_t>(depth), u);
                     bool ok = u[0] * u[0] + u[1] * u[1] + u[2] * u[2] <= 1.0;
                     if (ok) ok = in_cone(u[0], u[1], u[2], q.d[0], q.d[1], q.d[2], a.c2);
                     const unsigned long long b = __ballot(ok);
@@ -722,7 +733,7 @@ __global__ __launch_bounds__(256) void k_vip_chain(VipArgs a) {
                     rc.j = static_cast<int>(jk);
                     rc.o = q.nu * a.nrc + r;
                     push_record(a.rec, a.rec_next, a.head, idx1 + w8, rc);
-                    a.hot[jk >> a.lgT] = a.stamp;
+                    a.hot[jk >> a.lgT] = stamp;
                 }
                 break;
             }
@@ -773,7 +784,6 @@ struct HopArgs {
     long long N;
     int G, nrc, nf, K, rr_bin, rr_on, T, lgT;
     int hop, hop0, max_hops;
-    int stamp;                    // of this forward step
     const double* pos;
     const int* rev_off;
     const unsigned int* rev_ik;   // receiver-sorted edges: sender << 6 | position in the sender's list
@@ -950,7 +960,7 @@ struct HopLds {
 template <typename R, typename DT>
 __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
     if (!a.hop0) {
-        if (a.cnt[kCntDone] != 0 || a.cnt[kCntAct0 + a.act_rd] == 0) {
+        if (a.cnt[kCntDone] != 0 || a.cnt[kCntAct0 + kCntLine * a.act_rd] == 0) {
             if (blockIdx.x == 0 && threadIdx.x == 0) a.cnt[kCntDone] = 1;
             return;
         }
@@ -969,7 +979,8 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
         a.cnt[kCntDeep] = 0;  // and its virtual particles all handled
     }
     const long long tile = xcd_block(blockIdx.x, gridDim.x);
-    if (!a.hop0 && a.hot_rd[tile] != a.stamp) return;
+    const int stamp = static_cast<int>(a.cnt[kCntSerial]) + a.hop;  // of this forward step
+    if (!a.hop0 && a.hot_rd[tile] != stamp) return;
 
     constexpr bool f32 = sizeof(R) == 4;
     constexpr unsigned long long rsz = sizeof(R);
@@ -1067,7 +1078,7 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
         }
         const long long e_t0 = a.rev_off[j0], e_t1 = a.rev_off[jend];
         const long long my0 = valid ? a.rev_off[j] : 0, my1 = valid ? a.rev_off[j + 1] : 0;
-        const unsigned int prev = static_cast<unsigned int>(a.stamp - 1);
+        const unsigned int prev = static_cast<unsigned int>(stamp - 1);
         const DT gm = static_cast<DT>(nrc >= 8 * static_cast<int>(sizeof(DT)) ? ~DT(0) : ((DT(1) << nrc) - DT(1)));
         const int gbase_s = lane & ~(G - 1);
         const unsigned long long gmask_s = G >= 64 ? ~0ull : ((1ull << G) - 1ull);
@@ -1339,7 +1350,7 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
     wave_sync();  // the gather's LDS is free again
     const bool tile_act = __ballot(act) != 0;
     if (valid && o == 0 && hd >= 0) a.head[j] = -1;  // every lane of j has read its records
-    if (tile_act && threadIdx.x == 0) a.hot_wr[tile] = a.stamp + 1;  // its leaving packets empty their bins
+    if (tile_act && threadIdx.x == 0) a.hot_wr[tile] = stamp + 1;  // its leaving packets empty their bins
     const int gbase = lane & ~(G - 1);
     const unsigned long long gmaskG = G >= 64 ? ~0ull : ((1ull << G) - 1ull);
     const bool pact = ((__ballot(act) >> gbase) & gmaskG) != 0;
@@ -1388,7 +1399,7 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
         // transposed, lane o holds the delivery word of neighbour k0 + o
         const unsigned long long cs = send ? cmw : 0ull;
         Inbox<DT> ib;
-        ib.tag = (static_cast<unsigned int>(a.stamp) << 1) | (offdiag ? 1u : 0u);
+        ib.tag = (static_cast<unsigned int>(stamp) << 1) | (offdiag ? 1u : 0u);
         for (int k0 = 0; k0 < K; k0 += G) {
             const DT w = group_transpose(static_cast<DT>((cs >> k0) & gmaskG), G, o);
             const int k = k0 + o;
@@ -1400,7 +1411,7 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
                 else
                     e = __double_as_longlong(fj[k].w);
                 a.in_wr[e] = ib;
-                a.hot_wr[nj[k] >> a.lgT] = a.stamp + 1;
+                a.hot_wr[nj[k] >> a.lgT] = stamp + 1;
                 nbytes += sizeof(Inbox<DT>) + 4;
             }
         }
@@ -1462,7 +1473,7 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
     }
     // whether a packet moves next step (a flag, no count: plain stores), and
     // the tile's running tallies of packets moved, bytes and steps run
-    if (tile_act && lane == 0) a.cnt[kCntAct0 + a.act_wr] = 1;
+    if (tile_act && lane == 0) a.cnt[kCntAct0 + kCntLine * a.act_wr] = 1;
     const unsigned long long nupd = __popcll(__ballot(departed));
     const unsigned long long wb = wave_sum_u64(nbytes);
     if (lane < 3) a.part[3 * tile + lane] = tally + (lane == 0 ? nupd : (lane == 1 ? wb : 1ull));

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -120,6 +121,9 @@ struct rt_ctx {
     long long* inst_chunk0 = nullptr;
     long long step = 0;
     long long last_hops = 8;   // forward steps of the previous RT step
+    // forward steps 1..n of an RT step, captured once per n and replayed
+    std::map<int, hipGraphExec_t> hop_graphs;
+    bool graphs_ok = true;
     // timing
     bool timing = false;
     std::vector<hipEvent_t> ev;
@@ -240,7 +244,6 @@ rt_status launch_hop(rt_ctx* c, int hop) {
     a.wrcf = c->wrcf;
     a.dt = c->p.dt;
     a.lgT = c->lgT;
-    a.stamp = static_cast<int>(c->serial + hop);
     a.ngb = c->ngb;
     const int rd = (hop + 1) & 1, wr = hop & 1;
     a.pk = static_cast<Bin4<R>*>(c->pk);
@@ -290,7 +293,6 @@ rt_status launch_vip(rt_ctx* c, int hop) {
     a.max_depth = c->p.max_vip_depth;
     a.dep = c->dep;
     a.seed = c->p.seed;
-    a.step = static_cast<uint32_t>(c->step);
     a.c2 = c->c2;
     a.list = c->vip[hop & 1];
     a.vip_cap = c->vip_cap;
@@ -314,7 +316,6 @@ rt_status launch_vip(rt_ctx* c, int hop) {
     a.head = c->head[hop & 1];
     a.rec_cap = c->rec_cap;
     a.hot = c->hot[hop & 1];
-    a.stamp = static_cast<int>(c->serial + hop);
     a.lgT = c->lgT;
     a.deep = c->deep;
     a.deep_x = c->deep_x;
@@ -330,10 +331,11 @@ rt_status launch_vip(rt_ctx* c, int hop) {
     return RT_OK;
 }
 
-__global__ void k_step_reset(long long* cnt) {
+__global__ void k_step_reset(long long* cnt, long long serial) {
     if (threadIdx.x == 0) {
+        cnt[kCntSerial] = serial;
         cnt[kCntAct0] = 0;
-        cnt[kCntAct0 + 1] = 0;
+        cnt[kCntAct0 + kCntLine] = 0;
         cnt[kCntVipCnt0] = 0;
         cnt[kCntVipCnt0 + 1] = 0;
         cnt[kCntRec] = 0;
@@ -387,6 +389,44 @@ float elapsed(rt_ctx* c, size_t slot) {
     return ms;
 }
 
+// Forward steps 1..n as one graph.  Their launches do not change from step to
+// step (the step index and the stamps are read from device counters), so a
+// graph is captured once per n and replayed.  If capture is not possible the
+// launches are made one by one.
+rt_status launch_hops_graph(rt_ctx* c, int n, bool* done) {
+    *done = false;
+    if (!c->graphs_ok) return RT_OK;
+    auto it = c->hop_graphs.find(n);
+    if (it == c->hop_graphs.end()) {
+        if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipGetLastError();
+            c->graphs_ok = false;
+            return RT_OK;
+        }
+        rt_status st = RT_OK;
+        for (int q = 1; q <= n && st == RT_OK; ++q) {
+            st = launch_vip(c, q);
+            if (st == RT_OK) st = launch_hop_any(c, q);
+        }
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(c->stream, &g);
+        hipGraphExec_t ex = nullptr;
+        if (st != RT_OK || ec != hipSuccess || !g || hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipGetLastError();
+            c->graphs_ok = false;
+            c->sticky = false;
+            c->err.clear();
+            return RT_OK;
+        }
+        (void)hipGraphDestroy(g);
+        it = c->hop_graphs.emplace(n, ex).first;
+    }
+    HIPCHK(c, hipGraphLaunch(it->second, c->stream));
+    *done = true;
+    return RT_OK;
+}
+
 // One RT step (sections 2.1 and 2.2): rotations, emission, forward steps
 // until no packet is active, chemistry, ledger.
 rt_status one_step(rt_ctx* c, bool* hopcap) {
@@ -403,7 +443,7 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
     TRY(fill_i32(c, c->head[1], c->N, -1));
     TRY(fill_f64(c, c->A, c->N * c->nf, 0.0));
     TRY(fill_f64(c, c->P, c->N * c->nf, 0.0));
-    hipLaunchKernelGGL(k_step_reset, dim3(1), dim3(64), 0, c->stream, c->cnt);
+    hipLaunchKernelGGL(k_step_reset, dim3(1), dim3(64), 0, c->stream, c->cnt, c->serial);
     HIPCHK(c, hipGetLastError());
     TRY(time_begin(c, 0));
     StepBeginArgs sb{};
@@ -470,7 +510,9 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
         if (h <= c->p.max_hops) {
             const int hend = std::min(h + batch - 1, c->p.max_hops);
             if (c->p.hop_batch <= 0) batch = 1;
-            for (int q = h; q <= hend; ++q) {
+            bool graphed = false;
+            if (!c->timing && h == 1 && hend > 1) TRY(launch_hops_graph(c, hend, &graphed));
+            for (int q = h; q <= hend && !graphed; ++q) {
                 TRY(time_begin(c, 2 + 2 * q));
                 TRY(launch_vip(c, q));
                 TRY(time_end(c, 2 + 2 * q));
@@ -483,7 +525,7 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
         HIPCHK(c, hipMemcpyAsync(c->h_cnt, c->cnt, sizeof(long long) * kCntN, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         H = c->h_cnt[kCntHopsStep];
-        const long long act = c->h_cnt[kCntAct0 + ((H + 1) & 1)];
+        const long long act = c->h_cnt[kCntAct0 + kCntLine * ((H + 1) & 1)];
         if (act == 0) break;
         if (H >= c->p.max_hops) {
             *hopcap = true;
@@ -1162,6 +1204,11 @@ rt_status rt_get_state_blob(rt_ctx* c, void* blob, size_t* bytes) {
     HIPCHK(c, hipMemcpy(q, c->scale, 8 * c->n_inst * c->nf, hipMemcpyDeviceToHost));
     q += 8 * c->n_inst * c->nf;
     HIPCHK(c, hipMemcpy(q, c->cnt, 8 * kCntN, hipMemcpyDeviceToHost));
+    {  // the byte and tile tallies are timing diagnostics, not state
+        long long* cq = reinterpret_cast<long long*>(q);
+        cq[kCntBytes] = 0;
+        cq[kCntTiles] = 0;
+    }
     *bytes = need;
     return RT_OK;
 }
@@ -1215,6 +1262,8 @@ rt_status rt_set_state_blob(rt_ctx* c, const void* blob, size_t bytes) {
 void rt_destroy(rt_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    for (auto& kv : c->hop_graphs) (void)hipGraphExecDestroy(kv.second);
+    c->hop_graphs.clear();
     for (auto& b : c->owned) {
         if (c->p.dealloc)
             c->p.dealloc(c->p.alloc_user, b.p);

@@ -128,8 +128,9 @@ class Context:
         self.nf = int(p["n_freq"])
         self.G = int(p["n_rc"]) * self.nf
         self.n_inst = int(cfg["inst_off"].shape[0] - 1)
-        self.stream = torch.cuda.current_stream()
         self._dev = torch.cuda.current_device()
+        # a stream of its own (default priority): the library captures graphs on it
+        self.stream = torch.cuda.Stream(device=self._dev)
         if torch_alloc:
             dev, strm = self._dev, self.stream
 

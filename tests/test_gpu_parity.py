@@ -161,6 +161,26 @@ def test_determinism_bitwise():
         assert a.get_blob() == b.get_blob()
 
 
+def test_graph_replay_matches_eager():
+    # Forward steps 1..n of a step run as a captured graph unless timing is on
+    # (then every launch is made by hand).  Replays of the cached graphs, with
+    # eager work and host synchronisation between them, must give bit for bit
+    # the state of the eager launches after every step.
+    cfg = I.stromgren(10, rr=True, n_ngb=32, dt_myr=0.5)
+    RT = _rt()
+    for prec in ("fp64", "fp32"):
+        g = RT.Context(cfg, precision=prec)
+        e = RT.Context(cfg, precision=prec)
+        e.set_timing(True)
+        for k in range(8):
+            g.step(1)
+            e.step(1)
+            assert g.get_blob() == e.get_blob(), (prec, k)
+        sg, se = g.state(), e.state()
+        for key in ("xHI", "T", "A", "P", "ledger"):
+            assert np.array_equal(sg[key], se[key]), (prec, key)
+
+
 def test_checkpoint_restore_bitwise():
     cfg = I.stromgren(10, rr=True, n_ngb=32, dt_myr=0.5)
     for prec in ("fp64", "fp32"):
