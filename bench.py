@@ -6,7 +6,9 @@ source, N_ngb = 48, N_TC = N_RC = N_EC = 8, a source bin and an RR bin,
 dt = 0.1 Myr, 500 steps in all).  A step is one RT step: emission, all forward
 steps until no packet moves, chemistry, RR emission and the photon ledger.
 
-The FP32-transport run is the headline; the same steps in FP64 give the
+The FP32-transport run is the headline (forward steps replayed from captured
+graphs); a second FP32 run with per-launch HIP events gives the time split and
+the roofline of the forward-step kernel; the same steps in FP64 give the
 comparison, the packet-update count (work is credited as counted on the FP64
 run) and the x_HI reference for the FP32 error.  Prints one JSON line.
 """
@@ -124,8 +126,10 @@ def main():
         ctx.close()
         return res
 
-    r32 = run("fp32", True)
+    r32 = run("fp32", False)
     print(f"fp32: {K} steps in {r32['t']:.3f} s, {r32['updates']} updates", file=sys.stderr, flush=True)
+    r32t = run("fp32", True)
+    print(f"fp32 timed: {K} steps in {r32t['t']:.3f} s", file=sys.stderr, flush=True)
     r64 = None
     if not args.no_fp64:
         r64 = run("fp64", False)
@@ -135,7 +139,7 @@ def main():
     led = r32["state"]["ledger"]
     E, A, X, R, F = np.moveaxis(led, -1, 0)
     resid = float(np.max(np.abs(E - A - X - R - F) / np.maximum(E, 1e-300)))
-    tm = r32["timing"]
+    tm = r32t["timing"]
     launches = max(tm["hop_launches"], 1)
     avg_ms = tm["hop_ms"] / launches
     bytes_per_launch = tm["hop_bytes_total"] / launches
@@ -181,6 +185,7 @@ def main():
         "fp32_vs_fp64": None,
         "ledger_residual_fp32": resid,
         "time_split_ms": {k: tm[k] for k in ("hop_ms", "vip_ms", "chem_ms", "emit_ms", "ledger_ms")},
+        "ms_per_step_timed_run": r32t["t"] / K * 1e3,
     }
     if r64:
         dx = float(np.max(np.abs(r32["state"]["xHI"] - r64["state"]["xHI"])))
