@@ -122,7 +122,7 @@ def main():
         t = time.perf_counter() - t0
         st = ctx.state()
         tm = ctx.timing() if timing else None
-        res = dict(t=t, updates=int(st["counters"][3]) - u0, state=st, timing=tm)
+        res = dict(t=t, updates=int(st["counters"][3]) - u0, state=st, timing=tm, shape=ctx.hop_shape())
         ctx.close()
         return res
 
@@ -166,6 +166,7 @@ def main():
             "particles": int(cfg["pos"].shape[0]),
             "slots": int(cfg["pos"].shape[0]) * 16,
             "transport": "fp32 with TwoSum merge sums; chemistry and ledger fp64",
+            "hop_shape": r32["shape"],
         },
         "roofline": {
             "kernel": "k_hop<float> (forward step: gather, merge, cone masks)",

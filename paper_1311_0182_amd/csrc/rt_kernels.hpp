@@ -915,10 +915,25 @@ __device__ inline W group_transpose(W x, int G, int o) {
 // Afterwards the same bytes hold, for the particles with active packets, the
 // neighbour offsets (receiver-sorted edge index in the fourth component), the
 // neighbours and the delivery words.
-template <typename R, typename DT>
+// Shapes of a forward-step workgroup the autotuner chooses among: incoming
+// edges staged per chunk, and (edge, packet) pairs gathered per round in FP32
+// (half as many in FP64, at least 64).  Every shape adds a slot's contributions in the same
+// order, so they give identical results.
+template <int E, int P>
+struct HopShape {
+    static constexpr int kEdges = E;
+    static constexpr int kPairs32 = P;
+};
+using HopShape0 = HopShape<256, 128>;
+using HopShape1 = HopShape<128, 64>;
+using HopShape2 = HopShape<512, 256>;
+constexpr int kHopShapes = 3;
+
+template <typename R, typename DT, typename S = HopShape0>
 struct HopLds {
-    static constexpr int kEdges = 256;                          // edges staged at a time
-    static constexpr int kPairs = sizeof(R) == 4 ? 128 : 64;    // pairs gathered at a time
+    static constexpr int kEdges = S::kEdges;                                       // edges staged at a time
+    // pairs gathered at a time (a multiple of the wavefront)
+    static constexpr int kPairs = sizeof(R) == 4 ? S::kPairs32 : (S::kPairs32 / 2 > 64 ? S::kPairs32 / 2 : 64);
     static constexpr size_t ik = 0;
     static constexpr size_t tag = ik + 4 * kEdges;    // raw inbox words, loaded straight into LDS
     static constexpr size_t mw = tag + 4 * kEdges;    // [sizeof(DT)/4][kEdges] mask words
@@ -957,7 +972,7 @@ struct HopLds {
 // marks the tiles that will receive it.  Hop 0 of a step also merges what
 // stays (clocks carried over by -dt), the recombination photons of the last
 // chemistry step (section 2.2) and the emission records.
-template <typename R, typename DT>
+template <typename R, typename DT, typename S>
 __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
     if (!a.hop0) {
         if (a.cnt[kCntDone] != 0 || a.cnt[kCntAct0 + kCntLine * a.act_rd] == 0) {
@@ -985,7 +1000,7 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
     constexpr bool f32 = sizeof(R) == 4;
     constexpr unsigned long long rsz = sizeof(R);
     using V4 = typename std::conditional<f32, float4, double4>::type;
-    using L = HopLds<R, DT>;
+    using L = HopLds<R, DT, S>;
     constexpr int kP = L::kPairs;
     extern __shared__ __align__(32) unsigned char lds[];
 

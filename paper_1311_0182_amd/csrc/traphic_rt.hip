@@ -123,6 +123,14 @@ struct rt_ctx {
     long long last_hops = 8;   // forward steps of the previous RT step
     // forward steps 1..n of an RT step, captured once per n and replayed
     std::map<int, hipGraphExec_t> hop_graphs;
+    // autotuner of the forward-step shape: -1 tune once work is representative
+    int hop_shape = 0;
+    int tune_mode = -1;        // -1 automatic, -2 tune now, 0..kHopShapes-1 fixed by the caller
+    int tune_steps_left = 3;   // RT steps that time the shapes (alternating per forward step)
+    double tune_ms[kHopShapes] = {0, 0, 0};
+    long long tune_n[kHopShapes] = {0, 0, 0};
+    bool tuned = false;
+    bool tuning_now = false;   // this RT step times the shapes
     bool graphs_ok = true;
     // timing
     bool timing = false;
@@ -206,7 +214,7 @@ void direction_set(int n, std::vector<double>& u) {
 
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
-template <typename R, typename DT>
+template <typename R, typename DT, typename S>
 rt_status launch_hop(rt_ctx* c, int hop) {
     HopArgs<R, DT> a{};
     a.N = c->N;
@@ -269,16 +277,25 @@ rt_status launch_hop(rt_ctx* c, int hop) {
     a.part = c->part;
     a.act_rd = hop & 1;
     a.act_wr = (hop + 1) & 1;
-    const size_t lds = HopLds<R, DT>::bytes(c->tileT, c->K);
-    hipLaunchKernelGGL((k_hop<R, DT>), dim3(static_cast<unsigned>(c->ntiles)), dim3(64), lds, c->stream, a);
+    const size_t lds = HopLds<R, DT, S>::bytes(c->tileT, c->K);
+    hipLaunchKernelGGL((k_hop<R, DT, S>), dim3(static_cast<unsigned>(c->ntiles)), dim3(64), lds, c->stream, a);
     HIPCHK(c, hipGetLastError());
     return RT_OK;
 }
 
 
-rt_status launch_hop_any(rt_ctx* c, int hop) {
-    if (c->f32) return c->dl64 ? launch_hop<float, unsigned long long>(c, hop) : launch_hop<float, unsigned int>(c, hop);
-    return c->dl64 ? launch_hop<double, unsigned long long>(c, hop) : launch_hop<double, unsigned int>(c, hop);
+template <typename S>
+rt_status launch_hop_shape(rt_ctx* c, int hop) {
+    if (c->f32) return c->dl64 ? launch_hop<float, unsigned long long, S>(c, hop) : launch_hop<float, unsigned int, S>(c, hop);
+    return c->dl64 ? launch_hop<double, unsigned long long, S>(c, hop) : launch_hop<double, unsigned int, S>(c, hop);
+}
+
+// shape: the tuned one, or (during tuning) the one this forward step times
+rt_status launch_hop_any(rt_ctx* c, int hop, int shape = -1) {
+    if (shape < 0) shape = c->hop_shape;
+    if (shape == 1) return launch_hop_shape<HopShape1>(c, hop);
+    if (shape == 2) return launch_hop_shape<HopShape2>(c, hop);
+    return launch_hop_shape<HopShape0>(c, hop);
 }
 
 rt_status launch_vip(rt_ctx* c, int hop) {
@@ -369,7 +386,7 @@ rt_status fill_f64(rt_ctx* c, double* p, long long n, double v) {
     } while (0)
 
 rt_status time_begin(rt_ctx* c, size_t slot) {
-    if (!c->timing) return RT_OK;
+    if (!c->timing && !c->tuning_now) return RT_OK;
     while (c->ev.size() < 2 * (slot + 1)) {
         hipEvent_t e;
         HIPCHK(c, hipEventCreate(&e));
@@ -379,7 +396,7 @@ rt_status time_begin(rt_ctx* c, size_t slot) {
     return RT_OK;
 }
 rt_status time_end(rt_ctx* c, size_t slot) {
-    if (!c->timing) return RT_OK;
+    if (!c->timing && !c->tuning_now) return RT_OK;
     HIPCHK(c, hipEventRecord(c->ev[2 * slot + 1], c->stream));
     return RT_OK;
 }
@@ -430,6 +447,10 @@ rt_status launch_hops_graph(rt_ctx* c, int n, bool* done) {
 // One RT step (sections 2.1 and 2.2): rotations, emission, forward steps
 // until no packet is active, chemistry, ledger.
 rt_status one_step(rt_ctx* c, bool* hopcap) {
+    // The autotuner times the forward-step shapes on steps whose work is
+    // representative (at least 16 forward steps in the previous step),
+    // alternating the shape from one forward step to the next.
+    c->tuning_now = c->tune_mode < 0 && !c->tuned && (c->last_hops >= 16 || c->tune_mode == -2);
     // stamps are 30-bit: restart them (and forget every old mark) long before they wrap
     if (c->serial + c->p.max_hops + 2 >= (1ll << 30)) {
         for (int b = 0; b < 2; ++b) {
@@ -511,13 +532,13 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
             const int hend = std::min(h + batch - 1, c->p.max_hops);
             if (c->p.hop_batch <= 0) batch = 1;
             bool graphed = false;
-            if (!c->timing && h == 1 && hend > 1) TRY(launch_hops_graph(c, hend, &graphed));
+            if (!c->timing && !c->tuning_now && h == 1 && hend > 1) TRY(launch_hops_graph(c, hend, &graphed));
             for (int q = h; q <= hend && !graphed; ++q) {
                 TRY(time_begin(c, 2 + 2 * q));
                 TRY(launch_vip(c, q));
                 TRY(time_end(c, 2 + 2 * q));
                 TRY(time_begin(c, 3 + 2 * q));
-                TRY(launch_hop_any(c, q));
+                TRY(launch_hop_any(c, q, c->tuning_now ? q % kHopShapes : -1));
                 TRY(time_end(c, 3 + 2 * q));
             }
             h = hend + 1;
@@ -609,6 +630,23 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
     c->step += 1;
     HIPCHK(c, hipMemcpyAsync(c->h_cnt, c->cnt, sizeof(long long) * kCntN, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->tuning_now) {
+        for (long long q = 1; q <= H; ++q) {
+            c->tune_ms[q % kHopShapes] += elapsed(c, 3 + 2 * q);
+            c->tune_n[q % kHopShapes] += 1;
+        }
+        if (--c->tune_steps_left <= 0) {
+            int best = 0;
+            for (int k = 1; k < kHopShapes; ++k)
+                if (c->tune_n[k] > 0 && c->tune_ms[k] / c->tune_n[k] < c->tune_ms[best] / std::max(1ll, c->tune_n[best]))
+                    best = k;
+            c->hop_shape = best;
+            c->tuned = true;
+            for (auto& kv : c->hop_graphs) (void)hipGraphExecDestroy(kv.second);
+            c->hop_graphs.clear();
+        }
+        c->tuning_now = false;
+    }
     if (c->timing) {
         c->tm[4] += elapsed(c, 0);
         c->tm[3] += elapsed(c, 1);
@@ -1161,6 +1199,37 @@ rt_status rt_get_timing(rt_ctx* c, double* out, int32_t n) {
     double v[9] = {c->tm[0], c->tm[1], c->tm[2], c->tm[3], c->tm[4], c->tm[5], static_cast<double>(h[kCntBytes]),
                    static_cast<double>(h[kCntTiles]), dense};
     for (int k = 0; k < n && k < 9; ++k) out[k] = v[k];
+    return RT_OK;
+}
+
+rt_status rt_set_hop_shape(rt_ctx* c, int32_t shape) {
+    if (!c || shape < -2 || shape >= kHopShapes) return RT_EINVAL;
+    if (c->sticky) return RT_EDEVICE;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (auto& kv : c->hop_graphs) (void)hipGraphExecDestroy(kv.second);
+    c->hop_graphs.clear();
+    c->tune_mode = shape;
+    if (shape >= 0) {
+        c->hop_shape = shape;
+        c->tuned = true;
+    } else {
+        c->hop_shape = 0;
+        c->tuned = false;
+        c->tune_steps_left = 3;
+        for (int k = 0; k < kHopShapes; ++k) {
+            c->tune_ms[k] = 0.0;
+            c->tune_n[k] = 0;
+        }
+    }
+    return RT_OK;
+}
+
+rt_status rt_get_hop_shape(rt_ctx* c, int32_t* shape, int32_t* tuned, double* ms_per_launch) {
+    if (!c) return RT_EINVAL;
+    if (shape) *shape = c->hop_shape;
+    if (tuned) *tuned = (c->tuned && c->tune_mode < 0) ? 1 : 0;
+    if (ms_per_launch)
+        for (int k = 0; k < kHopShapes; ++k) ms_per_launch[k] = c->tune_n[k] ? c->tune_ms[k] / c->tune_n[k] : 0.0;
     return RT_OK;
 }
 

@@ -25,7 +25,8 @@ DEALLOC_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 EXPORTS = ["rt_init", "rt_add_sources", "rt_step", "rt_get_state", "rt_get_bins", "rt_get_neighbours",
            "rt_n_emitters", "rt_get_emitter_neighbours", "rt_get_cone_masks", "rt_get_pending_rr",
-           "rt_set_timing", "rt_get_timing", "rt_get_state_blob", "rt_set_state_blob", "rt_destroy",
+           "rt_set_timing", "rt_get_timing", "rt_set_hop_shape", "rt_get_hop_shape", "rt_get_state_blob",
+           "rt_set_state_blob", "rt_destroy",
            "rt_last_error"]
 
 
@@ -86,6 +87,10 @@ def load():
     L.rt_set_timing.argtypes = [C.c_void_p, C.c_int32]
     L.rt_get_timing.restype = C.c_int
     L.rt_get_timing.argtypes = [C.c_void_p, dp, C.c_int32]
+    L.rt_set_hop_shape.restype = C.c_int
+    L.rt_set_hop_shape.argtypes = [C.c_void_p, C.c_int32]
+    L.rt_get_hop_shape.restype = C.c_int
+    L.rt_get_hop_shape.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32), dp]
     L.rt_get_state_blob.restype = C.c_int
     L.rt_get_state_blob.argtypes = [C.c_void_p, C.c_void_p, P(C.c_size_t)]
     L.rt_set_state_blob.restype = C.c_int
@@ -237,6 +242,15 @@ class Context:
         keys = ["hop_ms", "hop_launches", "vip_ms", "chem_ms", "emit_ms", "ledger_ms", "hop_bytes_total",
                 "hop_tiles_total", "dense_bytes_per_hop"]
         return {k: float(out[i]) for i, k in enumerate(keys)}
+
+    def set_hop_shape(self, shape=-1):
+        self._check(load().rt_set_hop_shape(self.h, int(shape)))
+
+    def hop_shape(self):
+        sh, tu = C.c_int32(0), C.c_int32(0)
+        ms = np.zeros(3)
+        self._check(load().rt_get_hop_shape(self.h, C.byref(sh), C.byref(tu), _p(ms, C.c_double)))
+        return dict(shape=int(sh.value), tuned=bool(tu.value), ms_per_launch=[float(x) for x in ms])
 
     def get_blob(self):
         n = C.c_size_t(0)

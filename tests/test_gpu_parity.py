@@ -181,6 +181,30 @@ def test_graph_replay_matches_eager():
             assert np.array_equal(sg[key], se[key]), (prec, key)
 
 
+def test_hop_shapes_identical_and_tuner():
+    # Every workgroup shape of the forward step adds a slot's contributions in
+    # the same order, and the tuner alternates shapes while it times them: all
+    # runs must agree bit for bit.
+    cfg = I.stromgren(16, rr=True, n_ngb=32, dt_myr=0.5)
+    RT = _rt()
+    for prec in ("fp64", "fp32"):
+        blobs = []
+        for shape in (0, 1, 2, -2):
+            ctx = RT.Context(cfg, precision=prec)
+            ctx.set_hop_shape(shape)
+            ctx.step(12)
+            blobs.append(ctx.get_blob())
+            info = ctx.hop_shape()
+            say(prec, "shape", shape, info)
+            if shape >= 0:
+                assert info["shape"] == shape and not info["tuned"]
+            else:
+                assert info["tuned"] and 0 <= info["shape"] <= 2 and all(m > 0 for m in info["ms_per_launch"])
+        assert all(b == blobs[0] for b in blobs[1:]), prec
+    with pytest.raises(RT.RTError):
+        RT.Context(cfg).set_hop_shape(3)
+
+
 def test_checkpoint_restore_bitwise():
     cfg = I.stromgren(10, rr=True, n_ngb=32, dt_myr=0.5)
     for prec in ("fp64", "fp32"):
