@@ -176,6 +176,23 @@ def batched(n_inst=64, side_lo=8, side_hi=48, n_ngb=48, n_steps=100, seed_k=4, r
     return _pack(f"batched{n_inst}", params, [SIGMA_13P6] * n_freq, [0.0] * n_freq, insts, src, n_steps)
 
 
+def instance(cfg, k):
+    """Instance k of a batch as a workload of its own (same particles, box,
+    sources and parameters)."""
+    lo, hi = int(cfg["inst_off"][k]), int(cfg["inst_off"][k + 1])
+    src = cfg["sources"]
+    sel = src["inst"] == k
+    sources = dict(inst=np.zeros(int(sel.sum()), dtype=np.int32), kind=src["kind"][sel].copy(),
+                   pos=np.ascontiguousarray(src["pos"][sel]), rate=np.ascontiguousarray(src["rate"][sel]),
+                   n_side=src["n_side"][sel].copy())
+    out = dict(cfg)
+    out.update(name=f'{cfg["name"]}_{k}', inst_off=np.array([0, hi - lo], dtype=np.int64),
+               box=np.ascontiguousarray(cfg["box"][k:k + 1]), sources=sources)
+    for key in ("pos", "nH", "NH", "xHI", "T"):
+        out[key] = np.ascontiguousarray(cfg[key][lo:hi])
+    return out
+
+
 def chain(n=12, spacing_kpc=0.1, n_h=1e-3, x_hi=1e-3, **pkw):
     """A 1-D chain of particles along x with two neighbours each and a plane
     front on the x = 0 face: used to check attenuation exp(-sigma n sum l)."""
