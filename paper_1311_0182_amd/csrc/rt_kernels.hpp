@@ -833,11 +833,12 @@ struct HopArgs {
     int act_rd, act_wr;
 };
 
+// Sums of one bin's merge: photons (with a TwoSum compensation term in FP32)
+// and the photon-weighted direction and clock.
 template <typename R>
 struct Acc {
     R n, sx, sy, sz, sc;
-    // compensation terms (FP32 only)
-    R en, ex, ey, ez, ec;
+    R en;  // compensation of n (FP32 only)
 };
 
 template <typename R>
@@ -849,21 +850,47 @@ __device__ inline void tsum(R& s, R& e, R x) {
     s = t;
 }
 
+// Adds a packet given as its photons n and the products n d and n c.  The
+// photon count is TwoSum-compensated in FP32; the weighted direction and clock
+// only enter normalised means and are summed plainly.
+template <typename R>
+__device__ inline void acc_addp(Acc<R>& a, R n, R ndx, R ndy, R ndz, R nc) {
+    if constexpr (sizeof(R) == 4)
+        tsum(a.n, a.en, n);
+    else
+        a.n += n;
+    a.sx += ndx;
+    a.sy += ndy;
+    a.sz += ndz;
+    a.sc += nc;
+}
+
 template <typename R>
 __device__ inline void acc_add(Acc<R>& a, R n, R dx, R dy, R dz, R c) {
-    if constexpr (sizeof(R) == 4) {
-        tsum(a.n, a.en, n);
-        tsum(a.sx, a.ex, n * dx);
-        tsum(a.sy, a.ey, n * dy);
-        tsum(a.sz, a.ez, n * dz);
-        tsum(a.sc, a.ec, n * c);
-    } else {
-        a.n += n;
-        a.sx += n * dx;
-        a.sy += n * dy;
-        a.sz += n * dz;
-        a.sc += n * c;
-    }
+    acc_addp(a, n, n * dx, n * dy, n * dz, n * c);
+}
+
+// FP32 transport: absorbed N_in (1 - e^-tau) and transmitted N_in e^-tau parts
+// of a leg without branches.  Below tau = ln 2 the absorbed part is direct,
+// from the Taylor series of e^x - 1 to degree 9 (truncation below 2e-8
+// relative there); above, the transmitted part is direct, from the hardware
+// base-2 exponential.  The other part is the remainder, so they sum to N_in.
+__device__ inline void attenuate_f32(float nin, float tau, float& nabs, float& nout) {
+    const float x = -tau;
+    float p = 1.0f / 362880.0f;
+    p = __builtin_fmaf(p, x, 1.0f / 40320.0f);
+    p = __builtin_fmaf(p, x, 1.0f / 5040.0f);
+    p = __builtin_fmaf(p, x, 1.0f / 720.0f);
+    p = __builtin_fmaf(p, x, 1.0f / 120.0f);
+    p = __builtin_fmaf(p, x, 1.0f / 24.0f);
+    p = __builtin_fmaf(p, x, 1.0f / 6.0f);
+    p = __builtin_fmaf(p, x, 0.5f);
+    p = __builtin_fmaf(p, x, 1.0f);
+    const bool thin = tau < 0.693147182f;
+    const float d = thin ? -nin * (p * x) : nin * __builtin_amdgcn_exp2f(x * 1.44269502f);
+    const float rest = nin - d;
+    nabs = thin ? d : rest;
+    nout = thin ? rest : d;
 }
 
 template <typename R>
@@ -889,9 +916,33 @@ __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
 // Bit-matrix transpose inside each aligned group of G lanes (G a power of two
 // <= 64, the word type wide enough): lane o holds row o (bit c = entry (o, c),
 // c < G) and receives column o (bit e = entry (e, o)).  log2(G) rounds, each
-// exchanging the off-diagonal halves of 2j x 2j blocks between lanes o and o^j.
+// exchanging the off-diagonal halves of 2j x 2j blocks between lanes o and o^j;
+// the rounds are written out so that every mask and lane offset is a constant.
+template <int LJ, typename W>
+__device__ inline void transpose_round(W& x, int G, int o) {
+    constexpr int j = 1 << LJ;
+    if constexpr (j < 8 * static_cast<int>(sizeof(W))) {
+        if (j < G) {
+            constexpr unsigned long long kMask[6] = {0x5555555555555555ull, 0x3333333333333333ull,
+                                                     0x0F0F0F0F0F0F0F0Full, 0x00FF00FF00FF00FFull,
+                                                     0x0000FFFF0000FFFFull, 0x00000000FFFFFFFFull};
+            constexpr W m = static_cast<W>(kMask[LJ]);  // bits c with (c & j) == 0
+            const W y = __shfl_xor(x, j, 64);
+            // the lower lane of a pair keeps its bits in m and takes the
+            // partner's shifted up; the upper lane keeps ~m and takes them
+            // shifted down (selects as bit operations, no branch)
+            const W up = static_cast<W>(0) - static_cast<W>((o >> LJ) & 1);
+            const W keep = m ^ up;
+            const W ys = static_cast<W>(((y >> j) & up) | ((y << j) & ~up));
+            x = static_cast<W>((x & keep) | (ys & ~keep));
+        }
+    }
+}
+
+// The same transpose as a loop over the rounds, compact in code and registers:
+// the FP64 kernel, whose register budget is tight, runs faster with it.
 template <typename W>
-__device__ inline W group_transpose(W x, int G, int o) {
+__device__ inline W group_transpose_loop(W x, int G, int o) {
     for (int j = G >> 1; j > 0; j >>= 1) {
         W m;  // bits c with (c & j) == 0
         switch (j) {
@@ -905,6 +956,17 @@ __device__ inline W group_transpose(W x, int G, int o) {
         const W y = __shfl_xor(x, j, 64);
         x = (o & j) ? static_cast<W>((x & ~m) | ((y & ~m) >> j)) : static_cast<W>((x & m) | ((y & m) << j));
     }
+    return x;
+}
+
+template <typename W>
+__device__ inline W group_transpose(W x, int G, int o) {
+    transpose_round<5>(x, G, o);
+    transpose_round<4>(x, G, o);
+    transpose_round<3>(x, G, o);
+    transpose_round<2>(x, G, o);
+    transpose_round<1>(x, G, o);
+    transpose_round<0>(x, G, o);
     return x;
 }
 
@@ -949,7 +1011,7 @@ struct HopLds {
     }
     __host__ __device__ static constexpr size_t dw_off(int T, int K) { return ngb_off(T, K) + 4 * static_cast<size_t>(T) * K; }
     __host__ __device__ static constexpr size_t bytes(int T, int K) {
-        const size_t g = part + 2 * sizeof(R) * static_cast<size_t>(T);
+        const size_t g = part + sizeof(R) * (64 + static_cast<size_t>(T));
         const size_t f = dw_off(T, K) + sizeof(DT) * static_cast<size_t>(T) * K;
         return g > f ? g : f;
     }
@@ -1005,14 +1067,15 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
     extern __shared__ __align__(32) unsigned char lds[];
 
     const int G = a.G, nrc = a.nrc, K = a.K, T = a.T;
+    const int lgG = __builtin_ctz(G), lgN = __builtin_ctz(nrc);  // both powers of two
     const long long j0 = tile * T;
-    const int jl = threadIdx.x / G;
-    const int o = threadIdx.x - jl * G;
+    const int jl = threadIdx.x >> lgG;
+    const int o = threadIdx.x & (G - 1);
     const long long j = j0 + jl;
     const bool valid = jl < T && j < a.N;
     const long long s = j * G + o;
-    const int nu = o / nrc;
-    const int r = o - nu * nrc;
+    const int nu = o >> lgN;
+    const int r = o & (nrc - 1);
     const int inst = valid ? a.inst_of[j] : 0;
     const double U = f32 ? a.U[inst] : 1.0;
     const long long jend = (j0 + T < a.N) ? j0 + T : a.N;
@@ -1079,17 +1142,16 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
         unsigned char* e_nd = lds + L::nd;
         unsigned int* pdesc = reinterpret_cast<unsigned int*>(lds + L::desc);
         R* pval = reinterpret_cast<R*>(lds + L::val);  // [7][kP]
-        R* pa = reinterpret_cast<R*>(lds + L::part);   // per particle: FP32 kappa, FP64 x_HI
-        R* pb = pa + T;                                 // per particle: FP32 L/(c dt), FP64 n_H
-        if (threadIdx.x < T && j0 + threadIdx.x < a.N) {
-            const long long jj = j0 + threadIdx.x;
-            if constexpr (f32) {
-                pa[threadIdx.x] = a.kappa[jj];
-                pb[threadIdx.x] = a.clf[a.inst_of[jj]];
-            } else {
-                pa[threadIdx.x] = a.xHI[jj];
-                pb[threadIdx.x] = a.nH[jj];
-            }
+        // per (particle, bin): FP32 sigma_nu kappa, FP64 sigma_nu x_HI (the
+        // first product of the optical depth); per particle: FP32 L/(c dt), FP64 n_H
+        R* pa = reinterpret_cast<R*>(lds + L::part);
+        R* pb = pa + 64;
+        if (valid && r == 0) {
+            if constexpr (f32)
+                pa[jl * a.nf + nu] = a.sigmaf[nu] * a.kappa[j];
+            else
+                pa[jl * a.nf + nu] = a.sigma[nu] * a.xHI[j];
+            if (o == 0) pb[jl] = f32 ? static_cast<R>(a.clf[inst]) : static_cast<R>(a.nH[j]);
         }
         const long long e_t0 = a.rev_off[j0], e_t1 = a.rev_off[jend];
         const long long my0 = valid ? a.rev_off[j] : 0, my1 = valid ? a.rev_off[j + 1] : 0;
@@ -1153,7 +1215,7 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
                 for (int k = 0; k * G < 64; ++k) {
                     const int idx = k * G + o;
                     DT v = idx < len ? static_cast<DT>(e_ef[sb - cb + idx] & static_cast<DT>(gmask_s)) : DT(0);
-                    v = group_transpose(v, G, o);
+                    v = f32 ? group_transpose(v, G, o) : group_transpose_loop(v, G, o);
                     h |= (static_cast<unsigned long long>(v) & gmask_s) << (k * G);
                 }
                 return h;
@@ -1217,8 +1279,8 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
                     if (u < nr) {
                         const unsigned int d = pdesc[u];
                         const int t = static_cast<int>(d >> 14), pp = static_cast<int>(d >> 8) & 63, sl = static_cast<int>(d & 255u);
-                        const int so = sl % G;
-                        const long long tt = static_cast<long long>(e_ik[t] >> 6) * G + (so / nrc) * nrc + pp;
+                        const int so = sl & (G - 1);
+                        const long long tt = (static_cast<long long>(e_ik[t] >> 6) << lgG) + (so & ~(nrc - 1)) + pp;
                         qc[i] = a.mvc_rd[tt];
                         q[i] = a.mv_rd[tt];
                         v[i] = static_cast<const V4*>(a.rev_v)[cb + t];
@@ -1230,30 +1292,35 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
                     if (u < nr) {
                         const unsigned int d = pdesc[u];
                         const int t = static_cast<int>(d >> 14), sl = static_cast<int>(d & 255u);
-                        const int sjl = sl / G, so = sl - sjl * G, snu = so / nrc, sr = so - snu * nrc;
+                        const int sjl = sl >> lgG, so = sl & (G - 1), snu = so >> lgN, sr = so & (nrc - 1);
                         nbytes += 10 * rsz;
                         if (e_nd[t] && static_cast<int>(qc[i].s) != sr) {
                             pval[6 * kP + u] = R(-1);  // arrives in another cone of the particle
                             continue;
                         }
-                        const R aa = static_cast<R>(v[i].x) * q[i].x + static_cast<R>(v[i].y) * q[i].y +
-                                     static_cast<R>(v[i].z) * q[i].z;
-                        const R l = aa / sqrt(q[i].x * q[i].x + q[i].y * q[i].y + q[i].z * q[i].z);
-                        R tau, cl;
+                        R tau, cl, nabs, nout;
                         if constexpr (f32) {
-                            tau = a.sigmaf[snu] * pa[sjl] * l;
-                            cl = qc[i].c + l * pb[sjl];
+                            // path length: the offset along the packet's (unit) direction
+                            const float aa = __builtin_fmaf(v[i].z, q[i].z, __builtin_fmaf(v[i].y, q[i].y, v[i].x * q[i].x));
+                            const float qq = __builtin_fmaf(q[i].z, q[i].z, __builtin_fmaf(q[i].y, q[i].y, q[i].x * q[i].x));
+                            const float l = aa * __builtin_amdgcn_rsqf(qq);
+                            tau = pa[sjl * a.nf + snu] * l;
+                            cl = __builtin_fmaf(l, pb[sjl], qc[i].c);
+                            attenuate_f32(q[i].n, tau, nabs, nout);
                         } else {
-                            tau = a.sigma[snu] * pa[sjl] * pb[sjl] * l;
+                            const R aa = static_cast<R>(v[i].x) * q[i].x + static_cast<R>(v[i].y) * q[i].y +
+                                         static_cast<R>(v[i].z) * q[i].z;
+                            const R l = aa / sqrt(q[i].x * q[i].x + q[i].y * q[i].y + q[i].z * q[i].z);
+                            tau = pa[sjl * a.nf + snu] * pb[sjl] * l;
                             cl = qc[i].c + l / kCLight;
+                            attenuate(q[i].n, tau, nabs, nout);
                         }
-                        R nabs, nout;
-                        attenuate(q[i].n, tau, nabs, nout);
+                        // FP32: the merge's products, formed here on all lanes at once
                         pval[u] = nout;
-                        pval[kP + u] = q[i].x;
-                        pval[2 * kP + u] = q[i].y;
-                        pval[3 * kP + u] = q[i].z;
-                        pval[4 * kP + u] = cl;
+                        pval[kP + u] = f32 ? nout * q[i].x : q[i].x;
+                        pval[2 * kP + u] = f32 ? nout * q[i].y : q[i].y;
+                        pval[3 * kP + u] = f32 ? nout * q[i].z : q[i].z;
+                        pval[4 * kP + u] = f32 ? nout * cl : cl;
                         pval[5 * kP + u] = nabs;
                         pval[6 * kP + u] = q[i].n;
                     }
@@ -1268,7 +1335,10 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
                     if (nin < R(0)) continue;
                     sum_add(asum, aerr, pval[5 * kP + u]);
                     sum_add(psum, perr, nin);
-                    acc_add(acc, pval[u], pval[kP + u], pval[2 * kP + u], pval[3 * kP + u], pval[4 * kP + u]);
+                    if constexpr (f32)
+                        acc_addp(acc, pval[u], pval[kP + u], pval[2 * kP + u], pval[3 * kP + u], pval[4 * kP + u]);
+                    else
+                        acc_add(acc, pval[u], pval[kP + u], pval[2 * kP + u], pval[3 * kP + u], pval[4 * kP + u]);
                     ++narr;
                 }
                 wave_sync();  // the LDS is reused
@@ -1319,12 +1389,16 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
             cn = c0;
         }
     } else {
-        const R an = acc.n + acc.en, sx = acc.sx + acc.ex, sy = acc.sy + acc.ey, sz = acc.sz + acc.ez,
-                sc = acc.sc + acc.ec;
+        const R an = acc.n + acc.en, sx = acc.sx, sy = acc.sy, sz = acc.sz, sc = acc.sc;
         if (an > R(0)) {
             nn = an;
             const R s2 = sx * sx + sy * sy + sz * sz;
-            if (s2 > R(0)) {
+            if (f32 && s2 > R(1e-30)) {
+                const R inv = __builtin_amdgcn_rsqf(static_cast<float>(s2));
+                dx = sx * inv;
+                dy = sy * inv;
+                dz = sz * inv;
+            } else if (s2 > R(0)) {
                 const R nr = sqrt(s2);
                 dx = sx / nr;
                 dy = sy / nr;
@@ -1340,7 +1414,7 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
                     dz = a.wrc[3 * r + 2];
                 }
             }
-            cn = sc / an;
+            cn = (f32 && an > R(1e-30)) ? sc * static_cast<R>(__builtin_amdgcn_rcpf(static_cast<float>(an))) : sc / an;
         }
     }
     bool floored = false;
@@ -1385,15 +1459,27 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
     unsigned long long cmw = 0;
     int tgt = r;
     if (act) {
+        if constexpr (f32) {
+            // bit k: neighbour k is a cone member; the bits enter from the
+            // highest neighbour down (m = 2m + bit), in two 32-bit halves
+            unsigned int mh = 0, ml = 0;
+            int k = K - 1;
+            for (; k >= 32; --k) {
+                const V4 w = fj[k];
+                mh = mh + mh + (__builtin_fmaf(w.z, dz, __builtin_fmaf(w.y, dy, w.x * dx)) >= a.cosc ? 1u : 0u);
+            }
 #pragma unroll 8
-        for (int k = 0; k < K; ++k) {
-            const V4 w = fj[k];
-            bool in;
-            if constexpr (f32)
-                in = w.x * dx + w.y * dy + w.z * dz >= a.cosc;
-            else
-                in = in_cone(w.x, w.y, w.z, dx, dy, dz, a.c2);
-            if (in) cmw |= 1ull << k;
+            for (; k >= 0; --k) {
+                const V4 w = fj[k];
+                ml = ml + ml + (__builtin_fmaf(w.z, dz, __builtin_fmaf(w.y, dy, w.x * dx)) >= a.cosc ? 1u : 0u);
+            }
+            cmw = (static_cast<unsigned long long>(mh) << 32) | ml;
+        } else {
+#pragma unroll 8
+            for (int k = 0; k < K; ++k) {
+                const V4 w = fj[k];
+                if (in_cone(w.x, w.y, w.z, dx, dy, dz, a.c2)) cmw |= 1ull << k;
+            }
         }
         if constexpr (f32)
             tgt = nearest_direction(a.wrcf, nrc, dx, dy, dz);
@@ -1416,7 +1502,8 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
         Inbox<DT> ib;
         ib.tag = (static_cast<unsigned int>(stamp) << 1) | (offdiag ? 1u : 0u);
         for (int k0 = 0; k0 < K; k0 += G) {
-            const DT w = group_transpose(static_cast<DT>((cs >> k0) & gmaskG), G, o);
+            const DT w0 = static_cast<DT>((cs >> k0) & gmaskG);
+            const DT w = f32 ? group_transpose(w0, G, o) : group_transpose_loop(w0, G, o);
             const int k = k0 + o;
             if (psend && k < K && w != DT(0)) {
                 ib.mask = w;
