@@ -1036,28 +1036,34 @@ struct HopLds {
 // chemistry step (section 2.2) and the emission records.
 template <typename R, typename DT, typename S>
 __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
-    if (!a.hop0) {
-        if (a.cnt[kCntDone] != 0 || a.cnt[kCntAct0 + kCntLine * a.act_rd] == 0) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) a.cnt[kCntDone] = 1;
-            return;
-        }
-        if (a.hop > a.max_hops) {
-            if (blockIdx.x == 0 && threadIdx.x == 0)
-                atomicOr(reinterpret_cast<unsigned long long*>(&a.cnt[kCntFlags]), static_cast<unsigned long long>(kFlagHopCap));
-            return;
-        }
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        if (!a.hop0) {
-            a.cnt[kCntHops] += 1;
-            a.cnt[kCntHopsStep] += 1;
-        }
-        a.cnt[kCntRec] = 0;   // records of this step were all linked before launch
-        a.cnt[kCntDeep] = 0;  // and its virtual particles all handled
-    }
     const long long tile = xcd_block(blockIdx.x, gridDim.x);
-    const int stamp = static_cast<int>(a.cnt[kCntSerial]) + a.hop;  // of this forward step
-    if (!a.hop0 && a.hot_rd[tile] != stamp) return;
+    // The launch-level flags, the stamp base and the tile's mark are loaded
+    // together (every address is valid) and tested once.  A launch past the
+    // last forward step of an RT step, or past the cap, runs no tile.
+    const long long c_done = a.cnt[kCntDone];
+    const long long c_act = a.cnt[kCntAct0 + kCntLine * a.act_rd];
+    const long long c_serial = a.cnt[kCntSerial];
+    const int hot = a.hot_rd[tile];
+    const int stamp = static_cast<int>(c_serial) + a.hop;  // of this forward step
+    // (bitwise operators: no short-circuit branches between the loads)
+    const bool idle = (a.hop0 == 0) & ((c_done != 0) | (c_act == 0));
+    const bool capped = (a.hop0 == 0) & !idle & (a.hop > a.max_hops);
+    const bool runs = !idle & !capped & ((a.hop0 != 0) | (hot == stamp));
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (idle) {
+            a.cnt[kCntDone] = 1;
+        } else if (capped) {
+            atomicOr(reinterpret_cast<unsigned long long*>(&a.cnt[kCntFlags]), static_cast<unsigned long long>(kFlagHopCap));
+        } else {
+            if (!a.hop0) {
+                a.cnt[kCntHops] += 1;
+                a.cnt[kCntHopsStep] += 1;
+            }
+            a.cnt[kCntRec] = 0;   // records of this step were all linked before launch
+            a.cnt[kCntDeep] = 0;  // and its virtual particles all handled
+        }
+    }
+    if (!runs) return;
 
     constexpr bool f32 = sizeof(R) == 4;
     constexpr unsigned long long rsz = sizeof(R);
@@ -1076,15 +1082,40 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
     const long long s = j * G + o;
     const int nu = o >> lgN;
     const int r = o & (nrc - 1);
-    const int inst = valid ? a.inst_of[j] : 0;
-    const double U = f32 ? a.U[inst] : 1.0;
     const long long jend = (j0 + T < a.N) ? j0 + T : a.N;
     const int lane = threadIdx.x;
+    // Everything the slot reads of its own particle, and the tile's edge
+    // ranges: independent loads, issued together at clamped (always valid)
+    // indices before any loaded value is tested.
+    const long long jc = valid ? j : j0;
+    const long long ia = jc * a.nf + nu;
+    const int inst_l = a.inst_of[jc];
+    const R flo_l = a.floor_b[jc];
+    const int hd_l = a.head[jc];
+    const double A0_l = a.A[ia], P0_l = a.P[ia];
+    const Bin4<R> q0_l = a.pk[jc * G + o];
+    const R c0_l = a.pcl[jc * G + o];
+    const unsigned long long tally_l = a.part[3 * tile + (lane < 3 ? lane : 0)];
+    R ka_l, sg_l, nh_l;  // the optical depth's per-particle and per-bin factors
+    if constexpr (f32) {
+        ka_l = a.kappa[jc];
+        sg_l = a.sigmaf[nu];
+        nh_l = R(0);
+    } else {
+        ka_l = a.xHI[jc];
+        sg_l = a.sigma[nu];
+        nh_l = a.nH[jc];
+    }
+    const long long e_t0 = a.rev_off[j0], e_t1 = a.rev_off[jend];
+    const long long my0_l = a.rev_off[jc], my1_l = a.rev_off[jc + 1];
+    // per instance: a second, dependent round
+    const int inst = valid ? inst_l : 0;
+    const double U = f32 ? a.U[inst] : 1.0;
+    const float clf_l = f32 ? a.clf[inst] : 0.0f;
     // algorithmic bytes this lane moves (slot state, gathered packets, edges)
     unsigned long long nbytes = 0;
     // the tile's running tallies (read early, written back at the end)
-    unsigned long long tally = 0;
-    if (lane < 3) tally = a.part[3 * tile + lane];
+    const unsigned long long tally = lane < 3 ? tally_l : 0ull;
 
     Acc<R> acc = {};
     int narr = 0;            // packets merged into the bin besides the one that stays
@@ -1092,22 +1123,15 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
     Bin4<R> q0 = {};
     R c0 = 0;
     bool have_stay = false, departed = false;
-    // everything the slot reads of its own particle, issued up front
-    const long long ia = j * a.nf + nu;
-    R flo = 0;
-    int hd = -1;
-    double A0 = 0.0, P0 = 0.0;
+    const R flo = valid ? flo_l : R(0);
+    const int hd = valid ? hd_l : -1;
+    const double A0 = (valid && r == 0) ? A0_l : 0.0, P0 = (valid && r == 0) ? P0_l : 0.0;
+    q0.x = valid ? q0_l.x : R(0);  // selects, so that the loads stay up front
+    q0.y = valid ? q0_l.y : R(0);
+    q0.z = valid ? q0_l.z : R(0);
+    q0.n = valid ? q0_l.n : R(0);
+    c0 = valid ? c0_l : R(0);
     if (valid) {
-        flo = a.floor_b[j];
-        hd = a.head[j];
-        if (r == 0) {
-            A0 = a.A[ia];
-            P0 = a.P[ia];
-        }
-    }
-    if (valid) {
-        q0 = a.pk[s];
-        c0 = a.pcl[s];
         nbytes += 5 * rsz;
         if (q0.n > R(0)) {
             if (a.hop0) {
@@ -1147,14 +1171,10 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
         R* pa = reinterpret_cast<R*>(lds + L::part);
         R* pb = pa + 64;
         if (valid && r == 0) {
-            if constexpr (f32)
-                pa[jl * a.nf + nu] = a.sigmaf[nu] * a.kappa[j];
-            else
-                pa[jl * a.nf + nu] = a.sigma[nu] * a.xHI[j];
-            if (o == 0) pb[jl] = f32 ? static_cast<R>(a.clf[inst]) : static_cast<R>(a.nH[j]);
+            pa[jl * a.nf + nu] = sg_l * ka_l;
+            if (o == 0) pb[jl] = f32 ? static_cast<R>(clf_l) : nh_l;
         }
-        const long long e_t0 = a.rev_off[j0], e_t1 = a.rev_off[jend];
-        const long long my0 = valid ? a.rev_off[j] : 0, my1 = valid ? a.rev_off[j + 1] : 0;
+        const long long my0 = valid ? my0_l : 0, my1 = valid ? my1_l : 0;
         const unsigned int prev = static_cast<unsigned int>(stamp - 1);
         const DT gm = static_cast<DT>(nrc >= 8 * static_cast<int>(sizeof(DT)) ? ~DT(0) : ((DT(1) << nrc) - DT(1)));
         const int gbase_s = lane & ~(G - 1);
