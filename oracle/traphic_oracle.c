@@ -215,7 +215,8 @@ void or_rates(double T, double out[8])
 /* (Gamma + beta n_e) y, integrated with backward Euler (rates frozen over a */
 /* sub-step); the sub-step is limited so that y changes by at most chem_frac */
 /* of min(y, 1-y) (floored at 1e-6) and T by chem_frac of itself.  With      */
-/* photoheating and cooling d[(1+x)T]/dt = 2 (H - Lambda)/(3 k n_H).         */
+/* photoheating and cooling d[(1+x)T]/dt = 2 (H - Lambda)/(3 k n_H), where   */
+/* H = n_H y sum_nu Gamma_nu <eps>_nu with the current y.                     */
 /* ------------------------------------------------------------------------ */
 void or_chem_one(const or_params *p, const double *eps, const double *A, double nH, double NH,
                  double *xHI, double *T, double *nrr, int64_t *nsub)
@@ -230,8 +231,10 @@ void or_chem_one(const or_params *p, const double *eps, const double *A, double 
         Esum += A[nu] * eps[nu];
     }
     double gam = NHI0 > 0.0 ? Asum / (NHI0 * dt) : 0.0;
-    double vol = NH / nH;
-    double heat = Esum / (vol * dt);
+    /* photoheating per HI atom sum_nu Gamma_nu <eps>_nu (section 2.1); per    */
+    /* volume it scales with the neutral density n_H y as y evolves, like the  */
+    /* photoionizations                                                         */
+    double heat_y = NHI0 > 0.0 ? Esum / (NHI0 * dt) * nH : 0.0;
     int caseB = p->recomb_mode == OR_CASE_B_OTS;
     double Tc = *T;
     double t = 0.0, rr = 0.0;
@@ -257,7 +260,7 @@ void or_chem_one(const or_params *p, const double *eps, const double *A, double 
             double nHI = nH * y, nHII = nH * x;
             double lam_cool = (caseB ? rt[4] : rt[3]) * ne * nHII + K_BOLTZ * T_HI * rt[2] * ne * nHI +
                               rt[5] * ne * nHI + rt[6] * ne * nHII + rt[7] * ne;
-            dY = 2.0 * (heat - lam_cool) / (3.0 * K_BOLTZ * nH);
+            dY = 2.0 * (heat_y * y - lam_cool) / (3.0 * K_BOLTZ * nH);
             Y = (1.0 + x) * Tc;
             if (fabs(dY) > 0.0) {
                 double limT = p->chem_frac * Y / fabs(dY);

@@ -1005,14 +1005,18 @@ struct HopLds {
     static constexpr size_t desc = (nd + kEdges + 31) / 32 * 32;
     static constexpr size_t val = desc + 4 * kPairs;
     static constexpr size_t part = val + 7 * sizeof(R) * kPairs;
-    __host__ __device__ static constexpr int fstride(int K) { return K + 1; }  // padded against bank conflicts
+    // Rows of neighbour offsets and neighbours, one per particle.  FP32: 64
+    // entries per row (filled by one direct global-to-LDS load per row, lanes
+    // past K repeating the last neighbour), offsets padded to 65 against bank
+    // conflicts; FP64: K entries, offsets padded to K + 1.
+    __host__ __device__ static constexpr int fstride(int K) { return sizeof(R) == 4 ? 65 : K + 1; }
+    __host__ __device__ static constexpr int nstride(int K) { return sizeof(R) == 4 ? 64 : K; }
     __host__ __device__ static constexpr size_t ngb_off(int T, int K) {
         return static_cast<size_t>(T) * fstride(K) * 4 * sizeof(R);
     }
-    __host__ __device__ static constexpr size_t dw_off(int T, int K) { return ngb_off(T, K) + 4 * static_cast<size_t>(T) * K; }
     __host__ __device__ static constexpr size_t bytes(int T, int K) {
         const size_t g = part + sizeof(R) * (64 + static_cast<size_t>(T));
-        const size_t f = dw_off(T, K) + sizeof(DT) * static_cast<size_t>(T) * K;
+        const size_t f = ngb_off(T, K) + 4 * static_cast<size_t>(T) * nstride(K);
         return g > f ? g : f;
     }
 };
@@ -1462,16 +1466,53 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
     if (tile_act && threadIdx.x == 0) a.hot_wr[tile] = stamp + 1;  // its leaving packets empty their bins
     const int gbase = lane & ~(G - 1);
     const unsigned long long gmaskG = G >= 64 ? ~0ull : ((1ull << G) - 1ull);
-    const bool pact = ((__ballot(act) >> gbase) & gmaskG) != 0;
+    const unsigned long long wact = __ballot(act);
+    const bool pact = ((wact >> gbase) & gmaskG) != 0;
     V4* fj = reinterpret_cast<V4*>(lds) + static_cast<long long>(jl) * L::fstride(K);
-    int* nj = reinterpret_cast<int*>(lds + L::ngb_off(T, K)) + static_cast<long long>(jl) * K;
-    DT* dw = reinterpret_cast<DT*>(lds + L::dw_off(T, K)) + static_cast<long long>(jl) * K;
-    if (pact) {
+    int* nj = reinterpret_cast<int*>(lds + L::ngb_off(T, K)) + static_cast<long long>(jl) * L::nstride(K);
+    if constexpr (f32) {
+        // direct global-to-LDS loads (4 bytes per lane, all lanes, the row
+        // choice uniform) of the rows of particles with an active packet:
+        // the 4K words of the offsets, then the K neighbours; lanes past the
+        // end repeat the last word, which the row padding absorbs
+        const int nwd = 4 * K;
+        for (int rw = 0; rw < T; ++rw) {
+            if (((wact >> (rw * G)) & gmaskG) == 0) continue;
+            const long long jr = j0 + rw;
+            const unsigned int* fsrc = reinterpret_cast<const unsigned int*>(static_cast<const float4*>(a.fwd_v) + jr * K);
+            unsigned int* fdst = reinterpret_cast<unsigned int*>(reinterpret_cast<V4*>(lds) + rw * L::fstride(K));
+            for (int w0 = 0; w0 < nwd; w0 += 64) {
+                const int w = w0 + lane < nwd ? w0 + lane : nwd - 1;
+                __builtin_amdgcn_global_load_lds(fsrc + w, fdst + w0, 4, 0, 0);
+            }
+            const int kk = lane < K ? lane : K - 1;
+            __builtin_amdgcn_global_load_lds(reinterpret_cast<const unsigned int*>(a.ngb + jr * K + kk),
+                                             reinterpret_cast<unsigned int*>(lds + L::ngb_off(T, K)) + rw * L::nstride(K), 4, 0, 0);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        if (pact && o == 0) nbytes += static_cast<unsigned long long>(K) * (4 * rsz + 4);
+    } else if (pact) {
         const V4* src = static_cast<const V4*>(a.fwd_v) + j * K;
         const int* sn = a.ngb + j * K;
-        for (int k = o; k < K; k += G) {
-            fj[k] = src[k];
-            nj[k] = sn[k];
+        // kStage neighbours per lane in flight at once, then into LDS
+        constexpr int kStage = 4;
+        for (int kb = o; kb < K; kb += kStage * G) {
+            V4 f[kStage];
+            int nb[kStage];
+#pragma unroll
+            for (int u = 0; u < kStage; ++u) {
+                const int k = min(kb + u * G, K - 1);  // loads in one block, no branch
+                f[u] = src[k];
+                nb[u] = sn[k];
+            }
+#pragma unroll
+            for (int u = 0; u < kStage; ++u) {
+                const int k = kb + u * G;
+                if (k < K) {
+                    fj[k] = f[u];
+                    nj[k] = nb[u];
+                }
+            }
         }
         if (o == 0) nbytes += static_cast<unsigned long long>(K) * (4 * rsz + 4);
     }
@@ -1648,7 +1689,8 @@ struct ChemArgs {
 // step; the neutral fraction follows dy/dt = alpha n_e (1-y) - (Gamma +
 // beta n_e) y by backward Euler over sub-steps that change y by at most
 // frac * max(min(y, 1-y), 1e-6) (and T by frac * T); with heating and cooling
-// d[(1+x)T]/dt = 2 (H - Lambda) / (3 k n_H).  RR photons: alpha_1 n_e x N_H dt_sub.
+// d[(1+x)T]/dt = 2 (H - Lambda) / (3 k n_H), H = n_H y sum_nu Gamma_nu eps_nu
+// with the current y.  RR photons: alpha_1 n_e x N_H dt_sub.
 __global__ __launch_bounds__(256) void k_chem(ChemArgs a) {
     const long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (j >= a.N) return;
@@ -1677,7 +1719,8 @@ __global__ __launch_bounds__(256) void k_chem(ChemArgs a) {
             esum += a.A[j * a.nf + nu] * a.eps[nu];
         }
         const double gam = nhi0 > 0.0 ? asum / (nhi0 * a.dt) : 0.0;
-        const double heat = esum / ((NH / nH) * a.dt);
+        // photoheating per volume n_H y sum_nu Gamma_nu eps_nu, with the current y
+        const double heat_y = nhi0 > 0.0 ? esum / (nhi0 * a.dt) * nH : 0.0;
         const bool caseB = a.mode == 0;
         double t = 0.0;
         for (int n = 0; t < a.dt && n < 1000000; ++n) {
@@ -1700,7 +1743,7 @@ __global__ __launch_bounds__(256) void k_chem(ChemArgs a) {
                 const double nhi = nH * y, nhii = nH * x;
                 const double lam = (caseB ? rt.recB : rt.recA) * ne * nhii + kBoltz * kTHI * rt.beta * ne * nhi +
                                    rt.cexc * ne * nhi + rt.ff * ne * nhii + rt.compton * ne;
-                dY = 2.0 * (heat - lam) / (3.0 * kBoltz * nH);
+                dY = 2.0 * (heat_y * y - lam) / (3.0 * kBoltz * nH);
                 Y = (1.0 + x) * Tc;
                 if (fabs(dY) > 0.0) {
                     const double limT = a.frac * Y / fabs(dY);

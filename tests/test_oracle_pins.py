@@ -438,6 +438,46 @@ def test_rr_tally_is_ground_state_recombinations():
     assert abs(x_new / x_hi - 1) < 1e-9
 
 
+def test_photoheating_follows_the_neutral_fraction():
+    """Absorbed photons (section 2.1): per HI atom Gamma = N_abs / (N_HI dt) with
+    N_HI at the start of the step, and photoheating Gamma <eps>; per volume both
+    scale with the neutral density n_H y as y evolves.  The sub-cycled update
+    converges to a fine ODE solve of that system (a heating rate frozen at the
+    initial neutral density would overshoot T by far)."""
+    from scipy.integrate import solve_ivp
+    nH, T0, x_hi = 1e-3, 1e4, 0.5
+    NH = 1e62
+    dt = 0.1 * I.MYR_S
+    A = [0.3 * x_hi * NH]
+    eps = [5.0 * I.EV_ERG]
+    res = []
+    for f in (0.02, 0.01):
+        p = I.default_params(dt=dt, chem_frac=f, isothermal=0, recomb_mode=I.CASE_A_NO_RR)
+        y, T, _, _ = O.chem_one(p, eps, A, nH, NH, x_hi, T0)
+        res.append((y, T))
+    gam = A[0] / (x_hi * NH * dt)
+
+    def rhs(t, v):
+        xh, T = v
+        r = O.rates(T)
+        x = 1 - xh
+        ne = nH * x
+        dxh = r["alpha_A"] * ne * x - (gam + r["beta"] * ne) * xh
+        lam = (r["recA_cool"] * ne * nH * x + I.K_BOLTZ * 157807.0 * r["beta"] * ne * nH * xh
+               + r["ce_cool"] * ne * nH * xh + r["ff_cool"] * ne * nH * x + r["compton"] * ne)
+        dY = 2 * (nH * xh * gam * eps[0] - lam) / (3 * I.K_BOLTZ * nH)
+        dT = (dY + dxh * T) / (1 + x)
+        return [dxh, dT]
+
+    sol = solve_ivp(rhs, (0, dt), [x_hi, T0], method="LSODA", rtol=1e-10, atol=[1e-14, 1e-8])
+    yref, Tref = sol.y[0, -1], sol.y[1, -1]
+    assert Tref > T0 and yref < x_hi
+    (y1, T1), (y2, T2) = res
+    assert abs(T2 - Tref) < 0.01 * (Tref - T0)
+    assert abs(T2 - Tref) < abs(T1 - Tref)
+    assert abs(y2 - yref) < 0.01 * (x_hi - yref)
+
+
 def test_heating_cooling_integrator_against_ode_solver():
     """Temperature equation d[(1+x)T]/dt = 2(H - Lambda)/(3 k n_H) with frozen x
     (no photons): the sub-cycled explicit update converges to a fine ODE solve.
