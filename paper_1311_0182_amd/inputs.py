@@ -176,6 +176,51 @@ def batched(n_inst=64, side_lo=8, side_hi=48, n_ngb=48, n_steps=100, seed_k=4, r
     return _pack(f"batched{n_inst}", params, [SIGMA_13P6] * n_freq, [0.0] * n_freq, insts, src, n_steps)
 
 
+# Grey bins of a 1e5 K blackbody between 13.6, 24.6, 54.4 and 100 eV (section 4
+# uses this spectrum), with the hydrogen cross-section taken as 6.3e-18 cm^2
+# (nu / nu_0)^-3: the fraction of the photons in each bin, the photon-weighted
+# cross-section and the cross-section-weighted excess energy per absorption.
+BB1E5_EDGES_EV = (13.6, 24.6, 54.4, 100.0)
+BB1E5_FRAC = (0.4478, 0.4944, 0.0577)
+BB1E5_SIGMA = (2.802e-18, 4.746e-19, 6.390e-20)
+BB1E5_EPS_EV = (3.726, 17.393, 48.316)
+EPS_RR_EV = 2.327      # kT at 2.7e4 K: excess energy of a recombination photon (section 4)
+
+
+def shadow(n_side=128, box_kpc=6.6, n_h=2e-4, clump_nh=0.04, clump_r_kpc=0.8,
+           clump_c_kpc=(1.7, 3.3, 3.3), flux=1e6, n_pp=100, n_ngb=48, n_tc=16, n_rc=16,
+           n_ec=16, t0=8000.0, n_steps=20, seed_k=3, dt_myr=0.1, **pkw):
+    """Shadow set-up (section 4, scaled): a plane-parallel front from the x = 0
+    face (n_pp^2 boundary emitters, flux in photons/s/cm^2) with a 1e5 K
+    blackbody in three grey bins, a dense spherical clump in low-density gas,
+    recombination radiation in a fourth bin, photoheating and cooling on.
+    Particles are a jittered lattice; those inside the clump carry its density."""
+    rng = np.random.default_rng(BASE_SEED + seed_k)
+    L = box_kpc * KPC_CM
+    lo = np.zeros(3)
+    pos = jittered_lattice(n_side, lo, L, rng)
+    c = np.asarray(clump_c_kpc, dtype=np.float64) * KPC_CM
+    inside = np.sum((pos - c[None, :]) ** 2, axis=1) <= (clump_r_kpc * KPC_CM) ** 2
+    nh = np.where(inside, clump_nh, n_h)
+    NH = nh * (L ** 3 / pos.shape[0])
+    xhi = np.ones(pos.shape[0])
+    T = np.full(pos.shape[0], t0)
+    n_freq = 4
+    params = default_params(
+        n_ngb=n_ngb, n_tc=n_tc, n_rc=n_rc, n_ec=n_ec, n_freq=n_freq, rr_bin=3,
+        recomb_mode=RR_TRANSPORT, isothermal=0, dt=dt_myr * MYR_S, n_em=1,
+        seed=BASE_SEED + seed_k)
+    params.update(pkw)
+    sigma = list(BB1E5_SIGMA) + [SIGMA_13P6]
+    eps = [e * EV_ERG for e in BB1E5_EPS_EV] + [EPS_RR_EV * EV_ERG]
+    rate = np.zeros((1, n_freq))
+    rate[0, :3] = flux * np.asarray(BB1E5_FRAC)
+    src = dict(inst=np.zeros(1, np.int32), kind=np.array([SRC_PLANE_XLO], np.int32),
+               pos=np.zeros((1, 3)), rate=rate, n_side=np.array([n_pp], np.int32))
+    inst = dict(pos=pos, nH=nh, NH=NH, xHI=xhi, T=T, box_lo=lo, box_hi=lo + L)
+    return _pack(f"shadow{n_side}", params, sigma, eps, [inst], src, n_steps)
+
+
 def instance(cfg, k):
     """Instance k of a batch as a workload of its own (same particles, box,
     sources and parameters)."""
@@ -215,11 +260,14 @@ def chain(n=12, spacing_kpc=0.1, n_h=1e-3, x_hi=1e-3, **pkw):
 
 def config(k, **kw):
     """Named workloads: 1 = 16^3 Stromgren case B (FP64), 2 = 64^3 with recombination
-    radiation (FP32 vs FP64), 4 = 64 batched instances with recombination radiation."""
+    radiation (FP32 vs FP64), 3 = 128^3 shadow set-up (plane front, blackbody bins,
+    clump, heating and cooling), 4 = 64 batched instances with recombination radiation."""
     if k == 1:
         return stromgren(16, rr=False, n_ngb=32, n_steps=100, seed_k=1, **kw)
     if k == 2:
         return stromgren(64, rr=True, n_ngb=48, n_steps=500, seed_k=2, **kw)
+    if k == 3:
+        return shadow(**kw)
     if k == 4:
         return batched(**kw)
     raise ValueError(f"unknown workload {k}")

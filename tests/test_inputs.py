@@ -22,3 +22,33 @@ def test_instances_partition_the_batch():
         lo, hi = p["box"][0, :3], p["box"][0, 3:]
         assert np.all(p["pos"] >= lo) and np.all(p["pos"] <= hi)
     assert sum(len(p["sources"]["inst"]) for p in parts) == len(cfg["sources"]["inst"])
+
+
+def test_blackbody_bins_from_the_spectrum():
+    """The grey constants of the shadow set-up: photon fractions, photon-weighted
+    cross-sections (hydrogen sigma ~ nu^-3 from 6.3e-18 cm^2 at 13.6 eV) and
+    excess energies of a 1e5 K blackbody, recomputed by quadrature."""
+    from scipy.integrate import quad
+    kT = 8.617333262e-5 * 1e5
+    nph = lambda e: e * e / np.expm1(e / kT)
+    sig = lambda e: I.SIGMA_13P6 * (e / 13.6) ** -3
+    edges = I.BB1E5_EDGES_EV
+    tot = quad(nph, edges[0], edges[-1])[0]
+    for b in range(3):
+        a, c = edges[b], edges[b + 1]
+        n = quad(nph, a, c)[0]
+        sn = quad(lambda e: sig(e) * nph(e), a, c)[0]
+        en = quad(lambda e: (e - 13.6) * sig(e) * nph(e), a, c)[0]
+        assert abs(n / tot - I.BB1E5_FRAC[b]) < 1e-4
+        assert abs(sn / n / I.BB1E5_SIGMA[b] - 1) < 1e-3
+        assert abs(en / sn / I.BB1E5_EPS_EV[b] - 1) < 1e-3
+
+
+def test_shadow_layout():
+    cfg = I.shadow(n_side=16, n_pp=8)
+    p = cfg["params"]
+    assert p["n_rc"] * p["n_freq"] == 64 and p["rr_bin"] == 3 and p["isothermal"] == 0
+    nh = cfg["nH"]
+    assert set(np.unique(nh)) == {2e-4, 0.04}
+    assert 0 < np.sum(nh == 0.04) < nh.size // 10
+    assert cfg["sources"]["kind"][0] == I.SRC_PLANE_XLO and cfg["sources"]["n_side"][0] == 8
