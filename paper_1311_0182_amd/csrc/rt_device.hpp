@@ -314,6 +314,62 @@ __device__ inline int wave_count(P pred) {
     return c;
 }
 
+// The n <= 128 candidates in L.d2/L.idx sorted by (d^2, index) with a
+// bitonic network over the wavefront (element e = lane + 64 i in register i):
+// the first K of them are exactly the K that the selection below keeps, here
+// written back in order to L.d2/L.idx[0..K).  Returns the K-th d^2.
+__device__ inline double wave_sort_small(WaveKnn& L, int n, int K, int lane) {
+    unsigned long long kd[2];
+    int ki[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int e = lane + 64 * i;
+        kd[i] = e < n ? static_cast<unsigned long long>(__double_as_longlong(L.d2[e])) : ~0ull;  // d2 >= 0: ordered as bits
+        ki[i] = e < n ? L.idx[e] : 0x7fffffff;
+    }
+    wave_sync();
+    const int top = n <= 64 ? 64 : 128;
+    for (int k = 2; k <= top; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j == 64) {
+                // partners e and e + 64 sit in the same lane; k = 128 sorts ascending
+                const bool sw = kd[1] < kd[0] || (kd[1] == kd[0] && ki[1] < ki[0]);
+                if (sw) {
+                    const unsigned long long t = kd[0];
+                    kd[0] = kd[1];
+                    kd[1] = t;
+                    const int u = ki[0];
+                    ki[0] = ki[1];
+                    ki[1] = u;
+                }
+                continue;
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                if (i == 1 && top == 64) break;
+                const int e = lane + 64 * i;
+                const unsigned long long pk = __shfl_xor(kd[i], j, 64);
+                const int pi = __shfl_xor(ki[i], j, 64);
+                const bool up = (e & k) == 0;       // this block sorts ascending
+                const bool low = (lane & j) == 0;   // e is the lower of the pair
+                const bool pless = pk < kd[i] || (pk == kd[i] && pi < ki[i]);
+                const bool pmore = pk > kd[i] || (pk == kd[i] && pi > ki[i]);
+                if (low == up ? pless : pmore) {
+                    kd[i] = pk;
+                    ki[i] = pi;
+                }
+            }
+        }
+    }
+    if (lane < K) {
+        L.d2[lane] = __longlong_as_double(static_cast<long long>(kd[0]));
+        L.idx[lane] = ki[0];
+    }
+    const double kth = __longlong_as_double(static_cast<long long>(__shfl(kd[0], K - 1, 64)));
+    wave_sync();
+    return kth;
+}
+
 // Selects the K smallest of the n candidates in L.d2/L.idx (K <= n <=
 // kWaveCand) and writes them, compacted in arbitrary order, to L.d2/L.idx
 // [0, K).  Returns the K-th smallest d^2.
@@ -384,7 +440,7 @@ __device__ inline double wave_select(WaveKnn& L, int n, int K, int lane) {
 // back to the serial query).  On success res_idx/res_d2[0..K) are sorted and
 // kth = res_d2[K-1].
 __device__ inline bool knn_wave(const GridInfo& g, const int* __restrict__ cell_start,
-                                const int* __restrict__ cell_idx, const double* __restrict__ pos,
+                                const int* __restrict__ cell_idx, const double* __restrict__ cpos,
                                 double qx, double qy, double qz, int self, int K, WaveKnn& L, int lane) {
     int c[3];
     const double q[3] = {qx, qy, qz};
@@ -459,11 +515,14 @@ __device__ inline bool knn_wave(const GridInfo& g, const int* __restrict__ cell_
             const int total = L.cpre[m];
             // the candidates, four per lane per round
             for (int k0 = 0; k0 < total; k0 += 256) {
-                int jj[4];
+                // candidate k's entry in cell order: its index and its position
+                // (kept in cell order too) load together
+                int kc[4], jj[4];
+                double d2v[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int k = k0 + 64 * i + lane;
-                    jj[i] = -1;
+                    kc[i] = -1;
                     if (k < total) {
                         int lo = 0, hi = m - 1;  // the cell holding candidate k
                         while (lo < hi) {
@@ -473,17 +532,18 @@ __device__ inline bool knn_wave(const GridInfo& g, const int* __restrict__ cell_
                             else
                                 hi = mid - 1;
                         }
-                        jj[i] = cell_idx[L.cfirst[lo] + (k - L.cpre[lo])];
+                        kc[i] = L.cfirst[lo] + (k - L.cpre[lo]);
                     }
                 }
-                double d2v[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
+                    jj[i] = -1;
                     d2v[i] = 0.0;
-                    if (jj[i] >= 0) {
-                        const double ex = pos[3 * static_cast<long long>(jj[i]) + 0] - qx;
-                        const double ey = pos[3 * static_cast<long long>(jj[i]) + 1] - qy;
-                        const double ez = pos[3 * static_cast<long long>(jj[i]) + 2] - qz;
+                    if (kc[i] >= 0) {
+                        jj[i] = cell_idx[kc[i]];
+                        const double ex = cpos[3 * static_cast<long long>(kc[i]) + 0] - qx;
+                        const double ey = cpos[3 * static_cast<long long>(kc[i]) + 1] - qy;
+                        const double ez = cpos[3 * static_cast<long long>(kc[i]) + 2] - qz;
                         d2v[i] = ex * ex + ey * ey + ez * ez;
                     }
                 }
@@ -505,11 +565,17 @@ __device__ inline bool knn_wave(const GridInfo& g, const int* __restrict__ cell_
         }
         if (over) return false;
         if (n < K) continue;
-        const double kth = wave_select(L, n, K, lane);
+        const bool sorted = n <= 128;
+        const double kth = sorted ? wave_sort_small(L, n, K, lane) : wave_select(L, n, K, lane);
         const double reach = static_cast<double>(s) * csmin;
         if (kth <= reach * reach || s == smax) {
-            // sort the K selected pairs by (d^2, index)
-            if (lane < K) {
+            // the K selected pairs ordered by (d^2, index)
+            if (sorted) {
+                if (lane < K) {
+                    L.res_d2[lane] = L.d2[lane];
+                    L.res_idx[lane] = L.idx[lane];
+                }
+            } else if (lane < K) {
                 const double dc = L.d2[lane];
                 const int ic = L.idx[lane];
                 int rank = 0;

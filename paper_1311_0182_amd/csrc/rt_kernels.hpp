@@ -140,6 +140,17 @@ __global__ void k_cell_fill(long long N, const int* __restrict__ cell_of, const 
     idx[start[c] + atomicAdd(&cursor[c], 1)] = static_cast<int>(i);
 }
 
+// Positions in cell order: entry t is the position of particle cell_idx[t].
+__global__ void k_cell_pos(long long N, const int* __restrict__ idx, const double* __restrict__ pos,
+                           double* __restrict__ cpos) {
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    const long long i = idx[t];
+    cpos[3 * t] = pos[3 * i];
+    cpos[3 * t + 1] = pos[3 * i + 1];
+    cpos[3 * t + 2] = pos[3 * i + 2];
+}
+
 // k nearest neighbours of points (particles when self >= 0 is their own index).
 __global__ __launch_bounds__(128) void k_knn(long long n, const double* __restrict__ qpos, const int* __restrict__ qinst,
                                              int exclude_self, const GridInfo* __restrict__ grid,
@@ -455,6 +466,7 @@ struct VipArgs {
     const GridInfo* grid;
     const int* cell_start;
     const int* cell_idx;
+    const double* cell_pos;
     const double* pos;
     const double* xHI;
     const double* nH;
@@ -648,7 +660,7 @@ __global__ __launch_bounds__(256) void k_vip_chain(VipArgs a) {
                     break;
                 }
             }
-            if (!knn_wave(g, a.cell_start, a.cell_idx, a.pos, xv[0], xv[1], xv[2], -1, K, L, lane)) {
+            if (!knn_wave(g, a.cell_start, a.cell_idx, a.cell_pos, xv[0], xv[1], xv[2], -1, K, L, lane)) {
                 // candidate buffer overflow (very clustered cells): serial query on one lane
                 if (lane == 0) {
                     double bd[kMaxNgb];
@@ -667,13 +679,16 @@ __global__ __launch_bounds__(256) void k_vip_chain(VipArgs a) {
             const double d2k = nbl ? L.res_d2[lane] : 0.0;
             const double hv = sqrt(L.kth);
             wave_sync();
-            double w = nbl ? spline_shape(sqrt(d2k), hv) * (a.NH[jk] / a.nH[jk]) : 0.0;
+            // everything the leg needs of the neighbour, loaded together
+            const double NHk = a.NH[jk], nHk = a.nH[jk], xHk = a.xHI[jk];
+            const double pxk = a.pos[3 * jk], pyk = a.pos[3 * jk + 1], pzk = a.pos[3 * jk + 2];
+            double w = nbl ? spline_shape(sqrt(d2k), hv) * (NHk / nHk) : 0.0;
             double wsum = wave_sum(w);
             if (!(wsum > 0.0)) {
                 w = nbl ? 1.0 : 0.0;
                 wsum = static_cast<double>(K);
             }
-            const double nhi = wave_sum(nbl ? w * (a.xHI[jk] * a.nH[jk]) : 0.0) / wsum;
+            const double nhi = wave_sum(nbl ? w * (xHk * nHk) : 0.0) / wsum;
             const double dd = sqrt(q.d[0] * q.d[0] + q.d[1] * q.d[1] + q.d[2] * q.d[2]);
             const double l = ((xv[0] - q.x[0]) * q.d[0] + (xv[1] - q.x[1]) * q.d[1] + (xv[2] - q.x[2]) * q.d[2]) / dd;
             const double tau = a.sigma[q.nu] * nhi * l;
@@ -683,7 +698,7 @@ __global__ __launch_bounds__(256) void k_vip_chain(VipArgs a) {
             // (order-independent, deterministic sums): a coarse part in units of
             // N_H,k 2^-30 and a fine part in units of N_H,k 2^-62
             if (nbl) {
-                const double x = (nabs * w / wsum) / a.NH[jk] * 1073741824.0;  // 2^30
+                const double x = (nabs * w / wsum) / NHk * 1073741824.0;  // 2^30
                 if (x > 0.0) {
                     double cpart = floor(x);
                     if (!(cpart < 9.0e18)) {
@@ -701,9 +716,9 @@ __global__ __launch_bounds__(256) void k_vip_chain(VipArgs a) {
             double vx = 0.0, vy = 0.0, vz = 0.0;
             bool member = false;
             if (nbl) {
-                vx = a.pos[3 * jk] - xv[0];
-                vy = a.pos[3 * jk + 1] - xv[1];
-                vz = a.pos[3 * jk + 2] - xv[2];
+                vx = pxk - xv[0];
+                vy = pyk - xv[1];
+                vz = pzk - xv[2];
                 member = in_cone(vx, vy, vz, q.d[0], q.d[1], q.d[2], a.c2);
             }
             const unsigned long long bm = __ballot(member);
@@ -717,7 +732,7 @@ __global__ __launch_bounds__(256) void k_vip_chain(VipArgs a) {
                 if (member && idx1 >= 0) {
                     const int w8 = __popcll(bm & ((1ull << lane) - 1ull));
                     const double lk = (vx * q.d[0] + vy * q.d[1] + vz * q.d[2]) / dd;
-                    const double tk = a.sigma[q.nu] * a.xHI[jk] * a.nH[jk] * lk;
+                    const double tk = a.sigma[q.nu] * xHk * nHk * lk;
                     double ak, outk;
                     attenuate(nin, tk, ak, outk);
                     Rec rc;

@@ -60,6 +60,7 @@ struct rt_ctx {
     GridInfo* grid_d = nullptr;
     int* cell_start = nullptr;
     int* cell_idx = nullptr;
+    double* cell_pos = nullptr;  // positions in cell order (cell_idx order), for the wavefront kNN
     double *u_rc = nullptr, *u_ec = nullptr;
     double* rot = nullptr;
     float* wrcf = nullptr;
@@ -317,6 +318,7 @@ rt_status launch_vip(rt_ctx* c, int hop) {
     a.grid = c->grid_d;
     a.cell_start = c->cell_start;
     a.cell_idx = c->cell_idx;
+    a.cell_pos = c->cell_pos;
     a.pos = c->pos;
     a.xHI = c->xHI;
     a.nH = c->nH;
@@ -833,6 +835,8 @@ rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, cons
     hipLaunchKernelGGL(k_scan_i32, dim3(1), dim3(1024), 0, c->stream, cnt, ncell, c->cell_start);
     hipLaunchKernelGGL(k_cell_fill, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, cell_of, c->cell_start, cursor,
                        c->cell_idx);
+    ITRY(alloc_n(c, &c->cell_pos, 3 * N));
+    hipLaunchKernelGGL(k_cell_pos, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, c->cell_idx, c->pos, c->cell_pos);
     hipLaunchKernelGGL(k_knn, dim3(grid_for(N, 128)), dim3(128), 0, c->stream, N, c->pos, c->inst_of, 1, c->grid_d,
                        c->cell_start, c->cell_idx, c->pos, c->K, c->ngb, c->h);
     // reverse lists, sorted by sender
