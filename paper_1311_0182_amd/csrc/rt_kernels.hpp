@@ -1029,11 +1029,14 @@ struct HopLds {
     __host__ __device__ static constexpr size_t ngb_off(int T, int K) {
         return static_cast<size_t>(T) * fstride(K) * 4 * sizeof(R);
     }
-    __host__ __device__ static constexpr size_t bytes(int T, int K) {
+    // the rotated reception-cone directions of the step (3 N_RC <= 96 values),
+    // after everything else: read by every lane when it bins a packet
+    __host__ __device__ static constexpr size_t rcd_off(int T, int K) {
         const size_t g = part + sizeof(R) * (64 + static_cast<size_t>(T));
         const size_t f = ngb_off(T, K) + 4 * static_cast<size_t>(T) * nstride(K);
-        return g > f ? g : f;
+        return ((g > f ? g : f) + 15) / 16 * 16;
     }
+    __host__ __device__ static constexpr size_t bytes(int T, int K) { return rcd_off(T, K) + 96 * sizeof(R); }
 };
 
 // One forward step (section 2.1), receiver-sorted.  A workgroup of one
@@ -1127,6 +1130,8 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
     }
     const long long e_t0 = a.rev_off[j0], e_t1 = a.rev_off[jend];
     const long long my0_l = a.rev_off[jc], my1_l = a.rev_off[jc + 1];
+    R* rcd = reinterpret_cast<R*>(lds + L::rcd_off(T, K));
+    if (lane < 3 * nrc) rcd[lane] = f32 ? static_cast<R>(a.wrcf[lane]) : static_cast<R>(a.wrc[lane]);
     // per instance: a second, dependent round
     const int inst = valid ? inst_l : 0;
     const double U = f32 ? a.U[inst] : 1.0;
@@ -1557,10 +1562,7 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
                 if (in_cone(w.x, w.y, w.z, dx, dy, dz, a.c2)) cmw |= 1ull << k;
             }
         }
-        if constexpr (f32)
-            tgt = nearest_direction(a.wrcf, nrc, dx, dy, dz);
-        else
-            tgt = nearest_direction(a.wrc, nrc, dx, dy, dz);
+        tgt = nearest_direction(static_cast<const R*>(rcd), nrc, dx, dy, dz);
     }
     const bool send = act && cmw != 0;
     const bool vip = act && cmw == 0;
