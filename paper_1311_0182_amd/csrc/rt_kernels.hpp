@@ -611,6 +611,9 @@ __global__ __launch_bounds__(256) void k_vip_sample(VipArgs a) {
 // points drawn by the whole wavefront, 64 attempts at a time).
 __global__ __launch_bounds__(256) void k_vip_chain(VipArgs a) {
     __shared__ WaveKnn lds[4];
+    __shared__ double rcd[96];  // the step's reception-cone directions
+    if (threadIdx.x < 3 * a.nrc) rcd[threadIdx.x] = a.wrc[threadIdx.x];
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const long long gw = blockIdx.x * 4LL + wv;
@@ -724,7 +727,7 @@ __global__ __launch_bounds__(256) void k_vip_chain(VipArgs a) {
             const unsigned long long bm = __ballot(member);
             const int nc = __popcll(bm);
             if (nc > 0) {
-                const int r = nearest_direction(a.wrc, a.nrc, q.d[0], q.d[1], q.d[2]);
+                const int r = nearest_direction(static_cast<const double*>(rcd), a.nrc, q.d[0], q.d[1], q.d[2]);
                 const double nin = nrem / static_cast<double>(nc);
                 int idx1 = 0;
                 if (lane == 0) idx1 = alloc_records(a.cnt, nc, a.rec_cap);
@@ -1301,7 +1304,22 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
             const int M = __shfl(incl, 63, 64);
             const int off0 = incl - np;
             for (int base = 0; base < M; base += kP) {
-                {
+                if (!any_nd) {
+                    // no sender arrives off its own cone index: each hit edge
+                    // brings exactly the slot's own packet index, no LDS lookup
+                    int q = off0;
+                    for (int sg = 0; sg < nseg; ++sg) {
+                        unsigned long long h = sg == 0 ? h0 : seg_hit(sg);
+                        const unsigned int tb = static_cast<unsigned int>(lo + 64ll * sg - cb);
+                        while (h) {
+                            const unsigned int u = static_cast<unsigned int>(__builtin_ctzll(h));
+                            h &= h - 1ull;
+                            if (q >= base && q < base + kP)
+                                pdesc[q - base] = ((tb + u) << 14) | (static_cast<unsigned int>(r) << 8) | threadIdx.x;
+                            ++q;
+                        }
+                    }
+                } else {
                     // every lane takes part: the transpose needs all of a particle's lanes
                     int q = off0;
                     each_pair([&](int t, int pp) {
@@ -1375,15 +1393,26 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
                 const int qb = (off0 + np < base + nr) ? off0 + np : base + nr;
                 for (int qq = qa; qq < qb; ++qq) {
                     const int u = qq - base;
-                    const R nin = pval[6 * kP + u];
-                    if (nin < R(0)) continue;
-                    sum_add(asum, aerr, pval[5 * kP + u]);
-                    sum_add(psum, perr, nin);
-                    if constexpr (f32)
-                        acc_addp(acc, pval[u], pval[kP + u], pval[2 * kP + u], pval[3 * kP + u], pval[4 * kP + u]);
-                    else
+                    if constexpr (f32) {
+                        // all seven values read at once; a packet that arrives in
+                        // another cone of the particle (marked by nin < 0) adds
+                        // exact zeros, which leave the sums bit for bit unchanged
+                        const R nin = pval[6 * kP + u];
+                        const R v0 = pval[u], v1 = pval[kP + u], v2 = pval[2 * kP + u], v3 = pval[3 * kP + u],
+                                v4 = pval[4 * kP + u], v5 = pval[5 * kP + u];
+                        const bool ok = nin >= R(0);
+                        sum_add(asum, aerr, ok ? v5 : R(0));
+                        sum_add(psum, perr, ok ? nin : R(0));
+                        acc_addp(acc, ok ? v0 : R(0), ok ? v1 : R(0), ok ? v2 : R(0), ok ? v3 : R(0), ok ? v4 : R(0));
+                        narr += ok ? 1 : 0;
+                    } else {
+                        const R nin = pval[6 * kP + u];
+                        if (nin < R(0)) continue;
+                        sum_add(asum, aerr, pval[5 * kP + u]);
+                        sum_add(psum, perr, nin);
                         acc_add(acc, pval[u], pval[kP + u], pval[2 * kP + u], pval[3 * kP + u], pval[4 * kP + u]);
-                    ++narr;
+                        ++narr;
+                    }
                 }
                 wave_sync();  // the LDS is reused
             }
