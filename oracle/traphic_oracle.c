@@ -732,15 +732,55 @@ static double w_spline(double r, double h)
 /* Draw a point uniformly in the unit ball restricted to a cone: rejection from
  * the cube [-1,1]^3.  The cone is either the Voronoi cell ek of the emission
  * directions ecdir (n_ec of them) or the transmission cone around d. */
+/* Frame of a transmission cone: its unit axis a = d/|d| and two unit vectors */
+/* across it, e1 = (g x a)/|g x a| for the coordinate axis g least aligned    */
+/* with a (the first of the smallest |a_k|), and e2 = a x e1.                 */
+static void cone_frame(const double d[3], double a[3], double e1[3], double e2[3])
+{
+    double n = sqrt(dot3(d, d));
+    for (int k = 0; k < 3; ++k) a[k] = d[k] / n;
+    double ax = fabs(a[0]), ay = fabs(a[1]), az = fabs(a[2]);
+    int g = (ax <= ay && ax <= az) ? 0 : (ay <= az ? 1 : 2);
+    double c[3];
+    /* g x a for the unit vector g */
+    if (g == 0) { c[0] = 0.0; c[1] = -a[2]; c[2] = a[1]; }
+    else if (g == 1) { c[0] = a[2]; c[1] = 0.0; c[2] = -a[0]; }
+    else { c[0] = -a[1]; c[1] = a[0]; c[2] = 0.0; }
+    double m = sqrt(dot3(c, c));
+    for (int k = 0; k < 3; ++k) e1[k] = c[k] / m;
+    e2[0] = a[1] * e1[2] - a[2] * e1[1];
+    e2[1] = a[2] * e1[0] - a[0] * e1[2];
+    e2[2] = a[0] * e1[1] - a[1] * e1[0];
+}
+
+/* A point drawn uniformly in the unit ball intersected with the cone (section */
+/* 2.1: the virtual particle lies in the empty cone, within the smoothing      */
+/* length).  Reading: rejection sampling, attempt by attempt in order.  A       */
+/* transmission cone (axis d, cos theta = 1 - 2/N_TC) draws from the box       */
+/* [0, 1] x [-sin theta, sin theta]^2 in its frame, which holds the cone's part */
+/* of the ball; an emission cone (a Voronoi cell of the rotated directions)     */
+/* draws from the cube [-1, 1]^3.  Either way a point is kept iff it lies in the */
+/* ball and passes the cone's own membership test.                            */
 static int vip_sample(uint64_t seed, uint32_t tag, uint32_t step, uint32_t ida, uint32_t idb,
                       const double *ecdir, int n_ec, int ek, const double d[3], int n_tc, double p[3])
 {
+    double a[3], e1[3], e2[3], sn = 0.0;
+    if (!ecdir) {
+        cone_frame(d, a, e1, e2);
+        double c = 1.0 - 2.0 / (double)n_tc;
+        sn = sqrt(1.0 - c * c);
+    }
     for (uint32_t att = 0; att < VIP_MAX_ATTEMPTS; ++att) {
         double u[4];
         draw4(seed, tag, att, step, ida, idb, u);
-        p[0] = u[0];
-        p[1] = u[1];
-        p[2] = u[2];
+        if (ecdir) {
+            p[0] = u[0];
+            p[1] = u[1];
+            p[2] = u[2];
+        } else {
+            double t = 0.5 * (u[0] + 1.0), x = sn * u[1], y = sn * u[2];
+            for (int k = 0; k < 3; ++k) p[k] = t * a[k] + x * e1[k] + y * e2[k];
+        }
         if (p[0] * p[0] + p[1] * p[1] + p[2] * p[2] > 1.0) continue;
         if (ecdir) {
             if (nearest_dir(ecdir, n_ec, p) != ek) continue;

@@ -53,6 +53,51 @@ __host__ __device__ inline void uniforms4(uint64_t seed, uint32_t tag, uint32_t 
     }
 }
 
+// Frame of a transmission cone for drawing its points: the unit axis
+// a = d/abs(d) and unit vectors e1 = (g x a)/abs(g x a), e2 = a x e1 across it,
+// g the coordinate axis least aligned with a (the first of the smallest
+// abs(a_k)).  A draw (u0, u1, u2) in [-1, 1)^3 maps to the point
+// t a + x e1 + y e2 with t = (u0 + 1)/2, (x, y) = sin(theta) (u1, u2): a box
+// that holds the cone's part of the unit ball (about 30% of it is kept,
+// against 6.5% of the cube [-1, 1]^3 for N_TC = 8).
+struct ConeFrame {
+    double a[3], e1[3], e2[3], sn;
+};
+
+__host__ __device__ inline ConeFrame cone_frame(const double d[3], double c2) {
+    ConeFrame f;
+    const double n = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    for (int k = 0; k < 3; ++k) f.a[k] = d[k] / n;
+    const double ax = fabs(f.a[0]), ay = fabs(f.a[1]), az = fabs(f.a[2]);
+    const int g = (ax <= ay && ax <= az) ? 0 : (ay <= az ? 1 : 2);
+    double cr[3];
+    if (g == 0) {
+        cr[0] = 0.0;
+        cr[1] = -f.a[2];
+        cr[2] = f.a[1];
+    } else if (g == 1) {
+        cr[0] = f.a[2];
+        cr[1] = 0.0;
+        cr[2] = -f.a[0];
+    } else {
+        cr[0] = -f.a[1];
+        cr[1] = f.a[0];
+        cr[2] = 0.0;
+    }
+    const double m = sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+    for (int k = 0; k < 3; ++k) f.e1[k] = cr[k] / m;
+    f.e2[0] = f.a[1] * f.e1[2] - f.a[2] * f.e1[1];
+    f.e2[1] = f.a[2] * f.e1[0] - f.a[0] * f.e1[2];
+    f.e2[2] = f.a[0] * f.e1[1] - f.a[1] * f.e1[0];
+    f.sn = sqrt(1.0 - c2);  // c2 = cos^2(theta), formed as c * c
+    return f;
+}
+
+__host__ __device__ inline void cone_point(const ConeFrame& f, const double u[4], double p[3]) {
+    const double t = 0.5 * (u[0] + 1.0), x = f.sn * u[1], y = f.sn * u[2];
+    for (int k = 0; k < 3; ++k) p[k] = t * f.a[k] + x * f.e1[k] + y * f.e2[k];
+}
+
 // Haar-uniform rotation: a uniform point of the unit 4-ball (rejection), made
 // a unit quaternion, turned into its rotation matrix (row major).
 __host__ __device__ inline void random_rotation(uint64_t seed, uint32_t tag, uint32_t step,

@@ -504,11 +504,12 @@ struct VipArgs {
 // round*kVipLanes + sub-lane); the lowest accepted attempt wins, as if drawn
 // one by one.  Every lane of the group returns the point.  False if no attempt
 // is accepted.
-constexpr int kVipLanes = 16;
+constexpr int kVipLanes = 8;
 
 __device__ inline bool vip_draw_group(const VipArgs& a, uint32_t step, const Vip& q, bool live, int depth, int sub,
                                       int gshift, double p[3]) {
     const double* ecs = (q.ec >= 0 && depth == 1) ? a.ecd + 3 * (static_cast<long long>(q.ec) * a.nec) : nullptr;
+    const ConeFrame fr = cone_frame(q.d, a.c2);
     const unsigned long long gm = (kVipLanes >= 64 ? ~0ull : ((1ull << kVipLanes) - 1ull)) << gshift;
     bool done = !live;
     bool found = false;
@@ -517,6 +518,13 @@ __device__ inline bool vip_draw_group(const VipArgs& a, uint32_t step, const Vip
         double u[4] = {0.0, 0.0, 0.0, 0.0};
         if (!done) {
             uniforms4(a.seed, q.tag, base + static_cast<uint32_t>(sub), step, q.ida, q.idb | static_cast<uint32_t>(depth), u);
+            if (!ecs) {
+                double pc[3];
+                cone_point(fr, u, pc);
+                u[0] = pc[0];
+                u[1] = pc[1];
+                u[2] = pc[2];
+            }
             ok = u[0] * u[0] + u[1] * u[1] + u[2] * u[2] <= 1.0;
             if (ok) ok = ecs ? nearest_direction(ecs, a.nec, u[0], u[1], u[2]) == q.ek
                              : in_cone(u[0], u[1], u[2], q.d[0], q.d[1], q.d[2], a.c2);
@@ -636,9 +644,15 @@ __global__ __launch_bounds__(256) void k_vip_chain(VipArgs a) {
                 if (lane == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&a.cnt[kCntVips]), 1ull);
                 double p0 = 0.0, p1 = 0.0, p2 = 0.0;
                 bool found = false;
+                const ConeFrame fr = cone_frame(q.d, a.c2);
                 for (uint32_t base = 0; base < kVipAttempts; base += 64) {
                     double u[4];
                     uniforms4(a.seed, q.tag, base + lane, step, q.ida, q.idb | static_cast<uint32_t>(depth), u);
+                    double pc[3];
+                    cone_point(fr, u, pc);
+                    u[0] = pc[0];
+                    u[1] = pc[1];
+                    u[2] = pc[2];
                     bool ok = u[0] * u[0] + u[1] * u[1] + u[2] * u[2] <= 1.0;
                     if (ok) ok = in_cone(u[0], u[1], u[2], q.d[0], q.d[1], q.d[2], a.c2);
                     const unsigned long long b = __ballot(ok);

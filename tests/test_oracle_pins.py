@@ -191,11 +191,16 @@ def test_cone_solid_angle(n_tc):
     assert abs(frac - 1.0 / n_tc) < 5 * sd     # solid angle 4 pi / N_TC
 
 
-def test_vip_sampler_uniform_in_cone_ball():
-    d = np.array([0.0, 0.6, 0.8])
-    n_tc = 8
-    c = 1 - 2 / n_tc
+@pytest.mark.parametrize("d,n_tc", [((0.0, 0.6, 0.8), 8), ((1.0, 0.0, 0.0), 8), ((0.0, 0.0, -2.0), 16),
+                                    ((0.3, -0.5, 0.81), 16)])
+def test_vip_sampler_uniform_in_cone_ball(d, n_tc):
+    """Points of virtual particles: uniform in the unit ball within the cone
+    (section 2.1), whatever the axis (also along a coordinate axis, where the
+    cone's frame picks its helper axis by a tie-break) and its length."""
+    d = np.asarray(d, dtype=np.float64)
     ps = np.array([O.vip_sample(I.BASE_SEED, 3, 0, k, 0, d, n_tc) for k in range(20000)])
+    d = d / np.linalg.norm(d)
+    c = 1 - 2 / n_tc
     assert np.all((ps ** 2).sum(1) <= 1)
     assert all(O.in_cone(p, d, n_tc) for p in ps[:500])
     # centroid of a spherical sector of half-angle theta: 3/8 (1 + cos theta) along d
