@@ -1083,6 +1083,10 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
     const long long c_act = a.cnt[kCntAct0 + kCntLine * a.act_rd];
     const long long c_serial = a.cnt[kCntSerial];
     const int hot = a.hot_rd[tile];
+    // the tile's range of receiver-sorted edges (it depends on the tile alone)
+    const long long tj0 = tile * a.T;
+    const long long tj1 = (tj0 + a.T < a.N) ? tj0 + a.T : a.N;
+    const long long e_t0 = a.rev_off[tj0 < a.N ? tj0 : a.N], e_t1 = a.rev_off[tj1];
     const int stamp = static_cast<int>(c_serial) + a.hop;  // of this forward step
     // (bitwise operators: no short-circuit branches between the loads)
     const bool idle = (a.hop0 == 0) & ((c_done != 0) | (c_act == 0));
@@ -1123,6 +1127,28 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
     const int r = o & (nrc - 1);
     const long long jend = (j0 + T < a.N) ? j0 + T : a.N;
     const int lane = threadIdx.x;
+    // Gather staging: a chunk of the tile's incoming edges, inbox words and
+    // edge words straight from memory into LDS (no registers held, all loads in
+    // flight together); lanes past the end load a copy of the last edge.  The
+    // first chunk is requested before the tile's own loads, so that both
+    // arrive in one round trip.
+    unsigned int* e_ik = reinterpret_cast<unsigned int*>(lds + L::ik);
+    unsigned int* e_tag = reinterpret_cast<unsigned int*>(lds + L::tag);
+    unsigned int* e_mw = reinterpret_cast<unsigned int*>(lds + L::mw);
+    auto stage_chunk = [&](long long cb) {
+        const long long ne = (e_t1 - cb < L::kEdges) ? e_t1 - cb : L::kEdges;
+        const int nrd = static_cast<int>((ne + 63) >> 6);
+        for (int i = 0; i < nrd; ++i) {
+            const long long t = 64ll * i + lane;
+            const long long ts = cb + (t < ne ? t : ne - 1);
+            const unsigned int* ws = reinterpret_cast<const unsigned int*>(a.in_rd + ts);
+            __builtin_amdgcn_global_load_lds(ws, e_tag + 64 * i, 4, 0, 0);
+            for (int w = 0; w < static_cast<int>(sizeof(DT) / 4); ++w)
+                __builtin_amdgcn_global_load_lds(ws + offsetof(Inbox<DT>, mask) / 4 + w, e_mw + w * L::kEdges + 64 * i, 4, 0, 0);
+            __builtin_amdgcn_global_load_lds(a.rev_ik + ts, e_ik + 64 * i, 4, 0, 0);
+        }
+    };
+    if (!a.hop0 && e_t0 < e_t1) stage_chunk(e_t0);
     // Everything the slot reads of its own particle, and the tile's edge
     // ranges: independent loads, issued together at clamped (always valid)
     // indices before any loaded value is tested.
@@ -1145,7 +1171,6 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
         sg_l = a.sigma[nu];
         nh_l = a.nH[jc];
     }
-    const long long e_t0 = a.rev_off[j0], e_t1 = a.rev_off[jend];
     const long long my0_l = a.rev_off[jc], my1_l = a.rev_off[jc + 1];
     R* rcd = reinterpret_cast<R*>(lds + L::rcd_off(T, K));
     if (lane < 3 * nrc) rcd[lane] = f32 ? static_cast<R>(a.wrcf[lane]) : static_cast<R>(a.wrc[lane]);
@@ -1199,9 +1224,6 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
         }
     }
     if (!a.hop0) {
-        unsigned int* e_ik = reinterpret_cast<unsigned int*>(lds + L::ik);
-        unsigned int* e_tag = reinterpret_cast<unsigned int*>(lds + L::tag);
-        unsigned int* e_mw = reinterpret_cast<unsigned int*>(lds + L::mw);
         DT* e_dl = reinterpret_cast<DT*>(lds + L::dl);
         DT* e_ef = reinterpret_cast<DT*>(lds + L::eff);
         unsigned char* e_nd = lds + L::nd;
@@ -1223,19 +1245,7 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
         for (long long cb = e_t0; cb < e_t1; cb += L::kEdges) {
             const long long ne = (e_t1 - cb < L::kEdges) ? e_t1 - cb : L::kEdges;
             bool snd = false;
-            // inbox words and edge words go straight from memory into LDS (no
-            // registers held, all loads in flight together); lanes past the
-            // end load a copy of the last edge
-            const int nrd = static_cast<int>((ne + 63) >> 6);
-            for (int i = 0; i < nrd; ++i) {
-                const long long t = 64ll * i + lane;
-                const long long ts = cb + (t < ne ? t : ne - 1);
-                const unsigned int* ws = reinterpret_cast<const unsigned int*>(a.in_rd + ts);
-                __builtin_amdgcn_global_load_lds(ws, e_tag + 64 * i, 4, 0, 0);
-                for (int w = 0; w < static_cast<int>(sizeof(DT) / 4); ++w)
-                    __builtin_amdgcn_global_load_lds(ws + offsetof(Inbox<DT>, mask) / 4 + w, e_mw + w * L::kEdges + 64 * i, 4, 0, 0);
-                __builtin_amdgcn_global_load_lds(a.rev_ik + ts, e_ik + 64 * i, 4, 0, 0);
-            }
+            if (cb != e_t0) stage_chunk(cb);  // the first chunk is already on its way
             __builtin_amdgcn_s_waitcnt(0);
             wave_sync();
             for (long long t = lane; t < ne; t += 64) {
