@@ -49,6 +49,7 @@ enum : long long { kFlagHopCap = 1, kFlagVipOverflow = 2, kFlagRecOverflow = 4, 
 // units of the two fixed-point deposit accumulators, relative to the receiving particle's N_H
 constexpr double kDepositCoarse = 1.0 / 1073741824.0;         // 2^-30
 constexpr double kDepositFine = 1.0 / 4611686018427387904.0;  // 2^-62
+constexpr double kDepositFiner = kDepositFine / 4294967296.0;   // 2^-94
 
 template <typename R>
 struct alignas(4 * sizeof(R)) Bin4 {
@@ -457,7 +458,7 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
 
 struct VipArgs {
     int hop, hop0, max_hops, K, nf, nrc, nec, max_depth;
-    long long* dep;  // [N*nf][2] deposited photons of virtual-particle legs, fixed point
+    long long* dep;  // [N*nf][3] deposited photons of virtual-particle legs, fixed point
     uint64_t seed;
     double c2;
     const Vip* list;
@@ -712,8 +713,10 @@ __global__ __launch_bounds__(256) void k_vip_chain(VipArgs a) {
             double nabs, nrem;
             attenuate(q.N, tau, nabs, nrem);
             // deposits of the leg's absorptions to the neighbours, as integers
-            // (order-independent, deterministic sums): a coarse part in units of
-            // N_H,k 2^-30 and a fine part in units of N_H,k 2^-62
+            // (order-independent, deterministic sums) in units of N_H,k 2^-30,
+            // 2^-62 and 2^-94: every step of the split is exact, so the three
+            // parts hold all the bits of the deposit down to 2^-94 N_H,k (a bin
+            // with photons far below N_H keeps its relative precision)
             if (nbl) {
                 const double x = (nabs * w / wsum) / NHk * 1073741824.0;  // 2^30
                 if (x > 0.0) {
@@ -722,11 +725,15 @@ __global__ __launch_bounds__(256) void k_vip_chain(VipArgs a) {
                         cpart = 9.0e18;
                         atomicOr(reinterpret_cast<unsigned long long*>(&a.cnt[kCntFlags]), static_cast<unsigned long long>(kFlagRecOverflow));
                     }
+                    const double r1 = (x - cpart) * 4294967296.0;  // 2^32
+                    const double mpart = floor(r1);
                     const long long ic = static_cast<long long>(cpart);
-                    const long long ifn = __double2ll_rn((x - cpart) * 4294967296.0);  // 2^32
-                    unsigned long long* d = reinterpret_cast<unsigned long long*>(&a.dep[2 * (jk * a.nf + q.nu)]);
+                    const long long im = static_cast<long long>(mpart);
+                    const long long ifn = __double2ll_rn((r1 - mpart) * 4294967296.0);
+                    unsigned long long* d = reinterpret_cast<unsigned long long*>(&a.dep[3 * (jk * a.nf + q.nu)]);
                     if (ic) atomicAdd(d, static_cast<unsigned long long>(ic));
-                    if (ifn) atomicAdd(d + 1, static_cast<unsigned long long>(ifn));
+                    if (im) atomicAdd(d + 1, static_cast<unsigned long long>(im));
+                    if (ifn) atomicAdd(d + 2, static_cast<unsigned long long>(ifn));
                 }
             }
             const double cv = q.c + l / kCLight;
@@ -1766,11 +1773,13 @@ __global__ __launch_bounds__(256) void k_chem(ChemArgs a) {
     if (j >= a.N) return;
     const double nH = a.nH[j], NH = a.NH[j];
     for (int nu = 0; nu < a.nf; ++nu) {
-        long long* d = a.dep + 2 * (j * a.nf + nu);
-        if (d[0] != 0 || d[1] != 0)
-            a.A[j * a.nf + nu] += (static_cast<double>(d[0]) * kDepositCoarse + static_cast<double>(d[1]) * kDepositFine) * NH;
+        long long* d = a.dep + 3 * (j * a.nf + nu);
+        if (d[0] != 0 || d[1] != 0 || d[2] != 0)
+            a.A[j * a.nf + nu] += (static_cast<double>(d[0]) * kDepositCoarse + static_cast<double>(d[1]) * kDepositFine +
+                                   static_cast<double>(d[2]) * kDepositFiner) * NH;
         d[0] = 0;
         d[1] = 0;
+        d[2] = 0;
     }
     double y = a.xHI[j];
     double Tc = a.T[j];

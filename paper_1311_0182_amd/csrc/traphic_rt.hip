@@ -897,8 +897,8 @@ rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, cons
     ITRY(alloc_n(c, &c->A, N * c->nf));
     ITRY(alloc_n(c, &c->P, N * c->nf));
     ITRY(fill_f64(c, c->A, N * c->nf, 0.0));
-    ITRY(alloc_n(c, &c->dep, 2 * N * c->nf));
-    HIPCHK(c, hipMemsetAsync(c->dep, 0, sizeof(long long) * 2 * N * c->nf, c->stream));
+    ITRY(alloc_n(c, &c->dep, 3 * N * c->nf));
+    HIPCHK(c, hipMemsetAsync(c->dep, 0, sizeof(long long) * 3 * N * c->nf, c->stream));
     ITRY(fill_f64(c, c->P, N * c->nf, 0.0));
     ITRY(alloc_n(c, &c->xs, c->B));
     ITRY(alloc_n(c, &c->rs, c->B));

@@ -251,3 +251,28 @@ def test_full_size_first_steps_fp64():
     assert np.array_equal(so["counters"], sg["counters"])
     assert rel(sg["xHI"], so["xHI"]) < 1e-6
     assert np.max(residual(sg["ledger"])) < 1e-12
+
+
+@pytest.mark.parametrize("case", ["no_sources", "ionized_start", "tiny_instances"])
+def test_degenerate_inputs(case):
+    """Degenerate inputs against the oracle: no source at all (nothing is emitted
+    or moved, the ledger stays empty), a fully ionized start (tau = 0: the first
+    step transports without absorbing), and a batch of tiny uneven instances
+    (64..343 particles, tiles cut across instance boundaries)."""
+    base = I.stromgren(8, rr=True, n_ngb=32, dt_myr=0.5)
+    if case == "no_sources":
+        cfg = dict(base)
+        cfg["sources"] = {k: v[:0] for k, v in base["sources"].items()}
+    elif case == "ionized_start":
+        cfg = dict(base)
+        cfg["xHI"] = np.zeros_like(base["xHI"])
+    else:
+        cfg = I.batched(n_inst=3, side_lo=4, side_hi=7, n_ngb=32, n_steps=4)
+    say("degenerate case", case, "N", cfg["pos"].shape[0])
+    s, ctx = _compare_fp64(cfg, 3)
+    sg = ctx.state()
+    if case == "no_sources":
+        assert sg["counters"][1] == 0 and sg["counters"][3] == 0
+        assert np.all(sg["ledger"] == 0.0)
+    if case == "ionized_start":
+        assert np.all(sg["ledger"][..., 1] < sg["ledger"][..., 0])  # most photons were not absorbed
