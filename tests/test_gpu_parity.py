@@ -276,3 +276,30 @@ def test_degenerate_inputs(case):
         assert np.all(sg["ledger"] == 0.0)
     if case == "ionized_start":
         assert np.all(sg["ledger"][..., 1] < sg["ledger"][..., 0])  # most photons were not absorbed
+
+
+def test_full_size_batched_first_steps():
+    """The batched workload at full size (64 instances, 1.36 M particles, the
+    launch configuration bench.py times): its first steps against the oracle,
+    FP64 (neighbour lists and counters exact, x_HI within 1e-6, ledger closed)
+    and FP32 (x_HI within 1e-3, ledger residual within 1e-6)."""
+    cfg = I.config(4)
+    steps = 3
+    say("batched 64 instances full size,", steps, "steps")
+    s, _ = run_oracle(cfg, steps)
+    so = s.state()
+    ctx = run_gpu(cfg, steps, "fp64")
+    assert np.array_equal(s.ngb()[0], ctx.neighbours()[0])
+    sg = ctx.state()
+    ctx.close()
+    say("counters oracle", so["counters"], "gpu", sg["counters"])
+    assert np.array_equal(so["counters"], sg["counters"])
+    assert rel(sg["xHI"], so["xHI"]) < 1e-6
+    assert np.max(residual(sg["ledger"])) < 1e-12
+    c32 = run_gpu(cfg, steps, "fp32")
+    s32 = c32.state()
+    c32.close()
+    dx = np.max(np.abs(s32["xHI"] - so["xHI"]))
+    say("fp32 max |dx_HI|", dx, "residual", np.max(residual(s32["ledger"])))
+    assert dx <= 1e-3
+    assert np.max(residual(s32["ledger"])) <= 1e-6
