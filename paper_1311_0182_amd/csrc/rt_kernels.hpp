@@ -957,6 +957,36 @@ __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
 // c < G) and receives column o (bit e = entry (e, o)).  log2(G) rounds, each
 // exchanging the off-diagonal halves of 2j x 2j blocks between lanes o and o^j;
 // the rounds are written out so that every mask and lane offset is a constant.
+// The value of lane (this lane ^ 2^LJ) with the cheapest exchange the
+// distance allows: quad permutes for 1 and 2 and a rotation by 8 within a row
+// of 16 (DPP, no LDS unit), swizzles for 4 and 16, a permute for 32.
+template <int LJ>
+__device__ inline unsigned int xor_lane32(unsigned int x) {
+    if constexpr (LJ == 0)
+        return static_cast<unsigned int>(__builtin_amdgcn_mov_dpp(static_cast<int>(x), 0xB1, 0xF, 0xF, false));  // quad [1,0,3,2]
+    else if constexpr (LJ == 1)
+        return static_cast<unsigned int>(__builtin_amdgcn_mov_dpp(static_cast<int>(x), 0x4E, 0xF, 0xF, false));  // quad [2,3,0,1]
+    else if constexpr (LJ == 3)
+        return static_cast<unsigned int>(__builtin_amdgcn_mov_dpp(static_cast<int>(x), 0x128, 0xF, 0xF, false));  // row_ror:8
+    else if constexpr (LJ == 2)
+        return static_cast<unsigned int>(__builtin_amdgcn_ds_swizzle(static_cast<int>(x), 0x101F));  // xor 4 in 32
+    else if constexpr (LJ == 4)
+        return static_cast<unsigned int>(__builtin_amdgcn_ds_swizzle(static_cast<int>(x), 0x401F));  // xor 16 in 32
+    else
+        return __shfl_xor(x, 32, 64);
+}
+
+template <int LJ, typename W>
+__device__ inline W xor_lane(W x) {
+    if constexpr (sizeof(W) == 4) {
+        return static_cast<W>(xor_lane32<LJ>(static_cast<unsigned int>(x)));
+    } else {
+        const unsigned int lo = xor_lane32<LJ>(static_cast<unsigned int>(x));
+        const unsigned int hi = xor_lane32<LJ>(static_cast<unsigned int>(static_cast<unsigned long long>(x) >> 32));
+        return static_cast<W>((static_cast<unsigned long long>(hi) << 32) | lo);
+    }
+}
+
 template <int LJ, typename W>
 __device__ inline void transpose_round(W& x, int G, int o) {
     constexpr int j = 1 << LJ;
@@ -966,7 +996,7 @@ __device__ inline void transpose_round(W& x, int G, int o) {
                                                      0x0F0F0F0F0F0F0F0Full, 0x00FF00FF00FF00FFull,
                                                      0x0000FFFF0000FFFFull, 0x00000000FFFFFFFFull};
             constexpr W m = static_cast<W>(kMask[LJ]);  // bits c with (c & j) == 0
-            const W y = __shfl_xor(x, j, 64);
+            const W y = xor_lane<LJ>(x);
             // the lower lane of a pair keeps its bits in m and takes the
             // partner's shifted up; the upper lane keeps ~m and takes them
             // shifted down (selects as bit operations, no branch)
