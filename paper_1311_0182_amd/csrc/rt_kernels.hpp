@@ -987,6 +987,32 @@ __device__ inline W xor_lane(W x) {
     }
 }
 
+// Sum over aligned groups of `width` lanes (a power of two <= 32) in FP32,
+// butterfly order from width/2 down to 1 (the order of group_sum above).
+template <int LJ>
+__device__ inline void group_sum_round(float& v, int width) {
+    if ((1 << LJ) < width) v += __uint_as_float(xor_lane32<LJ>(__float_as_uint(v)));
+}
+
+__device__ inline float group_sum_f32(float v, int width) {
+    group_sum_round<4>(v, width);
+    group_sum_round<3>(v, width);
+    group_sum_round<2>(v, width);
+    group_sum_round<1>(v, width);
+    group_sum_round<0>(v, width);
+    return v;
+}
+
+__device__ inline unsigned long long wave_sum_u64_fast(unsigned long long v) {
+    v += xor_lane<5>(v);
+    v += xor_lane<4>(v);
+    v += xor_lane<3>(v);
+    v += xor_lane<2>(v);
+    v += xor_lane<1>(v);
+    v += xor_lane<0>(v);
+    return v;
+}
+
 template <int LJ, typename W>
 __device__ inline void transpose_round(W& x, int G, int o) {
     constexpr int j = 1 << LJ;
@@ -1559,8 +1585,14 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
         floored = true;
     }
     // absorbed / passing photons of (j, nu): sum over the n_rc lanes
-    const R ag = group_sum(asum + aerr, nrc);
-    const R pg = group_sum(psum + perr, nrc);
+    R ag, pg;
+    if constexpr (f32) {
+        ag = group_sum_f32(asum + aerr, nrc);
+        pg = group_sum_f32(psum + perr, nrc);
+    } else {
+        ag = group_sum(asum + aerr, nrc);
+        pg = group_sum(psum + perr, nrc);
+    }
     if (valid && r == 0 && (ag != R(0) || pg != R(0))) {
         a.A[ia] = A0 + static_cast<double>(ag) * U;
         a.P[ia] = P0 + static_cast<double>(pg) * U;
@@ -1745,7 +1777,7 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
     // the tile's running tallies of packets moved, bytes and steps run
     if (tile_act && lane == 0) a.cnt[kCntAct0 + kCntLine * a.act_wr] = 1;
     const unsigned long long nupd = __popcll(__ballot(departed));
-    const unsigned long long wb = wave_sum_u64(nbytes);
+    const unsigned long long wb = f32 ? wave_sum_u64_fast(nbytes) : wave_sum_u64(nbytes);
     if (lane < 3) a.part[3 * tile + lane] = tally + (lane == 0 ? nupd : (lane == 1 ? wb : 1ull));
 }
 
