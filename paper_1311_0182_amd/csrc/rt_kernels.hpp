@@ -505,7 +505,7 @@ struct VipArgs {
 // round*kVipLanes + sub-lane); the lowest accepted attempt wins, as if drawn
 // one by one.  Every lane of the group returns the point.  False if no attempt
 // is accepted.
-constexpr int kVipLanes = 8;
+constexpr int kVipLanes = 4;
 
 __device__ inline bool vip_draw_group(const VipArgs& a, uint32_t step, const Vip& q, bool live, int depth, int sub,
                                       int gshift, double p[3]) {
