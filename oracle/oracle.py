@@ -80,6 +80,9 @@ def lib():
         L.or_vip_sample.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, dp,
                                     C.c_int32, dp]
         L.or_merge_packets.argtypes = [C.c_int32, dp, dp, dp, dp, dp, dp]
+        L.or_shell_profile.restype = C.c_int
+        L.or_shell_profile.argtypes = [C.c_int64, C.c_int32, dp, dp, C.c_double, dp, dp, C.c_double,
+                                       C.c_double, C.c_int32, C.c_int32, C.c_double, dp, i64p]
         _lib = L
     return _lib
 
@@ -276,3 +279,25 @@ def merge_packets(N, d, c):
     oc = C.c_double(0)
     lib().or_merge_packets(len(N), Np, dp_, cp, C.byref(oN), _ptr(od, C.c_double), C.byref(oc))
     return oN.value, od, oc.value
+
+
+def shell_profile(pos, P, dt, center, r_max, n_shells, axis=None, half_height=0.0, mean=False, norm=1.0):
+    """Intensity profile of the passing photons P[n, n_freq] (sections 3 and 4):
+    returns (prof[n_shells, n_freq], count[n_shells])."""
+    pos, pp = _d(np.asarray(pos).reshape(-1, 3))
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    n = pos.shape[0]
+    P = P.reshape(n, -1)
+    nf = P.shape[1]
+    c, cp = _d(np.asarray(center, dtype=np.float64).reshape(3))
+    ap = None
+    if axis is not None:
+        a, ap = _d(np.asarray(axis, dtype=np.float64).reshape(3))
+    prof = np.empty((n_shells, nf))
+    cnt = np.empty(n_shells, dtype=np.int64)
+    rc = lib().or_shell_profile(n, nf, pp, _ptr(P, C.c_double), float(dt), cp, ap, float(half_height),
+                                float(r_max), int(n_shells), int(bool(mean)), float(norm),
+                                _ptr(prof, C.c_double), _ptr(cnt, C.c_int64))
+    if rc != 0:
+        raise ValueError(lib().or_error().decode())
+    return prof, cnt

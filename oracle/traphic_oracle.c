@@ -1305,3 +1305,74 @@ void or_cone_masks(const or_sim *S, uint64_t *mask)
         }
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Intensity profiles (section 3, radial profiles of the Stromgren tests;    */
+/* section 4, cylindrical-shell profiles of the shadow test).                */
+/* ------------------------------------------------------------------------ */
+
+/* The paper measures the intensity at particle j in bin nu as the photons
+ * that passed through j during one RT step divided by that step,
+ * I_j = P_j / dt.  Summed over a thin spherical shell around the source this
+ * is the number of photons per unit time crossing the sphere of radius r,
+ * 4 pi r^2 I(r); the shadow test averages I_j over thin cylindrical shells
+ * around the shadow's axis instead, between two planes normal to it.  Bins stay
+ * separate, so the source and the diffuse (RR-bin) components are separate
+ * columns; both are divided by a normalisation the caller chooses (I_0, the
+ * photons emitted per unit time, or a reference shell's value).
+ *
+ * Shells have width dr = r_max / n_shells; particle j lies in shell
+ * floor(r_j / dr) when that is below n_shells, r_j being its distance from
+ * center (axis NULL) or from the line through center along axis.  axis may
+ * have any nonzero length (it is normalised here); half_height > 0 keeps only
+ * particles with |(x_j - center) . u| <= half_height.  mean = 0 sums over the
+ * shell, mean = 1 averages over its particles (0 for an empty shell).
+ * prof[n_shells * nf] (shell-major), count[n_shells].  Returns 0, or -1 on a
+ * bad argument. */
+int or_shell_profile(int64_t n, int32_t nf, const double *pos, const double *P, double dt,
+                     const double center[3], const double *axis, double half_height, double r_max,
+                     int32_t n_shells, int32_t mean, double norm, double *prof, int64_t *count)
+{
+    if (n < 0 || nf < 1 || n_shells < 1 || !(dt > 0.0) || !(r_max > 0.0) || !(norm > 0.0)) {
+        set_err("shell profile: bad argument");
+        return -1;
+    }
+    double u[3] = {0.0, 0.0, 0.0};
+    if (axis) {
+        double a2 = axis[0] * axis[0] + axis[1] * axis[1] + axis[2] * axis[2];
+        if (!(a2 > 0.0)) {
+            set_err("shell profile: zero axis");
+            return -1;
+        }
+        double a = sqrt(a2);
+        for (int k = 0; k < 3; ++k) u[k] = axis[k] / a;
+    }
+    double dr = r_max / n_shells;
+    for (int64_t k = 0; k < (int64_t)n_shells * nf; ++k) prof[k] = 0.0;
+    for (int32_t k = 0; k < n_shells; ++k) count[k] = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        const double *x = pos + 3 * j;
+        double d[3] = {x[0] - center[0], x[1] - center[1], x[2] - center[2]};
+        double r2;
+        if (axis) {
+            double t = d[0] * u[0] + d[1] * u[1] + d[2] * u[2];
+            if (half_height > 0.0 && fabs(t) > half_height) continue;
+            double q[3] = {d[0] - t * u[0], d[1] - t * u[1], d[2] - t * u[2]};
+            r2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+        } else {
+            r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        }
+        double s = floor(sqrt(r2) / dr);
+        if (!(s < (double)n_shells)) continue;
+        int32_t k = (int32_t)s;
+        count[k] += 1;
+        for (int32_t nu = 0; nu < nf; ++nu) prof[(int64_t)k * nf + nu] += P[j * nf + nu] / dt;
+    }
+    for (int32_t k = 0; k < n_shells; ++k)
+        for (int32_t nu = 0; nu < nf; ++nu) {
+            double v = prof[(int64_t)k * nf + nu];
+            if (mean) v = count[k] > 0 ? v / (double)count[k] : 0.0;
+            prof[(int64_t)k * nf + nu] = v / norm;
+        }
+    return 0;
+}

@@ -17,7 +17,8 @@
  * membership against extended-precision angles, exact integer cases and the
  * 4 pi / N_TC solid angle; uniform virtual-particle sampling (sector centroid);
  * the merge rule; neighbour lists against brute force; 1-D chain attenuation;
- * photon conservation; case-B I-front growth; the case-B/case-A ratio in the
+ * photon conservation; case-B I-front growth; shell profiles on hand-placed
+ * particles and against an independent membership test; the case-B/case-A ratio in the
  * optically thin centre; on-the-spot balance of recombination radiation in
  * optically thick gas; the Riccati closed form of the isothermal chemistry.
  *
@@ -84,6 +85,10 @@ void or_merge_packets(int32_t n, const double *N, const double *d, const double 
                       double *od, double *oc);
 void or_knn_points(const or_sim *S, int32_t inst, int64_t n_q, const double *q,
                    int32_t *ngb, double *h);
+/* Intensity profile in spherical or cylindrical shells (sections 3 and 4). */
+int or_shell_profile(int64_t n, int32_t nf, const double *pos, const double *P, double dt,
+                     const double center[3], const double *axis, double half_height, double r_max,
+                     int32_t n_shells, int32_t mean, double norm, double *prof, int64_t *count);
 
 #ifdef __cplusplus
 }

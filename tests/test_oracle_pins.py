@@ -515,3 +515,76 @@ def test_heating_cooling_integrator_against_ode_solver():
     e1, e2 = abs(res[0] - Tref), abs(res[1] - Tref)
     assert e2 < 0.01 * Tref
     assert e2 < e1
+
+
+# ----- intensity profiles (sections 3 and 4) -----------------------------------
+
+def test_shell_profile_spherical_hand_placed():
+    # particles placed at known distances from an off-origin centre; shells of
+    # width 1 out to 3; two bins; dt = 2 halves every count
+    c = np.array([1.0, 1.0, 1.0])
+    off = np.array([[0.5, 0, 0], [0, -1.5, 0], [0, 0, 1.25], [1.2, 1.6, 0.5], [3.5, 0, 0], [2, 2, 2]])
+    P = np.array([[2, 20], [4, 40], [6, 60], [8, 80], [10, 100], [12, 120]], dtype=float)
+    prof, cnt = O.shell_profile(c + off, P, 2.0, c, 3.0, 3)
+    assert cnt.tolist() == [1, 2, 1]
+    assert prof.tolist() == [[1, 10], [5, 50], [4, 40]]
+    prof, cnt = O.shell_profile(c + off, P, 2.0, c, 3.0, 3, mean=True, norm=2.0)
+    assert prof.tolist() == [[0.5, 5], [1.25, 12.5], [2, 20]]
+
+
+@pytest.mark.parametrize("axis", [(1.0, 1.0, 0.0), (-3.0, -3.0, 0.0)])
+def test_shell_profile_cylindrical_hand_placed(axis):
+    # axis along (1,1,0) through the origin, height cut |t| <= 2, shells of width 1:
+    # distances from the axis 0, 1.5, sqrt 2, (cut: t = 2 sqrt 2), 2.5, sqrt 8.09, 3.2
+    pos = np.array([[1, 1, 0], [1, 1, 1.5], [-1, 1, 0], [2, 2, 0.5], [0, 0, 2.5], [-2, 2, 0.3], [0, 0, -3.2]])
+    P = np.arange(1.0, 8.0)[:, None]
+    prof, cnt = O.shell_profile(pos, P, 1.0, np.zeros(3), 3.0, 3, axis=axis, half_height=2.0)
+    assert cnt.tolist() == [1, 2, 2]
+    assert prof[:, 0].tolist() == [1, 5, 11]
+    prof, _ = O.shell_profile(pos, P, 1.0, np.zeros(3), 3.0, 3, axis=axis, half_height=2.0, mean=True)
+    assert prof[:, 0].tolist() == [1, 2.5, 5.5]
+    # without the cut the fourth particle (distance 0.5 from the axis) joins shell 0
+    _, cnt = O.shell_profile(pos, P, 1.0, np.zeros(3), 3.0, 3, axis=axis)
+    assert cnt.tolist() == [2, 2, 2]
+
+
+def test_shell_profile_against_independent_membership():
+    # membership by comparing squared distances with squared shell edges (sphere)
+    # and squared distances from the axis by a cross product (cylinder)
+    rng = np.random.default_rng(7)
+    pos = rng.random((2000, 3))
+    P = rng.random((2000, 2)) * 1e50
+    dt, c, n_sh, r_max = 3.1e12, np.array([0.5, 0.45, 0.55]), 17, 0.6
+    edges2 = (np.arange(1, n_sh + 1) * (r_max / n_sh)) ** 2
+    d = pos - c
+    for axis in (None, np.array([0.3, -0.2, 0.9])):
+        if axis is None:
+            r2 = np.einsum("ij,ij->i", d, d)
+            keep = np.ones(len(pos), bool)
+        else:
+            u = axis / np.linalg.norm(axis)
+            r2 = np.sum(np.cross(d, u) ** 2, axis=1)
+            keep = np.abs(d @ u) <= 0.3
+        sh = np.searchsorted(edges2, r2, side="right")
+        keep &= sh < n_sh
+        # no particle within rounding distance of an edge, so both memberships are exact
+        near = np.min(np.abs(r2[:, None] - edges2[None, :]) / edges2[None, :], axis=1)
+        assert np.min(near[keep | (sh == n_sh)]) > 1e-9
+        want_n = np.bincount(sh[keep], minlength=n_sh)
+        want = np.stack([np.bincount(sh[keep], weights=P[keep, k] / dt, minlength=n_sh) for k in range(2)], 1)
+        prof, cnt = O.shell_profile(pos, P, dt, c, r_max, n_sh, axis=axis, half_height=0.3)
+        assert np.array_equal(cnt, want_n)
+        assert np.max(np.abs(prof - want) / np.maximum(want, 1e-300)) < 1e-13
+    # every particle inside a large sphere: the shells add up to all passing photons
+    prof, cnt = O.shell_profile(pos, P, dt, c, 10.0, 5)
+    assert cnt.sum() == len(pos)
+    assert np.allclose(prof.sum(0), (P / dt).sum(0), rtol=1e-13)
+
+
+def test_shell_profile_rejects_bad_arguments():
+    pos, P = np.zeros((2, 3)), np.ones((2, 1))
+    for kw in (dict(dt=0.0), dict(r_max=-1.0), dict(n_shells=0), dict(norm=0.0), dict(axis=(0, 0, 0))):
+        a = dict(dt=1.0, r_max=1.0, n_shells=2, norm=1.0, axis=None)
+        a.update(kw)
+        with pytest.raises(ValueError):
+            O.shell_profile(pos, P, a["dt"], np.zeros(3), a["r_max"], a["n_shells"], axis=a["axis"], norm=a["norm"])
