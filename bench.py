@@ -75,6 +75,30 @@ def cpu_baseline(budget_s):
                        f"{dt:.1f} s; neighbour search {t_init:.1f} s not counted)")
 
 
+def shell_profile_timing(ctx, cfg, reps=50):
+    """The intensity-profile diagnostic on the state left by the timed run: wall
+    time per call (stream synchronisation, two fills, the kernel and the copy of
+    the histogram back included); the kernel's own duration is in the trace."""
+    import numpy as np
+    box = np.asarray(cfg["box"][0], dtype=float)
+    L = float(box[3] - box[0])
+    src = np.asarray(cfg["sources"]["pos"][0], dtype=float)
+    mid = 0.5 * (box[:3] + box[3:])
+    out = {}
+    for name, kw in (("sphere_128", dict(center=src, r_max=0.5 * L, n_shells=128)),
+                     ("cylinder_64", dict(center=mid, r_max=0.5 * L, n_shells=64, axis=(1.0, 0.0, 0.0),
+                                          half_height=0.25 * L, mean=True))):
+        ctx.shell_profile(**kw)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.shell_profile(**kw)
+        out[name + "_ms_per_call"] = (time.perf_counter() - t0) / reps * 1e3
+    n, nf = int(cfg["pos"].shape[0]), int(cfg["params"]["n_freq"])
+    out["particles"] = n
+    out["algorithmic_bytes_per_call"] = n * (24 + 8 * nf)
+    return out
+
+
 def batched_runs(K):
     """The batched workload: every instance in the same launches, FP32 and FP64
     transport, against the same instances solved one after another in FP64."""
@@ -180,7 +204,8 @@ def main():
         t = time.perf_counter() - t0
         st = ctx.state()
         tm = ctx.timing() if timing else None
-        res = dict(t=t, updates=int(st["counters"][3]) - u0, state=st, timing=tm, shape=ctx.hop_shape())
+        prof = shell_profile_timing(ctx, cfg) if timing else None
+        res = dict(t=t, updates=int(st["counters"][3]) - u0, state=st, timing=tm, shape=ctx.hop_shape(), prof=prof)
         ctx.close()
         return res
 
@@ -245,6 +270,7 @@ def main():
         "ledger_residual_fp32": resid,
         "time_split_ms": {k: tm[k] for k in ("hop_ms", "vip_ms", "chem_ms", "emit_ms", "ledger_ms")},
         "ms_per_step_timed_run": r32t["t"] / K * 1e3,
+        "shell_profile": r32t["prof"],
     }
     if r64:
         dx = float(np.max(np.abs(r32["state"]["xHI"] - r64["state"]["xHI"])))

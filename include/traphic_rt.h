@@ -126,6 +126,37 @@ rt_status rt_step(rt_ctx *ctx, int32_t n_steps);
 rt_status rt_get_state(rt_ctx *ctx, double *x_HI, double *T, double *absorbed, double *passing,
                        double *ledger, int64_t *counters);
 
+/* Intensity profile of the last step (section 3: radial profiles of the
+ * Stromgren tests, split into source and diffuse photons; section 4: profiles
+ * of the shadow test in cylindrical shells around the shadow's axis).  The
+ * intensity measure at particle j in bin nu is the number of photons that
+ * passed through j during the last RT step divided by dt; its sum over a thin
+ * spherical shell around the source is the photons per second crossing the
+ * sphere of that radius, 4 pi r^2 I(r).  Bins are kept apart, so the RR bin
+ * gives the diffuse component.
+ *   inst              instance whose particles are binned
+ *   passing           NULL: the context's passing photons of the last step;
+ *                     else a host array [N*n_freq] (photons) binned instead
+ *   center[3]         centre of the spheres, or a point on the cylinder axis (cm)
+ *   axis[3]           NULL: spherical shells; else the cylinder axis direction
+ *                     (any nonzero length)
+ *   half_height       cylinders: > 0 keeps only particles with
+ *                     |(x - center) . axis/|axis|| <= half_height; <= 0: no cut
+ *   r_max, n_shells   shells of width r_max / n_shells; particle j lies in shell
+ *                     floor(r_j / (r_max / n_shells)) if that is < n_shells
+ *                     (r_j: distance from center, or from the axis);
+ *                     1 <= n_shells <= 2048, n_shells * n_freq <= 6144
+ *   mean              0: sum over the shell; 1: mean over its particles (0 if empty)
+ *   norm              > 0; every output is divided by it (e.g. I_0, the source's
+ *                     photons per second; 1 for none)
+ *   prof[n_shells*n_freq]  out, shell-major, photons/s / norm
+ *   count[n_shells]   out, particles per shell (may be NULL)
+ * Synchronises the stream.  Errors: RT_EINVAL (nothing written), RT_ENOMEM,
+ * RT_EDEVICE. */
+rt_status rt_shell_profile(rt_ctx *ctx, int32_t inst, const double *passing, const double *center,
+                           const double *axis, double half_height, double r_max, int32_t n_shells,
+                           int32_t mean, double norm, double *prof, int64_t *count);
+
 /* Packet bins [N][n_freq][n_rc] in physical units: photons, unit direction
  * (3 per bin) and clock in s since the start of the last step.  Any pointer may be NULL. */
 rt_status rt_get_bins(rt_ctx *ctx, double *N, double *dir, double *clock);

@@ -12,6 +12,7 @@
 
 #include "../../include/traphic_rt.h"
 #include "rt_kernels.hpp"
+#include "rt_profile.hpp"
 
 using namespace trt;
 
@@ -77,6 +78,10 @@ struct rt_ctx {
     double* ers = nullptr;
     std::vector<int> h_em_inst;
     double* E_src = nullptr;
+    // intensity profiles: histogram and an optional copy of caller-given passing photons
+    double* prof_sum = nullptr;
+    unsigned long long* prof_cnt = nullptr;
+    double* prof_in = nullptr;
     // dynamic state: resting packets (in place), moving packets and delivery
     // masks (by forward-step parity), work marks of the tiles
     void* pk = nullptr;
@@ -169,6 +174,24 @@ rt_status dalloc(rt_ctx* c, void** out, size_t bytes) {
     c->owned.push_back({q, bytes});
     *out = q;
     return RT_OK;
+}
+
+// Free a buffer this context allocated (no-op for NULL).  Only once no queued
+// work or captured graph refers to it.
+template <typename T>
+void dfree(rt_ctx* c, T*& p) {
+    if (!p) return;
+    void* q = const_cast<void*>(static_cast<const void*>(p));
+    for (size_t k = 0; k < c->owned.size(); ++k)
+        if (c->owned[k].p == q) {
+            if (c->p.dealloc)
+                c->p.dealloc(c->p.alloc_user, q);
+            else if (!c->p.alloc)
+                (void)hipFree(q);
+            c->owned.erase(c->owned.begin() + static_cast<long>(k));
+            break;
+        }
+    p = nullptr;
 }
 
 template <typename T>
@@ -982,6 +1005,21 @@ rt_status rt_add_sources(rt_ctx* c, int32_t n_src, const int32_t* inst, const in
                 return fail(c, RT_EINVAL, "bad source rate");
     }
     if (total >= (1ll << 24)) return fail(c, RT_EINVAL, "too many emitters");
+    // The captured forward steps refer to the emitters' buffers (virtual
+    // particles of empty emission cones): drop them before the buffers change.
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (auto& kv : c->hop_graphs) (void)hipGraphExecDestroy(kv.second);
+    c->hop_graphs.clear();
+    dfree(c, c->em_kind);
+    dfree(c, c->em_inst);
+    dfree(c, c->em_pos);
+    dfree(c, c->em_pk);
+    dfree(c, c->E_src);
+    dfree(c, c->em_ngb);
+    dfree(c, c->em_h);
+    dfree(c, c->ecd);
+    dfree(c, c->exs);
+    dfree(c, c->ers);
     std::vector<int> ek(total), ei(total);
     std::vector<double> ep(3 * total), epk(total * c->nf);
     std::vector<double> esrc(static_cast<size_t>(c->n_inst) * c->nf, 0.0);
@@ -1078,6 +1116,76 @@ rt_status rt_get_state(rt_ctx* c, double* x_HI, double* T, double* absorbed, dou
         counters[1] = h[kCntHops];
         counters[2] = h[kCntVips];
         counters[3] = h[kCntUpdates];
+    }
+    return RT_OK;
+}
+
+rt_status rt_shell_profile(rt_ctx* c, int32_t inst, const double* passing, const double* center, const double* axis,
+                           double half_height, double r_max, int32_t n_shells, int32_t mean, double norm, double* prof,
+                           int64_t* count) {
+    if (!c) return RT_EINVAL;
+    if (c->sticky) return RT_EDEVICE;
+    if (!center || !prof || inst < 0 || inst >= c->n_inst) return fail(c, RT_EINVAL, "shell profile: bad pointer or instance");
+    if (n_shells < 1 || n_shells > kProfMaxShells || static_cast<long long>(n_shells) * c->nf > kProfMaxCells)
+        return fail(c, RT_EINVAL, "shell profile: n_shells out of range");
+    if (!(r_max > 0.0) || !(norm > 0.0) || !std::isfinite(r_max) || !std::isfinite(norm) || !std::isfinite(half_height) ||
+        !std::isfinite(center[0]) || !std::isfinite(center[1]) || !std::isfinite(center[2]))
+        return fail(c, RT_EINVAL, "shell profile: r_max, norm, half_height and center must be finite, r_max and norm > 0");
+    if (axis && !(std::isfinite(axis[0]) && std::isfinite(axis[1]) && std::isfinite(axis[2]) &&
+                  axis[0] * axis[0] + axis[1] * axis[1] + axis[2] * axis[2] > 0.0))
+        return fail(c, RT_EINVAL, "shell profile: axis must be finite and nonzero");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (!c->prof_sum) {
+        TRY(alloc_n(c, &c->prof_sum, kProfMaxCells));
+        TRY(alloc_n(c, &c->prof_cnt, kProfMaxShells));
+    }
+    const double* Pd = c->P;
+    if (passing) {
+        if (!c->prof_in) TRY(alloc_n(c, &c->prof_in, c->N * c->nf));
+        HIPCHK(c, hipMemcpy(c->prof_in, passing, sizeof(double) * c->N * c->nf, hipMemcpyHostToDevice));
+        Pd = c->prof_in;
+    }
+    const int ncell = n_shells * c->nf;
+    TRY(fill_f64(c, c->prof_sum, ncell, 0.0));
+    TRY(fill_i32(c, reinterpret_cast<int*>(c->prof_cnt), 2ll * n_shells, 0));
+    ProfileArgs a{};
+    a.pos = c->pos;
+    a.P = Pd;
+    a.j0 = c->inst_off[inst];
+    a.j1 = c->inst_off[inst + 1];
+    a.nf = c->nf;
+    a.n_shells = n_shells;
+    a.cyl = axis ? 1 : 0;
+    a.c0 = center[0];
+    a.c1 = center[1];
+    a.c2 = center[2];
+    if (axis) {
+        a.a0 = axis[0];
+        a.a1 = axis[1];
+        a.a2 = axis[2];
+    }
+    a.half_height = half_height;
+    a.r_max = r_max;
+    a.dt = c->p.dt;
+    a.sum = c->prof_sum;
+    a.cnt = c->prof_cnt;
+    // about 8 particles per thread, at most one workgroup per CU
+    const long long n = a.j1 - a.j0;
+    const unsigned grid = static_cast<unsigned>(std::max<long long>(1, std::min<long long>(256, (n + 2047) / 2048)));
+    const size_t lds = sizeof(double) * ncell + sizeof(unsigned) * n_shells;
+    hipLaunchKernelGGL(k_shell_profile, dim3(grid), dim3(kProfBlock), lds, c->stream, a);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::vector<unsigned long long> cnt(n_shells);
+    HIPCHK(c, hipMemcpy(prof, c->prof_sum, sizeof(double) * ncell, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(cnt.data(), c->prof_cnt, sizeof(unsigned long long) * n_shells, hipMemcpyDeviceToHost));
+    for (int k = 0; k < n_shells; ++k) {
+        if (count) count[k] = static_cast<int64_t>(cnt[k]);
+        for (int nu = 0; nu < c->nf; ++nu) {
+            double v = prof[static_cast<long long>(k) * c->nf + nu];
+            if (mean) v = cnt[k] > 0 ? v / static_cast<double>(cnt[k]) : 0.0;
+            prof[static_cast<long long>(k) * c->nf + nu] = v / norm;
+        }
     }
     return RT_OK;
 }

@@ -26,7 +26,7 @@ DEALLOC_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 EXPORTS = ["rt_init", "rt_add_sources", "rt_step", "rt_get_state", "rt_get_bins", "rt_get_neighbours",
            "rt_n_emitters", "rt_get_emitter_neighbours", "rt_get_cone_masks", "rt_get_pending_rr",
            "rt_set_timing", "rt_get_timing", "rt_set_hop_shape", "rt_get_hop_shape", "rt_get_state_blob",
-           "rt_set_state_blob", "rt_destroy",
+           "rt_set_state_blob", "rt_shell_profile", "rt_destroy",
            "rt_last_error"]
 
 
@@ -95,6 +95,9 @@ def load():
     L.rt_get_state_blob.argtypes = [C.c_void_p, C.c_void_p, P(C.c_size_t)]
     L.rt_set_state_blob.restype = C.c_int
     L.rt_set_state_blob.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
+    L.rt_shell_profile.restype = C.c_int
+    L.rt_shell_profile.argtypes = [C.c_void_p, C.c_int32, dp, dp, dp, C.c_double, C.c_double, C.c_int32,
+                                   C.c_int32, C.c_double, dp, i64p]
     L.rt_destroy.restype = None
     L.rt_destroy.argtypes = [C.c_void_p]
     L.rt_last_error.restype = C.c_char_p
@@ -251,6 +254,28 @@ class Context:
         ms = np.zeros(3)
         self._check(load().rt_get_hop_shape(self.h, C.byref(sh), C.byref(tu), _p(ms, C.c_double)))
         return dict(shape=int(sh.value), tuned=bool(tu.value), ms_per_launch=[float(x) for x in ms])
+
+    def shell_profile(self, center, r_max, n_shells, axis=None, half_height=0.0, mean=False, norm=1.0,
+                      inst=0, passing=None):
+        """rt_shell_profile: (prof[n_shells, n_freq], count[n_shells])."""
+        L = load()
+        c = _f64(np.asarray(center).reshape(3))
+        ap = None
+        if axis is not None:
+            a = _f64(np.asarray(axis).reshape(3))
+            ap = _p(a, C.c_double)
+        pp = None
+        if passing is not None:
+            ps = _f64(passing)
+            if ps.size != self.N * self.nf:
+                raise ValueError("passing must hold N * n_freq values")
+            pp = _p(ps, C.c_double)
+        prof = np.empty((int(n_shells), self.nf))
+        cnt = np.empty(int(n_shells), dtype=np.int64)
+        self._check(L.rt_shell_profile(self.h, int(inst), pp, _p(c, C.c_double), ap, float(half_height),
+                                       float(r_max), int(n_shells), int(bool(mean)), float(norm),
+                                       _p(prof, C.c_double), _p(cnt, C.c_int64)))
+        return prof, cnt
 
     def get_blob(self):
         n = C.c_size_t(0)
