@@ -221,6 +221,107 @@ def shadow(n_side=128, box_kpc=6.6, n_h=2e-4, clump_nh=0.04, clump_r_kpc=0.8,
     return _pack(f"shadow{n_side}", params, sigma, eps, [inst], src, n_steps)
 
 
+# Section 4 quotes one grey value pair for the 1e5 K blackbody when all its
+# photons travel in one bin.
+SIGMA_BB1E5_GREY = 1.6e-18     # cm^2
+EPS_BB1E5_GREY_EV = 6.3        # eV
+# Case-A and case-B recombination coefficients of hydrogen at 1e4 K (standard
+# tabulated values), used only to size the boundary sources of the recipe below.
+ALPHA_A_1E4 = 4.18e-13         # cm^3/s
+# Boundary-source grid faces: (normal axis, side) for y = lo, y = hi, z = lo, z = hi.
+BOUNDARY_FACES = ((1, 0), (1, 1), (2, 0), (2, 1))
+
+
+def boundary_rr_intensity(flux, n_h, sigma=SIGMA_13P6):
+    """Appendix B: recombination radiation reaching a point from uniformly
+    ionized gas around it, for monochromatic radiation of cross-section sigma.
+    Photoionization equilibrium with the front, sigma F (1 - x) = alpha_B n_H
+    x^2 (x = x_HII), fixes the emissivity of ground-state recombinations,
+    E = alpha_1 n_H^2 x^2 (alpha_1 = alpha_A - alpha_B), and the mean free path
+    of their photons, lambda = 1 / (sigma n_H (1 - x)); integrating
+    E e^{-r/lambda} / (4 pi r^2) over the sphere of radius lambda gives the
+    intensity I = (1 - 1/e) lambda E (photons/s/cm^2), the appendix's 0.63 lambda E."""
+    a = ALPHA_B_1E4 * n_h / (sigma * flux)
+    x = 2.0 / (1.0 + math.sqrt(1.0 + 4.0 * a))          # positive root of a x^2 + x - 1 = 0
+    lam = 1.0 / (sigma * n_h * (1.0 - x))
+    emis = (ALPHA_A_1E4 - ALPHA_B_1E4) * n_h * n_h * x * x
+    return dict(x_HII=x, mfp=lam, emissivity=emis, intensity=(1.0 - math.exp(-1.0)) * lam * emis)
+
+
+def shadow_boundary(n_side=32, box_kpc=13.2, n_h=1e-3, clump_nh=1.0, clump_r=0.1,
+                    clump_c=(0.27, 0.5, 0.5), flux=1e6, n_pp=100, n_bd=50, n_ngb=48, n_tc=16,
+                    n_rc=8, n_ec=8, t0=1e4, n_steps=100, seed_k=4, dt_myr=0.1, **pkw):
+    """Shadow set-up of section 4 with recombination radiation from outside the
+    box (appendix B): 32^3 particles in a 13.2 kpc box at n_H = 1e-3, a plane
+    front of 1e6 photons/s/cm^2 from the x = 0 face (n_pp^2 emitters) in one grey
+    bin of the 1e5 K blackbody, a dense clump (radius clump_r L at clump_c L)
+    casting the shadow, N_RC = 8, dt = dt_em = 0.1 Myr.  Bins: 0 source,
+    1 recombination photons emitted in the box, 2 recombination photons from
+    outside the box, 3 unused (no source: packet slots per particle, N_RC times
+    the bins, must be a power of two).
+    The outside-box photons come from n_bd^2 isotropic point sources on a
+    regular grid on each of the four faces parallel to the front's direction,
+    each emitting I L^2 / n_bd^2 photons/s in bin 2 (boundary_rr_intensity: the
+    appendix's equilibrium estimate for monochromatic 13.6 eV photons).
+    They start radiating once the I-front has passed them, which the caller
+    decides between steps: cfg["boundary"] holds their positions and rates and
+    boundary_sources(cfg, on) gives the source set with those switched on."""
+    rng = np.random.default_rng(BASE_SEED + seed_k)
+    L = box_kpc * KPC_CM
+    lo = np.zeros(3)
+    pos = jittered_lattice(n_side, lo, L, rng)
+    c = np.asarray(clump_c, dtype=np.float64) * L
+    inside = np.sum((pos - c[None, :]) ** 2, axis=1) <= (clump_r * L) ** 2
+    nh = np.where(inside, clump_nh, n_h)
+    NH = nh * (L ** 3 / pos.shape[0])
+    n_freq = 4
+    params = default_params(
+        n_ngb=n_ngb, n_tc=n_tc, n_rc=n_rc, n_ec=n_ec, n_freq=n_freq, rr_bin=1,
+        recomb_mode=RR_TRANSPORT, isothermal=0, dt=dt_myr * MYR_S, n_em=1,
+        seed=BASE_SEED + seed_k)
+    params.update(pkw)
+    sigma = [SIGMA_BB1E5_GREY, SIGMA_13P6, SIGMA_13P6, SIGMA_13P6]
+    eps = [EPS_BB1E5_GREY_EV * EV_ERG] + [EPS_RR_EV * EV_ERG] * 3
+    rate = np.zeros((1, n_freq))
+    rate[0, 0] = flux
+    src = dict(inst=np.zeros(1, np.int32), kind=np.array([SRC_PLANE_XLO], np.int32),
+               pos=np.zeros((1, 3)), rate=rate, n_side=np.array([n_pp], np.int32))
+    inst = dict(pos=pos, nH=nh, NH=NH, xHI=np.ones(pos.shape[0]), T=np.full(pos.shape[0], t0),
+                box_lo=lo, box_hi=lo + L)
+    cfg = _pack(f"shadow_boundary{n_side}", params, sigma, eps, [inst], src, n_steps)
+    bi = boundary_rr_intensity(flux, n_h)
+    g = (np.arange(n_bd) + 0.5) * (L / n_bd)
+    bpos = []
+    for ax, side in BOUNDARY_FACES:
+        t1, t2 = [k for k in range(3) if k != ax]
+        for u in g:
+            for v in g:
+                p = np.zeros(3)
+                p[ax] = lo[ax] + side * L
+                p[t1] = lo[t1] + u
+                p[t2] = lo[t2] + v
+                bpos.append(p)
+    brate = np.zeros((len(bpos), n_freq))
+    brate[:, 2] = bi["intensity"] * L * L / (n_bd * n_bd)
+    cfg["boundary"] = dict(pos=np.array(bpos), rate=brate, **bi)
+    return cfg
+
+
+def boundary_sources(cfg, on):
+    """The front's sources plus the boundary sources of shadow_boundary whose
+    entry in the boolean mask on[4 n_bd^2] is set."""
+    on = np.asarray(on, dtype=bool)
+    b, s = cfg["boundary"], cfg["sources"]
+    n = int(on.sum())
+    return dict(
+        inst=np.concatenate([s["inst"], np.zeros(n, np.int32)]),
+        kind=np.concatenate([s["kind"], np.full(n, SRC_POINT, np.int32)]),
+        pos=np.ascontiguousarray(np.concatenate([s["pos"], b["pos"][on]])),
+        rate=np.ascontiguousarray(np.concatenate([s["rate"], b["rate"][on]])),
+        n_side=np.concatenate([s["n_side"], np.zeros(n, np.int32)]),
+    )
+
+
 def instance(cfg, k):
     """Instance k of a batch as a workload of its own (same particles, box,
     sources and parameters)."""

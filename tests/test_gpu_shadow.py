@@ -8,6 +8,11 @@ relative, ledger residual 1e-12) and FP32 within its bars.  Full size (128^3
 particles, 134 M slots): too large for the oracle in a test, so FP32 transport
 is checked against the FP64 GPU path on the same inputs (ledger residuals 1e-6
 and 1e-12, totals, slab means and the 99.99% quantile of |dx_HI|).
+
+With recombination radiation from outside the box (appendix B): isotropic
+boundary sources on the four faces parallel to the front, switched on between
+steps once the I-front has passed them, in a bin of their own; checked against
+the oracle, with the cylindrical-shell profiles of the three components.
 """
 import sys
 
@@ -111,3 +116,58 @@ def test_shadow_full_size_fp32_against_fp64_gpu():
     for k in range(6):
         m = (xs >= k / 6) & (xs < (k + 1) / 6)
         assert abs(np.mean(x32[m]) - np.mean(x64[m])) <= 1e-5
+
+
+def _passed(cfg, xHI):
+    """Boundary sources the I-front has passed: their nearest particle is mostly ionized."""
+    b = cfg["boundary"]["pos"]
+    d2 = ((b[:, None, :] - cfg["pos"][None, :, :]) ** 2).sum(-1)
+    return xHI[np.argmin(d2, axis=1)] < 0.5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_boundary_rr_sources_against_oracle(precision):
+    from paper_1311_0182_amd import traphic_rt as RT
+    cfg = I.shadow_boundary(n_side=12, n_pp=16, n_bd=6, n_ngb=32)
+    say("shadow with boundary sources, 12^3,", precision)
+    s = O.OracleSim(cfg)
+    s.step(6)
+    # the switch is decided on the oracle's state and handed to both sides
+    on = _passed(cfg, s.state()["xHI"])
+    assert 0 < on.sum() < on.size
+    src = I.boundary_sources(cfg, on)
+    s.add_sources(src)
+    s.step(3)
+    ctx = RT.Context(cfg, precision=precision)
+    ctx.step(6)
+    ctx.add_sources(src)
+    ctx.step(3)
+    so, sg = s.state(), ctx.state()
+    say("on", int(on.sum()), "of", on.size, "max |dx_HI|", np.max(np.abs(sg["xHI"] - so["xHI"])),
+        "residual", np.max(residual(sg["ledger"])))
+    assert np.all(so["ledger"][0, 2, 0] > 0) and so["A"][:, 2].sum() > 0
+    if precision == "fp64":
+        assert np.array_equal(so["counters"], sg["counters"])
+        assert rel(sg["xHI"], so["xHI"]) < 1e-6
+        assert rel(sg["T"], so["T"]) < 1e-6
+        assert np.max(residual(sg["ledger"])) < 1e-12
+        assert rel(sg["ledger"][..., 0], so["ledger"][..., 0]) < 1e-12
+    else:
+        assert np.max(np.abs(sg["xHI"] - so["xHI"])) <= 1e-3
+        assert np.max(residual(sg["ledger"])) <= 1e-6
+    # section 4's diagnostic: mean intensity in cylindrical shells around the
+    # shadow's axis behind the clump, per component (source, RR from inside and
+    # from outside the box)
+    L = float(cfg["box"][0][3])
+    g = dict(center=(0.6 * L, 0.5 * L, 0.5 * L), r_max=0.5 * L, n_shells=6, axis=(1.0, 0.0, 0.0),
+             half_height=0.3 * L, mean=True)
+    pg, cg = ctx.shell_profile(**g)
+    po, co = O.shell_profile(cfg["pos"], so["P"], cfg["params"]["dt"], g["center"], g["r_max"], g["n_shells"],
+                             axis=g["axis"], half_height=g["half_height"], mean=True)
+    assert np.array_equal(cg, co)
+    assert po[:, 2].max() > 0
+    if precision == "fp64":
+        scale = np.maximum(np.max(np.abs(po), axis=0), 1e-300)
+        assert np.all(np.abs(pg - po) <= 1e-6 * scale)
+    ctx.close()
+    s.close()

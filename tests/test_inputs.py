@@ -52,3 +52,55 @@ def test_shadow_layout():
     assert set(np.unique(nh)) == {2e-4, 0.04}
     assert 0 < np.sum(nh == 0.04) < nh.size // 10
     assert cfg["sources"]["kind"][0] == I.SRC_PLANE_XLO and cfg["sources"]["n_side"][0] == 8
+
+
+def _paper(name):
+    import os
+    gold = os.path.join(os.path.dirname(__file__), "golden", "paper_numbers.txt")
+    for line in open(gold):
+        f = line.split()
+        if f and f[0] == name:
+            return float(f[1]), float(f[2])
+    raise KeyError(name)
+
+
+def test_boundary_rr_intensity_appendix_b():
+    from scipy.integrate import quad
+    b = I.boundary_rr_intensity(1e6, 1e-3)
+    # the appendix's mean free path for the section-4 flux and density
+    v, tol = _paper("lambda_mfp_kpc")
+    assert abs(b["mfp"] / I.KPC_CM / v - 1) < tol
+    # ionization balance holds at the root taken
+    x = b["x_HII"]
+    assert abs(I.SIGMA_13P6 * 1e6 * (1 - x) / (I.ALPHA_B_1E4 * 1e-3 * x * x) - 1) < 1e-9
+    # the intensity is the integral over the sphere of radius lambda_mfp ...
+    lam, E = b["mfp"], b["emissivity"]
+    val, err = quad(lambda r: 4 * np.pi * E * np.exp(-r / lam) / (4 * np.pi * r * r) * r * r, 0.0, lam)
+    assert abs(b["intensity"] / val - 1) < 1e-10
+    # ... which the appendix prints as 0.63 lambda E
+    v, tol = _paper("appB_intensity_factor")
+    assert abs(b["intensity"] / (lam * E) / v - 1) < tol
+
+
+def test_shadow_boundary_layout():
+    cfg = I.shadow_boundary(n_side=8, n_pp=10, n_bd=5)
+    p, L = cfg["params"], float(cfg["box"][0][3])
+    assert p["n_rc"] * p["n_freq"] == 32 and p["rr_bin"] == 1 and p["n_em"] == 1
+    b = cfg["boundary"]
+    assert b["pos"].shape == (4 * 25, 3)
+    on_face = np.isclose(b["pos"] % L, 0.0, atol=0.0) | np.isclose(b["pos"], L, rtol=0, atol=0)
+    # every boundary source lies on exactly one y or z face, none on an x face
+    assert np.all(on_face[:, 0] == False) and np.all(on_face[:, 1:].sum(1) == 1)
+    for ax, side in I.BOUNDARY_FACES:
+        sel = b["pos"][:, ax] == side * L
+        assert sel.sum() == 25
+        t = [k for k in range(3) if k != ax]
+        for k in t:   # cell-centred 5 x 5 grid over the face
+            assert np.allclose(np.unique(b["pos"][sel, k]) / L, (np.arange(5) + 0.5) / 5)
+    assert np.all(b["rate"][:, [0, 1, 3]] == 0)
+    assert np.isclose(b["rate"][:, 2].sum(), 4 * b["intensity"] * L * L)
+    on = np.zeros(100, bool)
+    on[[3, 50, 99]] = True
+    s = I.boundary_sources(cfg, on)
+    assert len(s["inst"]) == 4 and s["kind"][0] == I.SRC_PLANE_XLO and np.all(s["kind"][1:] == I.SRC_POINT)
+    assert np.array_equal(s["pos"][1:], b["pos"][on])
