@@ -1169,9 +1169,13 @@ rt_status rt_shell_profile(rt_ctx* c, int32_t inst, const double* passing, const
     a.dt = c->p.dt;
     a.sum = c->prof_sum;
     a.cnt = c->prof_cnt;
-    // about 8 particles per thread, at most one workgroup per CU
+    // Workgroups: small instances get one per 256 particles (up to 128), large
+    // ones one per 2048 (up to 256).  More would not help large instances: every
+    // workgroup's flush adds into the same few cache lines, and those atomics
+    // serialise.
     const long long n = a.j1 - a.j0;
-    const unsigned grid = static_cast<unsigned>(std::max<long long>(1, std::min<long long>(256, (n + 2047) / 2048)));
+    const unsigned grid = static_cast<unsigned>(std::max<long long>(
+        1, std::min<long long>(256, std::max<long long>((n + 2047) / 2048, std::min<long long>(128, (n + 255) / 256)))));
     const size_t lds = sizeof(double) * ncell + sizeof(unsigned) * n_shells;
     hipLaunchKernelGGL(k_shell_profile, dim3(grid), dim3(kProfBlock), lds, c->stream, a);
     HIPCHK(c, hipGetLastError());

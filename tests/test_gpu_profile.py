@@ -140,10 +140,14 @@ def test_shell_profile_edge_cases():
         _check(pg, cg, po, co)
     pg, cg = ctx.shell_profile(passing=P, center=src, r_max=2.0 * L, n_shells=1)
     assert cg[0] == n
-    # two calls in a row share the histogram: the second must not see the first
+    # two calls in a row share the histograms: the second must not see the first
     a1, c1 = ctx.shell_profile(passing=P, center=src, r_max=0.5 * L, n_shells=64)
     a2, c2 = ctx.shell_profile(passing=P, center=src, r_max=0.5 * L, n_shells=64)
     _check(a2, c2, a1, c1)
+    # a smaller call after a larger one
+    a3, c3 = ctx.shell_profile(passing=P, center=src, r_max=0.5 * L, n_shells=3)
+    p3, q3 = _oracle(cfg, 0, P, dict(center=src, r_max=0.5 * L, n_shells=3))
+    _check(a3, c3, p3, q3)
     bad = [dict(n_shells=0), dict(n_shells=2049), dict(n_shells=2048, axis=(0, 0, 0)), dict(norm=0.0),
            dict(r_max=-1.0), dict(r_max=float("nan")), dict(inst=1), dict(inst=-1)]
     for b in bad:
