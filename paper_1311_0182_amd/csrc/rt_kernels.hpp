@@ -1962,15 +1962,59 @@ __global__ __launch_bounds__(256) void k_ledger_partial(LedgerArgs a) {
     }
 }
 
+// Escaped and removed photons of the virtual particles of emission cones,
+// summed per instance and bin and cleared for the next step.  One workgroup per
+// (instance, bin) runs over that instance's emitters: each lane adds a fixed
+// stride of the entries in order and the lanes are combined by a fixed tree, so
+// the sums are the same on every run.
+constexpr int kEmTallyBlock = 1024;
+
+struct EmitTallyArgs {
+    int nf;
+    long long per_em;              // emission cones per emitter and step (sub-steps x N_EC)
+    const int* em_by_inst;         // emitter indices grouped by instance
+    const long long* em_ioff;      // [n_inst+1] each instance's range in em_by_inst
+    double* exs;                   // [emitter][per_em][nf] escaped, cleared here
+    double* ers;                   // [emitter][per_em][nf] removed, cleared here
+    double* emt;                   // [n_inst][nf][2] escaped, removed
+};
+
+__global__ __launch_bounds__(kEmTallyBlock) void k_emit_tally(EmitTallyArgs a) {
+    __shared__ double sx[kEmTallyBlock], sr[kEmTallyBlock];
+    const int k = blockIdx.x / a.nf, nu = blockIdx.x % a.nf;
+    const long long e0 = a.em_ioff[k];
+    const long long total = (a.em_ioff[k + 1] - e0) * a.per_em;
+    double x = 0.0, r = 0.0;
+    for (long long i = threadIdx.x; i < total; i += kEmTallyBlock) {
+        const long long m = a.em_by_inst[e0 + i / a.per_em];
+        const long long ix = (m * a.per_em + i % a.per_em) * a.nf + nu;
+        x += a.exs[ix];
+        r += a.ers[ix];
+        a.exs[ix] = 0.0;
+        a.ers[ix] = 0.0;
+    }
+    sx[threadIdx.x] = x;
+    sr[threadIdx.x] = r;
+    __syncthreads();
+    for (int w = kEmTallyBlock / 2; w > 0; w >>= 1) {
+        if (static_cast<int>(threadIdx.x) < w) {
+            sx[threadIdx.x] += sx[threadIdx.x + w];
+            sr[threadIdx.x] += sr[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        a.emt[2 * blockIdx.x] = sx[0];
+        a.emt[2 * blockIdx.x + 1] = sr[0];
+    }
+}
+
 struct LedgerFinalArgs {
-    int n_inst, nf, f32, nec, nsub;
-    long long n_emit;
+    int n_inst, nf, f32;
     const long long* inst_chunk0;   // [n_inst+1] chunk ranges
     const double* partial;
     const double* E_src;            // [n_inst][nf] source photons per step
-    const int* em_inst;
-    double* exs;
-    double* ers;
+    const double* emt;              // [n_inst][nf][2] emission-cone escaped, removed (k_emit_tally)
     double* led;                    // [n_inst][nf][5] E, A, X, R, F (F current)
     double* scale;                  // [n_inst][nf]
     long long* cnt;
@@ -1983,17 +2027,8 @@ __global__ void k_ledger_final(LedgerFinalArgs a) {
     double v[5] = {0, 0, 0, 0, 0};
     for (long long c = a.inst_chunk0[k]; c < a.inst_chunk0[k + 1]; ++c)
         for (int q = 0; q < 5; ++q) v[q] += a.partial[(c * a.nf + nu) * 5 + q];
-    const long long per_em = static_cast<long long>(a.nsub) * a.nec;
-    for (long long m = 0; m < a.n_emit; ++m) {
-        if (a.em_inst[m] != k) continue;
-        for (long long u = 0; u < per_em; ++u) {
-            const long long ix = (m * per_em + u) * a.nf + nu;
-            v[2] += a.exs[ix];
-            v[3] += a.ers[ix];
-            a.exs[ix] = 0.0;
-            a.ers[ix] = 0.0;
-        }
-    }
+    v[2] += a.emt[2 * t];
+    v[3] += a.emt[2 * t + 1];
     double* L = a.led + (static_cast<long long>(k) * a.nf + nu) * 5;
     L[0] += a.E_src[k * a.nf + nu] + v[0];
     L[1] += v[1];

@@ -77,6 +77,9 @@ struct rt_ctx {
     double* exs = nullptr;
     double* ers = nullptr;
     std::vector<int> h_em_inst;
+    int* em_by_inst = nullptr;      // emitter indices grouped by instance
+    long long* em_ioff = nullptr;   // [n_inst+1] ranges in em_by_inst
+    double* emt = nullptr;          // [n_inst][nf][2] emission-cone escaped, removed per step
     double* E_src = nullptr;
     // intensity profiles: histogram and an optional copy of caller-given passing photons
     double* prof_sum = nullptr;
@@ -632,19 +635,25 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
     la.partial = c->partial;
     hipLaunchKernelGGL(k_ledger_partial, dim3(static_cast<unsigned>(c->n_chunks)), dim3(256), 0, c->stream, la);
     HIPCHK(c, hipGetLastError());
+    EmitTallyArgs et{};
+    et.nf = c->nf;
+    et.per_em = static_cast<long long>(c->nsub) * c->nec;
+    et.em_by_inst = c->em_by_inst;
+    et.em_ioff = c->em_ioff;
+    et.exs = c->exs;
+    et.ers = c->ers;
+    et.emt = c->emt;
+    hipLaunchKernelGGL(k_emit_tally, dim3(static_cast<unsigned>(c->n_inst * c->nf)), dim3(kEmTallyBlock), 0, c->stream,
+                       et);
+    HIPCHK(c, hipGetLastError());
     LedgerFinalArgs lf{};
     lf.n_inst = c->n_inst;
     lf.nf = c->nf;
     lf.f32 = c->f32 ? 1 : 0;
-    lf.nec = c->nec;
-    lf.nsub = c->nsub;
-    lf.n_emit = c->n_emit;
     lf.inst_chunk0 = c->inst_chunk0;
     lf.partial = c->partial;
     lf.E_src = c->E_src;
-    lf.em_inst = c->em_inst;
-    lf.exs = c->exs;
-    lf.ers = c->ers;
+    lf.emt = c->emt;
     lf.led = c->led;
     lf.scale = c->scale;
     lf.cnt = c->cnt;
@@ -974,6 +983,12 @@ rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, cons
     ITRY(alloc_n(c, &c->ecd, 3));
     ITRY(alloc_n(c, &c->exs, 1));
     ITRY(alloc_n(c, &c->ers, 1));
+    ITRY(alloc_n(c, &c->em_by_inst, 1));
+    {
+        const std::vector<long long> zero(n_inst + 1, 0);
+        ITRY(upload(c, &c->em_ioff, zero.data(), n_inst + 1ll));
+    }
+    ITRY(alloc_n(c, &c->emt, 2ll * n_inst * c->nf));
     HIPCHK(c, hipStreamSynchronize(c->stream));
 #undef ITRY
     *out = c;
@@ -1020,6 +1035,8 @@ rt_status rt_add_sources(rt_ctx* c, int32_t n_src, const int32_t* inst, const in
     dfree(c, c->ecd);
     dfree(c, c->exs);
     dfree(c, c->ers);
+    dfree(c, c->em_by_inst);
+    dfree(c, c->em_ioff);
     std::vector<int> ek(total), ei(total);
     std::vector<double> ep(3 * total), epk(total * c->nf);
     std::vector<double> esrc(static_cast<size_t>(c->n_inst) * c->nf, 0.0);
@@ -1064,6 +1081,15 @@ rt_status rt_add_sources(rt_ctx* c, int32_t n_src, const int32_t* inst, const in
     TRY(upload(c, &c->em_pos, ep.data(), 3 * total));
     TRY(upload(c, &c->em_pk, epk.data(), total * c->nf));
     TRY(upload(c, &c->E_src, esrc.data(), static_cast<long long>(c->n_inst) * c->nf));
+    // emitters grouped by instance, in emitter order within each (counting sort)
+    std::vector<long long> ioff(c->n_inst + 1, 0);
+    for (long long q = 0; q < total; ++q) ioff[ei[q] + 1] += 1;
+    for (int k = 0; k < c->n_inst; ++k) ioff[k + 1] += ioff[k];
+    std::vector<long long> cur(ioff.begin(), ioff.end() - 1);
+    std::vector<int> by_inst(total);
+    for (long long q = 0; q < total; ++q) by_inst[cur[ei[q]]++] = static_cast<int>(q);
+    TRY(upload(c, &c->em_by_inst, by_inst.data(), total));
+    TRY(upload(c, &c->em_ioff, ioff.data(), c->n_inst + 1ll));
     TRY(alloc_n(c, &c->em_ngb, std::max<long long>(1, total) * c->K));
     TRY(alloc_n(c, &c->em_h, std::max<long long>(1, total)));
     const long long necd = std::max<long long>(1, total * c->nsub * c->nec);

@@ -307,6 +307,15 @@ def shadow_boundary(n_side=32, box_kpc=13.2, n_h=1e-3, clump_nh=1.0, clump_r=0.1
     return cfg
 
 
+def boundary_schedule(cfg, t, flux=1e6, n_h=1e-3):
+    """Boundary sources of shadow_boundary the I-front has passed at time t (s),
+    taking the front where it would be if no gas recombined: every photon of the
+    flux ionizes one atom, so it advances at F / n_H (the Stromgren distance of
+    the appendix, 1251 kpc, is far beyond the box).  A schedule for inputs only."""
+    lo = float(cfg["box"][0][0])
+    return cfg["boundary"]["pos"][:, 0] - lo <= flux * t / n_h
+
+
 def boundary_sources(cfg, on):
     """The front's sources plus the boundary sources of shadow_boundary whose
     entry in the boolean mask on[4 n_bd^2] is set."""

@@ -171,3 +171,50 @@ def test_boundary_rr_sources_against_oracle(precision):
         assert np.all(np.abs(pg - po) <= 1e-6 * scale)
     ctx.close()
     s.close()
+
+
+def test_boundary_rr_sources_full_size_fp32_against_fp64_gpu():
+    # section 4's size: 32^3 particles, 50^2 boundary sources per face, 100^2
+    # front emitters; too large for the oracle, so FP32 transport is checked
+    # against the FP64 GPU path on the same inputs and the same switch schedule
+    import time
+    from paper_1311_0182_amd import traphic_rt as RT
+    cfg = I.shadow_boundary()
+    dt = cfg["params"]["dt"]
+    s1, s2 = 6, 4
+    on = I.boundary_schedule(cfg, s1 * dt)
+    say("shadow with boundary sources, 32^3,", int(on.sum()), "of", on.size, "boundary sources on after", s1, "steps")
+    assert 0 < on.sum() < on.size
+    src = I.boundary_sources(cfg, on)
+    out = {}
+    for prec in ("fp64", "fp32"):
+        ctx = RT.Context(cfg, precision=prec)
+        ctx.step(s1)
+        ctx.add_sources(src)
+        ctx.step(1)
+        import torch
+        ctx.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.step(s2 - 1)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / (s2 - 1) * 1e3
+        tm = ctx.timing()
+        out[prec] = ctx.state()
+        say(prec, f"{ms:.2f} ms/step (every launch timed) with", len(src["inst"]), "sources;",
+            {k: round(v / (s2 - 1), 2) for k, v in tm.items() if k.endswith("_ms")}, "ms per step;",
+            tm["hop_launches"] / (s2 - 1), "forward steps per step")
+        ctx.close()
+    a, b = out["fp32"], out["fp64"]
+    r32, r64 = np.max(residual(a["ledger"])), np.max(residual(b["ledger"]))
+    dx = np.abs(a["xHI"] - b["xHI"])
+    say("residuals", r32, r64, "max |dx_HI|", dx.max(), "99.9% quantile", np.quantile(dx, 0.999))
+    assert r64 < 1e-12 and r32 < 1e-6
+    # the sources emit the same photons; the gas's recombination photons follow its state
+    assert rel(a["ledger"][0, [0, 2], 0], b["ledger"][0, [0, 2], 0]) < 1e-12
+    assert rel(a["ledger"][0, 1, 0], b["ledger"][0, 1, 0]) < 1e-5
+    A32, A64 = a["A"].sum(0), b["A"].sum(0)
+    assert np.all(np.abs(A32 - A64) <= 1e-5 * np.maximum(A64, 1e-300))  # absorbed per bin
+    assert A64[2] > 0                                                    # the outside-box bin arrives
+    assert np.quantile(dx, 0.999) <= 1e-3
+    assert abs(np.mean(a["xHI"]) - np.mean(b["xHI"])) < 1e-5
