@@ -104,7 +104,8 @@ rt_status rt_init(rt_ctx **out, const rt_params *p, const double *sigma_nu, cons
  *   pos[n_src*3]               point-source position (ignored for planes; must lie in its box)
  *   rate[n_src*n_freq]         photons/s per bin (point) or photons/s/cm^2 per bin (plane)
  *   n_side[n_src]              plane: emitters per side of the face grid; may be NULL if no planes
- * Errors: RT_EINVAL, RT_ENOMEM, RT_EDEVICE. */
+ * May be called again between steps (sources switched on during a run).
+ * Errors: RT_EINVAL and RT_ENOMEM (the previous sources stay), RT_EDEVICE. */
 rt_status rt_add_sources(rt_ctx *ctx, int32_t n_src, const int32_t *inst, const int32_t *kind,
                          const double *pos, const double *rate, const int32_t *n_side);
 

@@ -1020,23 +1020,6 @@ rt_status rt_add_sources(rt_ctx* c, int32_t n_src, const int32_t* inst, const in
                 return fail(c, RT_EINVAL, "bad source rate");
     }
     if (total >= (1ll << 24)) return fail(c, RT_EINVAL, "too many emitters");
-    // The captured forward steps refer to the emitters' buffers (virtual
-    // particles of empty emission cones): drop them before the buffers change.
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (auto& kv : c->hop_graphs) (void)hipGraphExecDestroy(kv.second);
-    c->hop_graphs.clear();
-    dfree(c, c->em_kind);
-    dfree(c, c->em_inst);
-    dfree(c, c->em_pos);
-    dfree(c, c->em_pk);
-    dfree(c, c->E_src);
-    dfree(c, c->em_ngb);
-    dfree(c, c->em_h);
-    dfree(c, c->ecd);
-    dfree(c, c->exs);
-    dfree(c, c->ers);
-    dfree(c, c->em_by_inst);
-    dfree(c, c->em_ioff);
     std::vector<int> ek(total), ei(total);
     std::vector<double> ep(3 * total), epk(total * c->nf);
     std::vector<double> esrc(static_cast<size_t>(c->n_inst) * c->nf, 0.0);
@@ -1074,13 +1057,6 @@ rt_status rt_add_sources(rt_ctx* c, int32_t n_src, const int32_t* inst, const in
                 }
         }
     }
-    c->n_emit = total;
-    c->h_em_inst = ei;
-    TRY(upload(c, &c->em_kind, ek.data(), total));
-    TRY(upload(c, &c->em_inst, ei.data(), total));
-    TRY(upload(c, &c->em_pos, ep.data(), 3 * total));
-    TRY(upload(c, &c->em_pk, epk.data(), total * c->nf));
-    TRY(upload(c, &c->E_src, esrc.data(), static_cast<long long>(c->n_inst) * c->nf));
     // emitters grouped by instance, in emitter order within each (counting sort)
     std::vector<long long> ioff(c->n_inst + 1, 0);
     for (long long q = 0; q < total; ++q) ioff[ei[q] + 1] += 1;
@@ -1088,14 +1064,81 @@ rt_status rt_add_sources(rt_ctx* c, int32_t n_src, const int32_t* inst, const in
     std::vector<long long> cur(ioff.begin(), ioff.end() - 1);
     std::vector<int> by_inst(total);
     for (long long q = 0; q < total; ++q) by_inst[cur[ei[q]]++] = static_cast<int>(q);
-    TRY(upload(c, &c->em_by_inst, by_inst.data(), total));
-    TRY(upload(c, &c->em_ioff, ioff.data(), c->n_inst + 1ll));
-    TRY(alloc_n(c, &c->em_ngb, std::max<long long>(1, total) * c->K));
-    TRY(alloc_n(c, &c->em_h, std::max<long long>(1, total)));
+    // The new buffers are built first: if one cannot be allocated, they are
+    // freed again and the context keeps its sources.
     const long long necd = std::max<long long>(1, total * c->nsub * c->nec);
-    TRY(alloc_n(c, &c->ecd, 3 * necd));
-    TRY(alloc_n(c, &c->exs, necd * c->nf));
-    TRY(alloc_n(c, &c->ers, necd * c->nf));
+    int *n_kind = nullptr, *n_inst = nullptr, *n_ngb = nullptr, *n_by = nullptr;
+    double *n_pos = nullptr, *n_pk = nullptr, *n_E = nullptr, *n_h = nullptr, *n_ecd = nullptr, *n_exs = nullptr,
+           *n_ers = nullptr;
+    long long* n_ioff = nullptr;
+    auto undo = [&]() {
+        (void)hipStreamSynchronize(c->stream);
+        dfree(c, n_kind);
+        dfree(c, n_inst);
+        dfree(c, n_ngb);
+        dfree(c, n_by);
+        dfree(c, n_pos);
+        dfree(c, n_pk);
+        dfree(c, n_E);
+        dfree(c, n_h);
+        dfree(c, n_ecd);
+        dfree(c, n_exs);
+        dfree(c, n_ers);
+        dfree(c, n_ioff);
+    };
+#define ATRY(x)                       \
+    do {                              \
+        rt_status s_ = (x);           \
+        if (s_ != RT_OK) {            \
+            undo();                   \
+            return s_;                \
+        }                             \
+    } while (0)
+    ATRY(upload(c, &n_kind, ek.data(), total));
+    ATRY(upload(c, &n_inst, ei.data(), total));
+    ATRY(upload(c, &n_pos, ep.data(), 3 * total));
+    ATRY(upload(c, &n_pk, epk.data(), total * c->nf));
+    ATRY(upload(c, &n_E, esrc.data(), static_cast<long long>(c->n_inst) * c->nf));
+    ATRY(upload(c, &n_by, by_inst.data(), total));
+    ATRY(upload(c, &n_ioff, ioff.data(), c->n_inst + 1ll));
+    ATRY(alloc_n(c, &n_ngb, std::max<long long>(1, total) * c->K));
+    ATRY(alloc_n(c, &n_h, std::max<long long>(1, total)));
+    ATRY(alloc_n(c, &n_ecd, 3 * necd));
+    ATRY(alloc_n(c, &n_exs, necd * c->nf));
+    ATRY(alloc_n(c, &n_ers, necd * c->nf));
+#undef ATRY
+    // The captured forward steps refer to the emitters' buffers (virtual
+    // particles of empty emission cones): drop them, and free the old buffers
+    // once no queued work uses them.
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (auto& kv : c->hop_graphs) (void)hipGraphExecDestroy(kv.second);
+    c->hop_graphs.clear();
+    dfree(c, c->em_kind);
+    dfree(c, c->em_inst);
+    dfree(c, c->em_pos);
+    dfree(c, c->em_pk);
+    dfree(c, c->E_src);
+    dfree(c, c->em_ngb);
+    dfree(c, c->em_h);
+    dfree(c, c->ecd);
+    dfree(c, c->exs);
+    dfree(c, c->ers);
+    dfree(c, c->em_by_inst);
+    dfree(c, c->em_ioff);
+    c->em_kind = n_kind;
+    c->em_inst = n_inst;
+    c->em_pos = n_pos;
+    c->em_pk = n_pk;
+    c->E_src = n_E;
+    c->em_ngb = n_ngb;
+    c->em_h = n_h;
+    c->ecd = n_ecd;
+    c->exs = n_exs;
+    c->ers = n_ers;
+    c->em_by_inst = n_by;
+    c->em_ioff = n_ioff;
+    c->n_emit = total;
+    c->h_em_inst = ei;
     TRY(fill_f64(c, c->exs, necd * c->nf, 0.0));
     TRY(fill_f64(c, c->ers, necd * c->nf, 0.0));
     TRY(fill_f64(c, c->ecd, 3 * necd, 0.0));
@@ -1161,10 +1204,8 @@ rt_status rt_shell_profile(rt_ctx* c, int32_t inst, const double* passing, const
                   axis[0] * axis[0] + axis[1] * axis[1] + axis[2] * axis[2] > 0.0))
         return fail(c, RT_EINVAL, "shell profile: axis must be finite and nonzero");
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (!c->prof_sum) {
-        TRY(alloc_n(c, &c->prof_sum, kProfMaxCells));
-        TRY(alloc_n(c, &c->prof_cnt, kProfMaxShells));
-    }
+    if (!c->prof_sum) TRY(alloc_n(c, &c->prof_sum, kProfMaxCells));
+    if (!c->prof_cnt) TRY(alloc_n(c, &c->prof_cnt, kProfMaxShells));
     const double* Pd = c->P;
     if (passing) {
         if (!c->prof_in) TRY(alloc_n(c, &c->prof_in, c->N * c->nf));
