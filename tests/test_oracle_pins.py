@@ -211,6 +211,20 @@ def test_vip_sampler_uniform_in_cone_ball(d, n_tc):
     # uniform in the ball: E|p|^2 = 3/5
     r2 = (ps ** 2).sum(1)
     assert abs(r2.mean() - 0.6) < 4 * r2.std() / math.sqrt(len(ps))
+    # and the whole distributions (Kolmogorov-Smirnov, 0.1% level): uniform in volume,
+    # |p|^3 ~ U(0, 1); uniform in solid angle within the cone, cos(angle to d) ~ U(cos theta, 1);
+    # no preferred azimuth around d (the proposal box of the cone's frame has corners)
+    from scipy.stats import kstest
+    n = len(ps)
+    crit = 1.95 / math.sqrt(n)
+    r = np.sqrt(r2)
+    assert kstest(r ** 3, "uniform").statistic < crit
+    assert kstest(along / r, "uniform", args=(c, 1 - c)).statistic < crit
+    e1 = np.cross(d, [1.0, 0.0, 0.0] if abs(d[0]) < 0.9 else [0.0, 1.0, 0.0])
+    e1 /= np.linalg.norm(e1)
+    e2 = np.cross(d, e1)
+    phi = np.arctan2(ps @ e2, ps @ e1)
+    assert kstest(phi, "uniform", args=(-math.pi, 2 * math.pi)).statistic < crit
 
 
 def test_merge_two_packets():
