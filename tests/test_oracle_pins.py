@@ -602,3 +602,27 @@ def test_shell_profile_rejects_bad_arguments():
         a.update(kw)
         with pytest.raises(ValueError):
             O.shell_profile(pos, P, a["dt"], np.zeros(3), a["r_max"], a["n_shells"], axis=a["axis"], norm=a["norm"])
+
+
+def test_shell_profile_flat_in_optically_thin_gas():
+    # Section 3 measures 4 pi r^2 I(r) by summing the photons passing particles
+    # in thin spherical shells.  Without absorption every photon the source emits
+    # crosses every sphere inside the box, so the profile is flat in r: each
+    # packet arrives at particles of a shell about (shell width / radial advance
+    # per forward step) times, the same at every radius in uniform gas.
+    cfg = I.stromgren(20, rr=False, n_ngb=32, n_steps=1)
+    cfg["sigma"] = np.array([1e-40])
+    cfg["params"]["freeze_chem"] = 1
+    s = O.OracleSim(cfg)
+    s.step(1)
+    st = s.state()
+    s.close()
+    L = float(cfg["box"][0][3])
+    prof, cnt = O.shell_profile(cfg["pos"], st["P"], cfg["params"]["dt"], cfg["sources"]["pos"][0], 0.5 * L, 8,
+                                norm=cfg["sources"]["rate"][0][0])
+    outer = prof[2:, 0]          # beyond two lattice spacings of the source
+    assert np.all(cnt[2:] > 100)
+    assert np.max(np.abs(outer / outer.mean() - 1)) < 0.12
+    # and nothing is absorbed: every emitted photon left the box or is in flight
+    E, A, X, R, F = st["ledger"][0, 0]
+    assert A < 1e-20 * E and abs(E - X - F - R) <= 1e-12 * E
