@@ -140,7 +140,7 @@ rt_status rt_get_state(rt_ctx *ctx, double *x_HI, double *T, double *absorbed, d
  *                     else a host array [N*n_freq] (photons) binned instead
  *   center[3]         centre of the spheres, or a point on the cylinder axis (cm)
  *   axis[3]           NULL: spherical shells; else the cylinder axis direction
- *                     (any nonzero length)
+ *                     (any length whose square is finite and nonzero)
  *   half_height       cylinders: > 0 keeps only particles with
  *                     |(x - center) . axis/|axis|| <= half_height; <= 0: no cut
  *   r_max, n_shells   shells of width r_max / n_shells; particle j lies in shell

@@ -1340,8 +1340,8 @@ int or_shell_profile(int64_t n, int32_t nf, const double *pos, const double *P, 
     double u[3] = {0.0, 0.0, 0.0};
     if (axis) {
         double a2 = axis[0] * axis[0] + axis[1] * axis[1] + axis[2] * axis[2];
-        if (!(a2 > 0.0)) {
-            set_err("shell profile: zero axis");
+        if (!(a2 > 0.0) || !isfinite(a2)) {
+            set_err("shell profile: zero or overflowing axis");
             return -1;
         }
         double a = sqrt(a2);

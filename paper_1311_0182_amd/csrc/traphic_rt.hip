@@ -1200,9 +1200,11 @@ rt_status rt_shell_profile(rt_ctx* c, int32_t inst, const double* passing, const
     if (!(r_max > 0.0) || !(norm > 0.0) || !std::isfinite(r_max) || !std::isfinite(norm) || !std::isfinite(half_height) ||
         !std::isfinite(center[0]) || !std::isfinite(center[1]) || !std::isfinite(center[2]))
         return fail(c, RT_EINVAL, "shell profile: r_max, norm, half_height and center must be finite, r_max and norm > 0");
-    if (axis && !(std::isfinite(axis[0]) && std::isfinite(axis[1]) && std::isfinite(axis[2]) &&
-                  axis[0] * axis[0] + axis[1] * axis[1] + axis[2] * axis[2] > 0.0))
-        return fail(c, RT_EINVAL, "shell profile: axis must be finite and nonzero");
+    if (axis) {
+        const double a2 = axis[0] * axis[0] + axis[1] * axis[1] + axis[2] * axis[2];
+        if (!(a2 > 0.0) || !std::isfinite(a2))
+            return fail(c, RT_EINVAL, "shell profile: the axis's squared length must be finite and nonzero");
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (!c->prof_sum) TRY(alloc_n(c, &c->prof_sum, kProfMaxCells));
     if (!c->prof_cnt) TRY(alloc_n(c, &c->prof_cnt, kProfMaxShells));

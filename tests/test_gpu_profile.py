@@ -148,7 +148,8 @@ def test_shell_profile_edge_cases():
     a3, c3 = ctx.shell_profile(passing=P, center=src, r_max=0.5 * L, n_shells=3)
     p3, q3 = _oracle(cfg, 0, P, dict(center=src, r_max=0.5 * L, n_shells=3))
     _check(a3, c3, p3, q3)
-    bad = [dict(n_shells=0), dict(n_shells=2049), dict(n_shells=2048, axis=(0, 0, 0)), dict(norm=0.0),
+    bad = [dict(n_shells=0), dict(n_shells=2049), dict(n_shells=2048, axis=(0, 0, 0)), dict(axis=(1e200, 0, 0)),
+           dict(norm=0.0),
            dict(r_max=-1.0), dict(r_max=float("nan")), dict(inst=1), dict(inst=-1)]
     for b in bad:
         g = dict(center=src, r_max=0.5 * L, n_shells=8)

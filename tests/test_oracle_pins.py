@@ -597,7 +597,8 @@ def test_shell_profile_against_independent_membership():
 
 def test_shell_profile_rejects_bad_arguments():
     pos, P = np.zeros((2, 3)), np.ones((2, 1))
-    for kw in (dict(dt=0.0), dict(r_max=-1.0), dict(n_shells=0), dict(norm=0.0), dict(axis=(0, 0, 0))):
+    for kw in (dict(dt=0.0), dict(r_max=-1.0), dict(n_shells=0), dict(norm=0.0), dict(axis=(0, 0, 0)),
+               dict(axis=(1e200, 0, 0))):
         a = dict(dt=1.0, r_max=1.0, n_shells=2, norm=1.0, axis=None)
         a.update(kw)
         with pytest.raises(ValueError):
