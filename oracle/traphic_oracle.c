@@ -29,7 +29,7 @@
 #define VIP_MAX_ATTEMPTS 65536
 
 /* Philox counter tags: what a random draw is for. */
-enum { TAG_RC = 1, TAG_EC = 2, TAG_VIP_T = 3, TAG_VIP_E = 4 };
+enum { TAG_RC = 1, TAG_EC = 2, TAG_VIP_T = 3, TAG_VIP_E = 4, TAG_RR_EC = 5, TAG_VIP_RR = 6 };
 
 static char g_err[256];
 const char *or_error(void) { return g_err; }
@@ -268,7 +268,8 @@ void or_chem_one(const or_params *p, const double *eps, const double *A, double 
             }
         }
         double yn = (y + dts * rec) / (1.0 + dts * (ion + rec));
-        if (p->recomb_mode == OR_RR_TRANSPORT) rr += (rt[0] - rt[1]) * ne * (1.0 - yn) * NH * dts;
+        if (p->recomb_mode == OR_RR_TRANSPORT || p->recomb_mode == OR_RR_ORIGINAL)
+            rr += (rt[0] - rt[1]) * ne * (1.0 - yn) * NH * dts;
         if (!p->isothermal) {
             Y = Y + dts * dY;
             Tc = Y / (2.0 - yn);
@@ -474,7 +475,7 @@ or_sim *or_create(const or_params *p, const double *sigma, const double *eps, in
         set_err("invalid parameters");
         return NULL;
     }
-    if (p->recomb_mode == OR_RR_TRANSPORT && p->rr_bin < 0) {
+    if ((p->recomb_mode == OR_RR_TRANSPORT || p->recomb_mode == OR_RR_ORIGINAL) && p->rr_bin < 0) {
         set_err("RR transport needs an RR frequency bin");
         return NULL;
     }
@@ -1078,6 +1079,72 @@ static void emit_sources(or_sim *S, double *Xled, double *Rled)
     }
 }
 
+/* The predecessor scheme of emitting recombination radiation, kept as a
+ * reference for the comparison of section 2.2 (the new scheme reuses the
+ * reception cones instead).  Every particle is a source of the RR photons of
+ * its last chemistry step: like a point source it emits them in N_EC isotropic
+ * emission cones on each of the n_em emission sub-steps, with a fresh random
+ * rotation per particle and sub-step, into its own neighbours; packets start
+ * with clock 0; empty cones become virtual particles.  Reading: its cones are
+ * the Voronoi cells of the rotated directions, as for point sources. */
+static void emit_rr_original(or_sim *S, uint32_t step, double *Xled, double *Rled)
+{
+    int nf = S->nf, K = S->p.n_ngb, nu = S->p.rr_bin, nec = S->p.n_ec, nsub = S->p.n_em;
+    int kc[64], ncount[64];
+    double ecd[3 * 64];
+    for (int64_t i = 0; i < S->N; ++i) {
+        double nrr = S->nrr[i];
+        S->nrr[i] = 0.0;
+        if (!(nrr > 0.0)) continue;
+        int inst = S->inst_of[i];
+        double pk = nrr / (double)(nsub * nec);
+        const double *xi = S->pos + 3 * i;
+        const int32_t *nb = S->ngb + i * K;
+        S->led[((int64_t)inst * nf + nu) * 4 + 0] += nrr;
+        for (int sub = 0; sub < nsub; ++sub) {
+            double R[9];
+            or_rotation(S->p.seed, TAG_RR_EC, step, (uint32_t)i, (uint32_t)sub, R);
+            for (int k = 0; k < nec; ++k) {
+                rotate(R, S->u_ec + 3 * k, ecd + 3 * k);
+                ncount[k] = 0;
+            }
+            for (int t = 0; t < K; ++t) {
+                const double *xj = S->pos + 3 * (int64_t)nb[t];
+                double v[3] = {xj[0] - xi[0], xj[1] - xi[1], xj[2] - xi[2]};
+                kc[t] = nearest_dir(ecd, nec, v);
+                ncount[kc[t]]++;
+            }
+            S->counters[3] += nec;
+            for (int t = 0; t < K; ++t) {
+                int k = kc[t];
+                int64_t j = nb[t];
+                const double *xj = S->pos + 3 * j;
+                double v[3] = {xj[0] - xi[0], xj[1] - xi[1], xj[2] - xi[2]};
+                double *dk = ecd + 3 * k;
+                double l = dot3(v, dk) / sqrt(dot3(dk, dk));
+                leg_to_particle(S, j, nu, dk, pk / (double)ncount[k], l, 0.0);
+            }
+            for (int k = 0; k < nec; ++k) {
+                if (ncount[k] > 0) continue;
+                vip_req q;
+                memcpy(q.x, xi, sizeof q.x);
+                q.h = S->h[i];
+                memcpy(q.d, ecd + 3 * k, sizeof q.d);
+                q.N = pk;
+                q.c = 0.0;
+                q.nu = nu;
+                q.inst = inst;
+                q.ecdir = ecd;
+                q.ek = k;
+                q.tag = TAG_VIP_RR;
+                q.ida = (uint32_t)i;
+                q.idb_base = ((uint32_t)sub << 20) | ((uint32_t)k << 4);
+                vip_chain(S, q, &Xled[inst * nf + nu], &Rled[inst * nf + nu]);
+            }
+        }
+    }
+}
+
 /* One RT step followed by the chemistry step (section 2.1) and the emission
  * of recombination radiation into the reception cones (section 2.2).
  * Reading of the order inside a step: (1) clocks carried over from the last
@@ -1121,6 +1188,7 @@ static int one_step(or_sim *S)
         }
     }
     emit_sources(S, Xs, Rs);
+    if (S->p.recomb_mode == OR_RR_ORIGINAL) emit_rr_original(S, step, Xs, Rs);
     finalize_bins(S);
 
     /* (4) Forward steps (section 2.1): all active packets move at once to the
@@ -1199,9 +1267,9 @@ static int one_step(or_sim *S)
         for (int64_t j = 0; j < N; ++j) {
             double nrr = 0.0;
             or_chem_one(&S->p, S->eps, S->A + j * nf, S->nH[j], S->NH[j], &S->xHI[j], &S->T[j], &nrr, NULL);
-            if (S->p.recomb_mode == OR_RR_TRANSPORT) S->nrr[j] = nrr;
+            if (S->p.recomb_mode == OR_RR_TRANSPORT || S->p.recomb_mode == OR_RR_ORIGINAL) S->nrr[j] = nrr;
         }
-    } else if (S->p.recomb_mode == OR_RR_TRANSPORT) {
+    } else if (S->p.recomb_mode == OR_RR_TRANSPORT || S->p.recomb_mode == OR_RR_ORIGINAL) {
         /* Frozen ionization state (transport-only runs): the ground-state
          * recombinations of the fixed state over dt still feed the RR bin. */
         double rt[8];

@@ -38,7 +38,10 @@
 extern "C" {
 #endif
 
-enum { OR_CASE_B_OTS = 0, OR_CASE_A_NO_RR = 1, OR_RR_TRANSPORT = 2 };
+/* OR_RR_ORIGINAL: RR emitted by every particle in its own N_EC emission cones
+ * (the predecessor scheme of section 2.2), a reference for the comparison of
+ * the two schemes; the HIP library implements only the reception-cone scheme. */
+enum { OR_CASE_B_OTS = 0, OR_CASE_A_NO_RR = 1, OR_RR_TRANSPORT = 2, OR_RR_ORIGINAL = 3 };
 enum { OR_SRC_POINT = 0, OR_SRC_PLANE_XLO = 1 };
 
 typedef struct {

@@ -627,3 +627,33 @@ def test_shell_profile_flat_in_optically_thin_gas():
     # and nothing is absorbed: every emitted photon left the box or is in flight
     E, A, X, R, F = st["ledger"][0, 0]
     assert A < 1e-20 * E and abs(E - X - F - R) <= 1e-12 * E
+
+
+def _shell_xhii(cfg, st, n_sh=6):
+    src = cfg["sources"]["pos"][0]
+    r = np.linalg.norm(cfg["pos"] - src, axis=1)
+    k = np.minimum((r / (0.5 * float(cfg["box"][0][3])) * n_sh).astype(int), n_sh)
+    x = 1.0 - st["xHI"]
+    return np.array([x[k == i].mean() for i in range(n_sh)])
+
+
+def test_rr_in_reception_cones_matches_the_original_scheme():
+    # Section 2.2: emitting the recombination photons into the reception cones
+    # gives nearly the same result as the predecessor scheme, in which every
+    # particle emits them through its own N_EC emission cones on the emission
+    # sub-steps.  Same Stromgren problem with RR, both schemes, 20 steps.
+    out = {}
+    for mode in (I.RR_TRANSPORT, 3, I.CASE_A_NO_RR):
+        cfg = I.stromgren(12, rr=True, n_ngb=32, dt_myr=0.5)
+        cfg["params"]["recomb_mode"] = mode
+        s = O.OracleSim(cfg)
+        s.step(20)
+        out[mode] = (_shell_xhii(cfg, s.state()), s.state()["ledger"][0, 1, 0])
+        s.close()
+    new, orig, lost = out[I.RR_TRANSPORT], out[3], out[I.CASE_A_NO_RR]
+    assert np.max(np.abs(new[0] - orig[0])) < 1e-3          # ionized fraction in radial shells
+    assert abs(new[1] / orig[1] - 1) < 1e-3                  # RR photons emitted
+    # the test can tell: without the RR photons (case A, nothing transported)
+    # the shells move by several times the tolerance and nothing is emitted
+    assert np.max(np.abs(lost[0] - orig[0])) > 5e-3
+    assert lost[1] == 0.0
