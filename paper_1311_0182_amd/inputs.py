@@ -303,17 +303,18 @@ def shadow_boundary(n_side=32, box_kpc=13.2, n_h=1e-3, clump_nh=1.0, clump_r=0.1
                 bpos.append(p)
     brate = np.zeros((len(bpos), n_freq))
     brate[:, 2] = bi["intensity"] * L * L / (n_bd * n_bd)
-    cfg["boundary"] = dict(pos=np.array(bpos), rate=brate, **bi)
+    cfg["boundary"] = dict(pos=np.array(bpos), rate=brate, flux=flux, n_h=n_h, **bi)
     return cfg
 
 
-def boundary_schedule(cfg, t, flux=1e6, n_h=1e-3):
+def boundary_schedule(cfg, t):
     """Boundary sources of shadow_boundary the I-front has passed at time t (s),
     taking the front where it would be if no gas recombined: every photon of the
     flux ionizes one atom, so it advances at F / n_H (the Stromgren distance of
     the appendix, 1251 kpc, is far beyond the box).  A schedule for inputs only."""
+    b = cfg["boundary"]
     lo = float(cfg["box"][0][0])
-    return cfg["boundary"]["pos"][:, 0] - lo <= flux * t / n_h
+    return b["pos"][:, 0] - lo <= b["flux"] * t / b["n_h"]
 
 
 def boundary_sources(cfg, on):

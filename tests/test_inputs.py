@@ -104,3 +104,9 @@ def test_shadow_boundary_layout():
     s = I.boundary_sources(cfg, on)
     assert len(s["inst"]) == 4 and s["kind"][0] == I.SRC_PLANE_XLO and np.all(s["kind"][1:] == I.SRC_POINT)
     assert np.array_equal(s["pos"][1:], b["pos"][on])
+    # the switch schedule follows the set-up's own front: twice the flux, twice as far
+    t = 3 * cfg["params"]["dt"]
+    x1 = b["pos"][I.boundary_schedule(cfg, t), 0].max()
+    fast = I.shadow_boundary(n_side=8, n_pp=10, n_bd=5, flux=2e6)
+    x2 = fast["boundary"]["pos"][I.boundary_schedule(fast, t), 0].max()
+    assert x2 > x1 and abs(1e6 * t / 1e-3 - x1) < L / 5 and abs(2e6 * t / 1e-3 - x2) < L / 5
