@@ -153,6 +153,37 @@ __host__ __device__ inline int nearest_direction(const R* w, int n, R dx, R dy, 
     return best;
 }
 
+// Half-width of the band around a threshold inside which an FP32 decision of
+// the transport (cone membership, reception cone) is handed to FP64.  The
+// FP32 dot products of unit vectors that decide them are within 1e-6 of the
+// exact ones (each operand rounded once: 6e-8; three roundings of the fused
+// products: 1.8e-7; lengths within a few ulp of 1: 3e-7), so outside the band
+// the FP32 decision is the exact one.
+constexpr double kConeGuard = 4e-6;
+
+// nearest_direction for the FP32 transport: the FP32 argmax over the rounded
+// directions w32, unless the runner-up lies within kConeGuard of the best; then
+// the FP64 argmax over w64 (the FP64 transport's own directions, same rule).
+__device__ inline int nearest_direction_guarded(const float* w32, const double* w64, int n, float dx, float dy,
+                                                float dz) {
+    int best = 0;
+    float bv = dx * w32[0] + dy * w32[1] + dz * w32[2];
+    float sv = -3.0f;
+    for (int k = 1; k < n; ++k) {
+        const float v = dx * w32[3 * k] + dy * w32[3 * k + 1] + dz * w32[3 * k + 2];
+        if (v > bv) {
+            sv = bv;
+            bv = v;
+            best = k;
+        } else if (v > sv) {
+            sv = v;
+        }
+    }
+    if (bv - sv < static_cast<float>(kConeGuard))
+        best = nearest_direction<double>(w64, n, static_cast<double>(dx), static_cast<double>(dy), static_cast<double>(dz));
+    return best;
+}
+
 // Absorbed N_in (1 - e^-tau) and transmitted N_in e^-tau parts of a packet leg:
 // the smaller part is evaluated directly, the larger is the remainder, so both
 // keep full relative precision at any optical depth and they sum to N_in.

@@ -839,7 +839,8 @@ struct HopArgs {
     const double* sigma;
     const float* sigmaf;
     R c2;
-    R cosc;                  // cosine of the cone half-angle (FP32 unit-vector test)
+    double c2d;              // cos^2 of the cone half-angle, FP64 (the exact test)
+    float cos_lo, cos_hi;    // FP32: cos(theta) - kConeGuard, cos(theta) + kConeGuard
     R dtc;                   // clock limit in clock units
     const float* clf;        // FP32: L_inst / (c dt) per instance
     const double* U;         // photons per bin unit per instance (1 in FP64)
@@ -1664,27 +1665,52 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
     if (act) {
         if constexpr (f32) {
             // bit k: neighbour k is a cone member; the bits enter from the
-            // highest neighbour down (m = 2m + bit), in two 32-bit halves
-            unsigned int mh = 0, ml = 0;
+            // highest neighbour down (m = 2m + bit), in two 32-bit halves.
+            // The FP32 cosine (unit vectors rounded once, fused products)
+            // is within kConeGuard / 4 of the exact one, so it decides every
+            // test outside the band cos(theta) -+ kConeGuard; the few inside
+            // it are decided by the FP64 test on the FP64 positions, the
+            // test of the FP64 transport, so both precisions take the same
+            // decision for the same direction.
+            unsigned int mh = 0, ml = 0, nh = 0, nl = 0;
             int k = K - 1;
             for (; k >= 32; --k) {
                 const V4 w = fj[k];
-                mh = mh + mh + (__builtin_fmaf(w.z, dz, __builtin_fmaf(w.y, dy, w.x * dx)) >= a.cosc ? 1u : 0u);
+                const float cv = __builtin_fmaf(w.z, dz, __builtin_fmaf(w.y, dy, w.x * dx));
+                mh = mh + mh + (cv >= a.cos_hi ? 1u : 0u);
+                nh = nh + nh + (cv >= a.cos_lo ? 1u : 0u);
             }
 #pragma unroll 8
             for (; k >= 0; --k) {
                 const V4 w = fj[k];
-                ml = ml + ml + (__builtin_fmaf(w.z, dz, __builtin_fmaf(w.y, dy, w.x * dx)) >= a.cosc ? 1u : 0u);
+                const float cv = __builtin_fmaf(w.z, dz, __builtin_fmaf(w.y, dy, w.x * dx));
+                ml = ml + ml + (cv >= a.cos_hi ? 1u : 0u);
+                nl = nl + nl + (cv >= a.cos_lo ? 1u : 0u);
             }
             cmw = (static_cast<unsigned long long>(mh) << 32) | ml;
+            unsigned long long band = ((static_cast<unsigned long long>(nh) << 32) | nl) ^ cmw;
+            if (band) {
+                const double ddx = dx, ddy = dy, ddz = dz;
+                const double px = a.pos[3 * j], py = a.pos[3 * j + 1], pz = a.pos[3 * j + 2];
+                while (band) {
+                    const int kb = __builtin_ctzll(band);
+                    band &= band - 1ull;
+                    const long long nb = nj[kb];
+                    if (in_cone(a.pos[3 * nb] - px, a.pos[3 * nb + 1] - py, a.pos[3 * nb + 2] - pz, ddx, ddy, ddz, a.c2d))
+                        cmw |= 1ull << kb;
+                }
+            }
+            // reception cone: the FP32 argmax unless the two largest dot
+            // products lie within kConeGuard, then the FP64 argmax
+            tgt = nearest_direction_guarded(static_cast<const R*>(rcd), a.wrc, nrc, dx, dy, dz);
         } else {
 #pragma unroll 8
             for (int k = 0; k < K; ++k) {
                 const V4 w = fj[k];
                 if (in_cone(w.x, w.y, w.z, dx, dy, dz, a.c2)) cmw |= 1ull << k;
             }
+            tgt = nearest_direction(static_cast<const R*>(rcd), nrc, dx, dy, dz);
         }
-        tgt = nearest_direction(static_cast<const R*>(rcd), nrc, dx, dy, dz);
     }
     const bool send = act && cmw != 0;
     const bool vip = act && cmw == 0;

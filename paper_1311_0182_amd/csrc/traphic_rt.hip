@@ -269,7 +269,12 @@ rt_status launch_hop(rt_ctx* c, int hop) {
     a.sigma = c->sigma_d;
     a.sigmaf = c->sigmaf_d;
     a.c2 = static_cast<R>(c->c2);
-    a.cosc = static_cast<R>(1.0 - 2.0 / static_cast<double>(c->p.n_tc));
+    a.c2d = c->c2;
+    {
+        const double cc = 1.0 - 2.0 / static_cast<double>(c->p.n_tc);
+        a.cos_lo = static_cast<float>(cc - kConeGuard);
+        a.cos_hi = static_cast<float>(cc + kConeGuard);
+    }
     a.dtc = c->f32 ? R(1) : static_cast<R>(c->p.dt);
     a.clf = c->clf_d;
     a.U = c->U_d;

@@ -282,7 +282,9 @@ def test_full_size_batched_first_steps():
     """The batched workload at full size (64 instances, 1.36 M particles, the
     launch configuration bench.py times): its first steps against the oracle,
     FP64 (neighbour lists and counters exact, x_HI within 1e-6, ledger closed)
-    and FP32 (x_HI within 1e-3, ledger residual within 1e-6)."""
+    and FP32 (x_HI within 1e-3, ledger residual within 1e-6).  Then the window
+    bench.py times (5 + 20 steps), FP32 against the FP64 GPU path after every
+    step: max |dx_HI| <= 1e-3 and both ledgers closed."""
     cfg = I.config(4)
     steps = 3
     say("batched 64 instances full size,", steps, "steps")
@@ -303,3 +305,39 @@ def test_full_size_batched_first_steps():
     say("fp32 max |dx_HI|", dx, "residual", np.max(residual(s32["ledger"])))
     assert dx <= 1e-3
     assert np.max(residual(s32["ledger"])) <= 1e-6
+    _fp32_window_against_fp64(cfg, 25)
+
+
+def _fp32_window_against_fp64(cfg, steps):
+    """FP32 and FP64 GPU runs side by side: max |dx_HI| <= 1e-3 after every step."""
+    a, b = run_gpu(cfg, 0, "fp32"), run_gpu(cfg, 0, "fp64")
+    worst = 0.0
+    for k in range(steps):
+        a.step(1)
+        b.step(1)
+        sa, sb = a.state(), b.state()
+        d = float(np.max(np.abs(sa["xHI"] - sb["xHI"])))
+        worst = max(worst, d)
+        assert d <= 1e-3, (k + 1, d)
+        assert np.max(residual(sa["ledger"])) <= 1e-6
+        assert np.max(residual(sb["ledger"])) <= 1e-12
+    say("fp32 vs fp64 over", steps, "steps: max |dx_HI|", worst)
+    a.close()
+    b.close()
+
+
+def test_full_size_rr64_fp32():
+    """The 64^3 workload with recombination radiation at full size in FP32: its
+    first steps against the oracle (x_HI within 1e-3, ledger residual 1e-6),
+    then the first 100 steps against the FP64 GPU path after every step."""
+    cfg = I.config(2)
+    s, _ = run_oracle(cfg, 3)
+    so = s.state()
+    c32 = run_gpu(cfg, 3, "fp32")
+    s32 = c32.state()
+    c32.close()
+    dx = np.max(np.abs(s32["xHI"] - so["xHI"]))
+    say("config 2 fp32 vs oracle, 3 steps: max |dx_HI|", dx)
+    assert dx <= 1e-3
+    assert np.max(residual(s32["ledger"])) <= 1e-6
+    _fp32_window_against_fp64(cfg, 100)

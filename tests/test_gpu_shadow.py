@@ -7,7 +7,7 @@ Small: FP64 against the oracle (counters exact, x_HI and T within 1e-6
 relative, ledger residual 1e-12) and FP32 within its bars.  Full size (128^3
 particles, 134 M slots): too large for the oracle in a test, so FP32 transport
 is checked against the FP64 GPU path on the same inputs (ledger residuals 1e-6
-and 1e-12, totals, slab means and the 99.99% quantile of |dx_HI|).
+and 1e-12, totals, slab means and max |dx_HI| <= 1e-3).
 
 With recombination radiation from outside the box (appendix B): isotropic
 boundary sources on the four faces parallel to the front, switched on between
@@ -81,11 +81,11 @@ def test_shadow_small_fp32_within_bars():
 
 def test_shadow_full_size_fp32_against_fp64_gpu():
     """Full size, FP32 transport against the FP64 GPU path on the same inputs.
-    Photon ledgers close in both.  Totals and slab means agree to far below the
-    bar; individual particles at the I-front can differ by more than 1e-3,
-    because a discrete choice (cone membership at a boundary, a virtual
-    particle's path) that flips between the precisions moves part of a packet
-    to other neighbours: those are few (checked) and unbiased (the totals)."""
+    Photon ledgers close in both; max |dx_HI| <= 1e-3 over every particle, and
+    totals and slab means agree to far below it.  The FP32 transport takes its
+    cone-membership and reception-cone decisions near their thresholds in FP64
+    (a guard band), so a decision flips between the precisions only through the
+    FP32 rounding of the packet's own direction."""
     from paper_1311_0182_amd import traphic_rt as RT
     cfg = I.config(3)
     steps = 2
@@ -105,8 +105,7 @@ def test_shadow_full_size_fp32_against_fp64_gpu():
     assert np.min(x64) < 0.5                 # the front entered the box
     d = np.abs(x32 - x64)
     say("max |dx_HI|", d.max(), "99.99% quantile", np.quantile(d, 0.9999), "beyond 1e-3", int(np.sum(d > 1e-3)))
-    assert np.quantile(d, 0.9999) <= 1e-3
-    assert np.mean(d > 1e-3) <= 1e-4
+    assert d.max() <= 1e-3
     ion64, ion32 = np.sum(1.0 - x64), np.sum(1.0 - x32)
     assert abs(ion32 - ion64) <= 1e-6 * ion64
     A64, A32 = s64["A"].sum(axis=0), s32["A"].sum(axis=0)
@@ -208,7 +207,7 @@ def test_boundary_rr_sources_full_size_fp32_against_fp64_gpu():
     a, b = out["fp32"], out["fp64"]
     r32, r64 = np.max(residual(a["ledger"])), np.max(residual(b["ledger"]))
     dx = np.abs(a["xHI"] - b["xHI"])
-    say("residuals", r32, r64, "max |dx_HI|", dx.max(), "99.9% quantile", np.quantile(dx, 0.999))
+    say("residuals", r32, r64, "max |dx_HI|", dx.max())
     assert r64 < 1e-12 and r32 < 1e-6
     # the sources emit the same photons; the gas's recombination photons follow its state
     assert rel(a["ledger"][0, [0, 2], 0], b["ledger"][0, [0, 2], 0]) < 1e-12
@@ -216,5 +215,5 @@ def test_boundary_rr_sources_full_size_fp32_against_fp64_gpu():
     A32, A64 = a["A"].sum(0), b["A"].sum(0)
     assert np.all(np.abs(A32 - A64) <= 1e-5 * np.maximum(A64, 1e-300))  # absorbed per bin
     assert A64[2] > 0                                                    # the outside-box bin arrives
-    assert np.quantile(dx, 0.999) <= 1e-3
+    assert dx.max() <= 1e-3
     assert abs(np.mean(a["xHI"]) - np.mean(b["xHI"])) < 1e-5
