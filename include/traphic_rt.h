@@ -8,7 +8,8 @@
  * Conventions for every entry point
  *   - Units are cgs: positions in cm, densities in cm^-3, time in s, photon
  *     counts in photons, energies in erg, temperatures in K.
- *   - Every array argument is a HOST pointer, owned by the caller and only
+ *   - Every array argument is a HOST pointer (one exception: passing_dev of
+ *     rt_shell_profile_noalloc), owned by the caller and only
  *     read (inputs) or written (outputs) during the call.  The library copies
  *     inputs to device memory it owns.
  *   - All device work runs on the HIP stream given to rt_init.  rt_step only
@@ -157,6 +158,24 @@ rt_status rt_get_state(rt_ctx *ctx, double *x_HI, double *T, double *absorbed, d
 rt_status rt_shell_profile(rt_ctx *ctx, int32_t inst, const double *passing, const double *center,
                            const double *axis, double half_height, double r_max, int32_t n_shells,
                            int32_t mean, double norm, double *prof, int64_t *count);
+
+/* rt_shell_profile for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same profile, arguments and limits, with two differences.
+ *   passing_dev   NULL: the context's passing photons of the last step; else a
+ *                 DEVICE array [N*n_freq] (photons) binned instead (host
+ *                 memory is rejected with RT_EINVAL: staging it would allocate)
+ *   scratch       the shell histogram lives in a static device array of the
+ *                 library, 64 KiB per GPU (6144 sums and 2048 counts: the
+ *                 limits above), held until the process ends; it is cleared
+ *                 by kernels at every call.
+ * No hipMalloc, hipFree or other allocating call is made.  Every call on one
+ * GPU uses that GPU's single array: calls that overlap on one GPU (two host
+ * threads, or two streams) race and must be serialised by the caller.
+ * Synchronises the stream.  Errors: RT_EINVAL (nothing written), RT_EDEVICE. */
+rt_status rt_shell_profile_noalloc(rt_ctx *ctx, int32_t inst, const double *passing_dev, const double *center,
+                                   const double *axis, double half_height, double r_max, int32_t n_shells,
+                                   int32_t mean, double norm, double *prof, int64_t *count);
 
 /* Packet bins [N][n_freq][n_rc] in physical units: photons, unit direction
  * (3 per bin) and clock in s since the start of the last step.  Any pointer may be NULL. */

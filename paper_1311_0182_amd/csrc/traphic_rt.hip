@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -19,6 +20,10 @@ using namespace trt;
 namespace {
 
 constexpr int kChunk = 2048;      // particles per ledger partial sum
+constexpr int kMaxDevices = 64;
+// Scratch of rt_shell_profile_noalloc: the shell histogram (sums, then
+// counts), the largest any call may need.
+constexpr size_t kProfScratchBytes = sizeof(double) * kProfMaxCells + sizeof(unsigned long long) * kProfMaxShells;
 
 struct DevBuf {
     void* p = nullptr;
@@ -27,9 +32,21 @@ struct DevBuf {
 
 }  // namespace
 
+// Allocation-free scratch (rt_shell_profile_noalloc): one copy per GPU, held
+// until the process ends.  Host code never uses this name as an address: the
+// device address of each GPU's copy is looked up once per device and kept in
+// g_scratch.
+static __device__ __align__(256) unsigned char scratch[kProfScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+}  // namespace
+
 struct rt_ctx {
     rt_params p{};
     hipStream_t stream = nullptr;
+    int dev = 0;           // device current at rt_init (the stream's)
     bool sticky = false;
     std::string err;
 
@@ -163,6 +180,25 @@ rt_status fail(rt_ctx* c, rt_status s, const std::string& m) {
         if (e_ != hipSuccess)                                                               \
             return fail(ctx, RT_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
+
+// The device address of this process's scratch on the context's GPU, looked
+// up once per device with that device current (rt_init does it; a context
+// made before another device's lookup finds its own entry already filled).
+rt_status resolve_scratch(rt_ctx* c) {
+    if (c->dev < 0 || c->dev >= kMaxDevices) return fail(c, RT_EDEVICE, "device index out of range for the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[c->dev]) return RT_OK;
+    int cur = -1;
+    HIPCHK(c, hipGetDevice(&cur));
+    if (cur != c->dev) HIPCHK(c, hipSetDevice(c->dev));
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != c->dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr)
+        return fail(c, RT_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch[c->dev] = ptr;
+    return RT_OK;
+}
 
 rt_status dalloc(rt_ctx* c, void** out, size_t bytes) {
     bytes = std::max<size_t>(bytes, 256);
@@ -740,6 +776,10 @@ rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, cons
     rt_ctx* c = new rt_ctx();
     c->p = *p;
     c->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipGetDevice(&c->dev) != hipSuccess) {
+        delete c;
+        return RT_EDEVICE;
+    }
     c->N = N;
     c->n_inst = n_inst;
     c->nf = p->n_freq;
@@ -994,6 +1034,7 @@ rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, cons
         ITRY(upload(c, &c->em_ioff, zero.data(), n_inst + 1ll));
     }
     ITRY(alloc_n(c, &c->emt, 2ll * n_inst * c->nf));
+    ITRY(resolve_scratch(c));
     HIPCHK(c, hipStreamSynchronize(c->stream));
 #undef ITRY
     *out = c;
@@ -1194,9 +1235,13 @@ rt_status rt_get_state(rt_ctx* c, double* x_HI, double* T, double* absorbed, dou
     return RT_OK;
 }
 
-rt_status rt_shell_profile(rt_ctx* c, int32_t inst, const double* passing, const double* center, const double* axis,
-                           double half_height, double r_max, int32_t n_shells, int32_t mean, double norm, double* prof,
-                           int64_t* count) {
+}  // extern "C"
+
+namespace {
+
+// Arguments of a shell profile, checked before any device work (RT_EINVAL).
+rt_status shell_profile_check(rt_ctx* c, int32_t inst, const double* center, const double* axis, double half_height,
+                              double r_max, int32_t n_shells, double norm, double* prof) {
     if (!c) return RT_EINVAL;
     if (c->sticky) return RT_EDEVICE;
     if (!center || !prof || inst < 0 || inst >= c->n_inst) return fail(c, RT_EINVAL, "shell profile: bad pointer or instance");
@@ -1210,18 +1255,18 @@ rt_status rt_shell_profile(rt_ctx* c, int32_t inst, const double* passing, const
         if (!(a2 > 0.0) || !std::isfinite(a2))
             return fail(c, RT_EINVAL, "shell profile: the axis's squared length must be finite and nonzero");
     }
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (!c->prof_sum) TRY(alloc_n(c, &c->prof_sum, kProfMaxCells));
-    if (!c->prof_cnt) TRY(alloc_n(c, &c->prof_cnt, kProfMaxShells));
-    const double* Pd = c->P;
-    if (passing) {
-        if (!c->prof_in) TRY(alloc_n(c, &c->prof_in, c->N * c->nf));
-        HIPCHK(c, hipMemcpy(c->prof_in, passing, sizeof(double) * c->N * c->nf, hipMemcpyHostToDevice));
-        Pd = c->prof_in;
-    }
+    return RT_OK;
+}
+
+// The profile of the passing photons Pd (device) binned into the histogram
+// sum[n_shells*nf], cnt[n_shells] (device, cleared here by fill kernels), copied
+// out and normalised.  Allocates nothing.
+rt_status shell_profile_run(rt_ctx* c, int32_t inst, const double* Pd, const double* center, const double* axis,
+                            double half_height, double r_max, int32_t n_shells, int32_t mean, double norm, double* sum,
+                            unsigned long long* cnt_d, double* prof, int64_t* count) {
     const int ncell = n_shells * c->nf;
-    TRY(fill_f64(c, c->prof_sum, ncell, 0.0));
-    TRY(fill_i32(c, reinterpret_cast<int*>(c->prof_cnt), 2ll * n_shells, 0));
+    TRY(fill_f64(c, sum, ncell, 0.0));
+    TRY(fill_i32(c, reinterpret_cast<int*>(cnt_d), 2ll * n_shells, 0));
     ProfileArgs a{};
     a.pos = c->pos;
     a.P = Pd;
@@ -1241,8 +1286,8 @@ rt_status rt_shell_profile(rt_ctx* c, int32_t inst, const double* passing, const
     a.half_height = half_height;
     a.r_max = r_max;
     a.dt = c->p.dt;
-    a.sum = c->prof_sum;
-    a.cnt = c->prof_cnt;
+    a.sum = sum;
+    a.cnt = cnt_d;
     // Workgroups: small instances get one per 256 particles (up to 128), large
     // ones one per 2048 (up to 256).  More would not help large instances: every
     // workgroup's flush adds into the same few cache lines, and those atomics
@@ -1254,9 +1299,9 @@ rt_status rt_shell_profile(rt_ctx* c, int32_t inst, const double* passing, const
     hipLaunchKernelGGL(k_shell_profile, dim3(grid), dim3(kProfBlock), lds, c->stream, a);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    std::vector<unsigned long long> cnt(n_shells);
-    HIPCHK(c, hipMemcpy(prof, c->prof_sum, sizeof(double) * ncell, hipMemcpyDeviceToHost));
-    HIPCHK(c, hipMemcpy(cnt.data(), c->prof_cnt, sizeof(unsigned long long) * n_shells, hipMemcpyDeviceToHost));
+    unsigned long long cnt[kProfMaxShells];
+    HIPCHK(c, hipMemcpy(prof, sum, sizeof(double) * ncell, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(cnt, cnt_d, sizeof(unsigned long long) * n_shells, hipMemcpyDeviceToHost));
     for (int k = 0; k < n_shells; ++k) {
         if (count) count[k] = static_cast<int64_t>(cnt[k]);
         for (int nu = 0; nu < c->nf; ++nu) {
@@ -1266,6 +1311,49 @@ rt_status rt_shell_profile(rt_ctx* c, int32_t inst, const double* passing, const
         }
     }
     return RT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rt_status rt_shell_profile(rt_ctx* c, int32_t inst, const double* passing, const double* center, const double* axis,
+                           double half_height, double r_max, int32_t n_shells, int32_t mean, double norm, double* prof,
+                           int64_t* count) {
+    TRY(shell_profile_check(c, inst, center, axis, half_height, r_max, n_shells, norm, prof));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (!c->prof_sum) TRY(alloc_n(c, &c->prof_sum, kProfMaxCells));
+    if (!c->prof_cnt) TRY(alloc_n(c, &c->prof_cnt, kProfMaxShells));
+    const double* Pd = c->P;
+    if (passing) {
+        if (!c->prof_in) TRY(alloc_n(c, &c->prof_in, c->N * c->nf));
+        HIPCHK(c, hipMemcpy(c->prof_in, passing, sizeof(double) * c->N * c->nf, hipMemcpyHostToDevice));
+        Pd = c->prof_in;
+    }
+    return shell_profile_run(c, inst, Pd, center, axis, half_height, r_max, n_shells, mean, norm, c->prof_sum,
+                             c->prof_cnt, prof, count);
+}
+
+rt_status rt_shell_profile_noalloc(rt_ctx* c, int32_t inst, const double* passing_dev, const double* center,
+                                   const double* axis, double half_height, double r_max, int32_t n_shells,
+                                   int32_t mean, double norm, double* prof, int64_t* count) {
+    TRY(shell_profile_check(c, inst, center, axis, half_height, r_max, n_shells, norm, prof));
+    const double* Pd = c->P;
+    if (passing_dev) {
+        hipPointerAttribute_t at{};
+        const hipError_t e = hipPointerGetAttributes(&at, passing_dev);
+        if (e != hipSuccess || (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)) {
+            (void)hipGetLastError();
+            return fail(c, RT_EINVAL, "shell profile (no allocation): passing must be device memory or NULL");
+        }
+        Pd = passing_dev;
+    }
+    TRY(resolve_scratch(c));
+    unsigned char* base = static_cast<unsigned char*>(g_scratch[c->dev]);
+    double* sum = reinterpret_cast<double*>(base);
+    unsigned long long* cnt_d = reinterpret_cast<unsigned long long*>(base + sizeof(double) * kProfMaxCells);
+    return shell_profile_run(c, inst, Pd, center, axis, half_height, r_max, n_shells, mean, norm, sum, cnt_d, prof,
+                             count);
 }
 
 rt_status rt_get_bins(rt_ctx* c, double* N, double* dir, double* clock) {

@@ -26,7 +26,7 @@ DEALLOC_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 EXPORTS = ["rt_init", "rt_add_sources", "rt_step", "rt_get_state", "rt_get_bins", "rt_get_neighbours",
            "rt_n_emitters", "rt_get_emitter_neighbours", "rt_get_cone_masks", "rt_get_pending_rr",
            "rt_set_timing", "rt_get_timing", "rt_set_hop_shape", "rt_get_hop_shape", "rt_get_state_blob",
-           "rt_set_state_blob", "rt_shell_profile", "rt_destroy",
+           "rt_set_state_blob", "rt_shell_profile", "rt_shell_profile_noalloc", "rt_destroy",
            "rt_last_error"]
 
 
@@ -98,6 +98,9 @@ def load():
     L.rt_shell_profile.restype = C.c_int
     L.rt_shell_profile.argtypes = [C.c_void_p, C.c_int32, dp, dp, dp, C.c_double, C.c_double, C.c_int32,
                                    C.c_int32, C.c_double, dp, i64p]
+    L.rt_shell_profile_noalloc.restype = C.c_int
+    L.rt_shell_profile_noalloc.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, dp, dp, C.c_double, C.c_double,
+                                           C.c_int32, C.c_int32, C.c_double, dp, i64p]
     L.rt_destroy.restype = None
     L.rt_destroy.argtypes = [C.c_void_p]
     L.rt_last_error.restype = C.c_char_p
@@ -275,6 +278,28 @@ class Context:
         self._check(L.rt_shell_profile(self.h, int(inst), pp, _p(c, C.c_double), ap, float(half_height),
                                        float(r_max), int(n_shells), int(bool(mean)), float(norm),
                                        _p(prof, C.c_double), _p(cnt, C.c_int64)))
+        return prof, cnt
+
+    def shell_profile_noalloc(self, center, r_max, n_shells, axis=None, half_height=0.0, mean=False, norm=1.0,
+                              inst=0, passing_dev=None):
+        """rt_shell_profile_noalloc: passing_dev is None or a CUDA tensor of N * n_freq
+        float64 values (device memory); returns (prof[n_shells, n_freq], count[n_shells])."""
+        L = load()
+        c = _f64(np.asarray(center).reshape(3))
+        ap = None
+        if axis is not None:
+            a = _f64(np.asarray(axis).reshape(3))
+            ap = _p(a, C.c_double)
+        dptr = None
+        if passing_dev is not None:
+            if passing_dev.numel() != self.N * self.nf or not passing_dev.is_contiguous():
+                raise ValueError("passing_dev must be a contiguous tensor of N * n_freq values")
+            dptr = C.c_void_p(passing_dev.data_ptr())
+        prof = np.empty((int(n_shells), self.nf))
+        cnt = np.empty(int(n_shells), dtype=np.int64)
+        self._check(L.rt_shell_profile_noalloc(self.h, int(inst), dptr, _p(c, C.c_double), ap, float(half_height),
+                                               float(r_max), int(n_shells), int(bool(mean)), float(norm),
+                                               _p(prof, C.c_double), _p(cnt, C.c_int64)))
         return prof, cnt
 
     def get_blob(self):
