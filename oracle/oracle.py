@@ -80,6 +80,8 @@ def lib():
         L.or_vip_sample.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, dp,
                                     C.c_int32, dp]
         L.or_merge_packets.argtypes = [C.c_int32, dp, dp, dp, dp, dp, dp]
+        L.or_vip_leg.argtypes = [C.c_void_p, C.c_int32, dp, dp, dp, C.c_double, C.c_int32, ip, dp, dp, dp, dp,
+                                 dp, dp]
         L.or_shell_profile.restype = C.c_int
         L.or_shell_profile.argtypes = [C.c_int64, C.c_int32, dp, dp, C.c_double, dp, dp, C.c_double,
                                        C.c_double, C.c_int32, C.c_int32, C.c_double, dp, i64p]
@@ -202,6 +204,21 @@ class OracleSim:
         h = np.empty(q.shape[0])
         lib().or_knn_points(self.h, int(inst), q.shape[0], qp, _ptr(nb, C.c_int32), _ptr(h, C.c_double))
         return nb.reshape(-1, k), h
+
+    def vip_leg(self, inst, x, xv, d, N, nu=0):
+        """One virtual-particle leg (or_vip_leg): dict of neighbours, h, deposits,
+        nhi, l, Nabs, Nrem."""
+        L = lib()
+        K = int(self.p["n_ngb"])
+        xa, xp = _d(np.asarray(x, dtype=float).reshape(3))
+        va, vp = _d(np.asarray(xv, dtype=float).reshape(3))
+        da, dpp = _d(np.asarray(d, dtype=float).reshape(3))
+        ngb = np.empty(K, dtype=np.int32)
+        dep = np.empty(K)
+        h, nhi, l, na, nr = (C.c_double() for _ in range(5))
+        L.or_vip_leg(self.h, int(inst), xp, vp, dpp, float(N), int(nu), _ptr(ngb, C.c_int32), C.byref(h),
+                     _ptr(dep, C.c_double), C.byref(nhi), C.byref(l), C.byref(na), C.byref(nr))
+        return dict(ngb=ngb, h=h.value, dep=dep, nhi=nhi.value, l=l.value, Nabs=na.value, Nrem=nr.value)
 
     def close(self):
         if getattr(self, "h", None):

@@ -811,6 +811,52 @@ typedef struct {
     uint32_t tag, ida, idb_base; /* Philox identity of the draws */
 } vip_req;
 
+/* The leg of a packet from x to its virtual particle at xv (section 2.1):
+ * the virtual particle's N_ngb nearest particles vn (and its smoothing length
+ * hv, the distance to the farthest); its neutral hydrogen density by SPH
+ * interpolation, nhi = sum_k w_k x_HI,k n_H,k / sum_k w_k with weights
+ * w_k = W(r_k, hv) N_H,k / n_H,k (W the cubic spline, N_H / n_H the particle's
+ * volume); the path length l along d; the absorbed Nabs = N (1 - exp(-tau)),
+ * tau = sigma_nu nhi l, shared among the neighbours in proportion to w_k
+ * (dep[k]), and the rest Nrem.  If every weight vanishes (reading) the
+ * neighbours count equally. */
+static void vip_leg(const or_sim *S, int inst, const double x[3], const double xv[3], const double d[3], double N,
+                    int nu, int32_t *vn, double *hv, double *dep, double *nhi_out, double *l_out, double *Nabs,
+                    double *Nrem)
+{
+    int K = S->p.n_ngb;
+    double wk[64];
+    knn(S, inst, xv, -1, K, vn, hv);
+    double wsum = 0.0, nhi = 0.0;
+    for (int k = 0; k < K; ++k) {
+        const double *xk = S->pos + 3 * (int64_t)vn[k];
+        double dx = xk[0] - xv[0], dy = xk[1] - xv[1], dz = xk[2] - xv[2];
+        double r = sqrt(dx * dx + dy * dy + dz * dz);
+        wk[k] = w_spline(r, *hv) * (S->NH[vn[k]] / S->nH[vn[k]]);
+        wsum += wk[k];
+    }
+    if (!(wsum > 0.0)) {
+        for (int k = 0; k < K; ++k) wk[k] = 1.0;
+        wsum = (double)K;
+    }
+    for (int k = 0; k < K; ++k) nhi += wk[k] * (S->xHI[vn[k]] * S->nH[vn[k]]);
+    nhi = nhi / wsum;
+    double dd = sqrt(dot3(d, d));
+    double l = ((xv[0] - x[0]) * d[0] + (xv[1] - x[1]) * d[1] + (xv[2] - x[2]) * d[2]) / dd;
+    double tau = S->sigma[nu] * nhi * l;
+    attenuate(N, tau, Nabs, Nrem);
+    for (int k = 0; k < K; ++k) dep[k] = *Nabs * wk[k] / wsum;
+    *nhi_out = nhi;
+    *l_out = l;
+}
+
+void or_vip_leg(const or_sim *S, int32_t inst, const double x[3], const double xv[3], const double d[3], double N,
+                int32_t nu, int32_t *ngb, double *h, double *dep, double *nhi, double *l, double *Nabs,
+                double *Nrem)
+{
+    vip_leg(S, inst, x, xv, d, N, nu, ngb, h, dep, nhi, l, Nabs, Nrem);
+}
+
 /* Virtual particle chain for a packet whose cone holds no neighbour (section
  * 2.1).  Reading: the virtual particle is drawn uniformly in the part of the
  * cone inside the ball of radius h around the origin (rejection from the cube
@@ -844,28 +890,10 @@ static void vip_chain(or_sim *S, vip_req q, double *X, double *R)
                 return;
             }
         }
-        double hv;
-        knn(S, q.inst, xv, -1, K, vn, &hv);
-        double wsum = 0.0, nhi = 0.0;
-        for (int k = 0; k < K; ++k) {
-            const double *xk = S->pos + 3 * (int64_t)vn[k];
-            double dx = xk[0] - xv[0], dy = xk[1] - xv[1], dz = xk[2] - xv[2];
-            double r = sqrt(dx * dx + dy * dy + dz * dz);
-            wk[k] = w_spline(r, hv) * (S->NH[vn[k]] / S->nH[vn[k]]);
-            wsum += wk[k];
-        }
-        if (!(wsum > 0.0)) {
-            for (int k = 0; k < K; ++k) wk[k] = 1.0;
-            wsum = (double)K;
-        }
-        for (int k = 0; k < K; ++k) nhi += wk[k] * (S->xHI[vn[k]] * S->nH[vn[k]]);
-        nhi = nhi / wsum;
+        double hv, nhi, l, Nabs, Nrem;
+        vip_leg(S, q.inst, q.x, xv, q.d, q.N, q.nu, vn, &hv, wk, &nhi, &l, &Nabs, &Nrem);
+        for (int k = 0; k < K; ++k) S->A[(int64_t)vn[k] * nf + q.nu] += wk[k];
         double dd = sqrt(dot3(q.d, q.d));
-        double l = ((xv[0] - q.x[0]) * q.d[0] + (xv[1] - q.x[1]) * q.d[1] + (xv[2] - q.x[2]) * q.d[2]) / dd;
-        double tau = S->sigma[q.nu] * nhi * l;
-        double Nabs, Nrem;
-        attenuate(q.N, tau, &Nabs, &Nrem);
-        for (int k = 0; k < K; ++k) S->A[(int64_t)vn[k] * nf + q.nu] += Nabs * wk[k] / wsum;
         double cv = q.c + l / C_LIGHT;
         int nc = 0;
         for (int k = 0; k < K; ++k) {

@@ -20,14 +20,21 @@
  * photon conservation; case-B I-front growth; shell profiles on hand-placed
  * particles and against an independent membership test; the case-B/case-A ratio in the
  * optically thin centre; on-the-spot balance of recombination radiation in
- * optically thick gas; the Riccati closed form of the isothermal chemistry.
+ * optically thick gas; the Riccati closed form of the isothermal chemistry;
+ * the light-travel clock (a front stops at the first particle whose projected
+ * path reaches c dt and resumes with its clock less dt; clocks advance by the
+ * projected path); recombination photons enter the reception cones at clock
+ * zero, an equal share per cone; virtual-particle legs (a constant field
+ * interpolates to itself, deposits sum to the absorbed photons, the farthest
+ * neighbour receives nothing); the section-4 photoheated temperature (soft).
  *
- * parity unpinned: the cooling coefficients of or_rates (recombination
- * cooling, collisional ionization and excitation cooling, free-free, Compton)
- * and the SPH interpolation weights of virtual particles.  The paper takes
- * both from predecessor papers it does not reproduce; only the integrator of
- * the temperature equation and photon conservation through virtual particles
- * are pinned.
+ * parity unpinned: the individual cooling coefficients of or_rates
+ * (recombination cooling, collisional ionization and excitation cooling,
+ * free-free, Compton; only their combination at the section-4 photoheating
+ * equilibrium is pinned, softly, to the paper's 27000 K) and the form of the
+ * SPH interpolation weights of virtual particles (W_k N_H,k / n_H,k; only the
+ * properties above are pinned).  The paper takes both from predecessor papers
+ * it does not reproduce.
  */
 #ifndef TRAPHIC_ORACLE_H
 #define TRAPHIC_ORACLE_H
@@ -88,6 +95,14 @@ void or_merge_packets(int32_t n, const double *N, const double *d, const double 
                       double *od, double *oc);
 void or_knn_points(const or_sim *S, int32_t inst, int64_t n_q, const double *q,
                    int32_t *ngb, double *h);
+/* One virtual-particle leg from x to the virtual particle at xv along d
+ * (section 2.1): its neighbours ngb[n_ngb] and smoothing length h, the
+ * interpolated neutral density nhi, the path length l, the absorbed and
+ * remaining photons of a packet of N, and the deposits dep[n_ngb] of the
+ * absorbed photons on the neighbours.  Changes nothing in S. */
+void or_vip_leg(const or_sim *S, int32_t inst, const double x[3], const double xv[3], const double d[3],
+                double N, int32_t nu, int32_t *ngb, double *h, double *dep, double *nhi, double *l,
+                double *Nabs, double *Nrem);
 /* Intensity profile in spherical or cylindrical shells (sections 3 and 4). */
 int or_shell_profile(int64_t n, int32_t nf, const double *pos, const double *P, double dt,
                      const double center[3], const double *axis, double half_height, double r_max,

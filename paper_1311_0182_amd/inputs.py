@@ -5,6 +5,10 @@ positions, densities, atom counts, initial ionization state and temperature,
 sources and the per-bin grey constants.  It holds none of the transport,
 chemistry or recombination arithmetic of the method, and it is the only code
 shared by the CPU oracle and the HIP path (both take these arrays as inputs).
+Three formulas size inputs only: the grey cross-sections and excess energies of
+blackbody bins (a quadrature of the Verner et al. 1996 cross-section), the
+recombination coefficients at 1e4 K that size the boundary sources of the
+shadow test, and the appendix-B intensity those sources carry.
 
 The shapes follow the paper's test set-ups:
   * Stromgren HII region (section 3): uniform hydrogen, n_H = 1e-3 cm^-3,
@@ -176,14 +180,59 @@ def batched(n_inst=64, side_lo=8, side_hi=48, n_ngb=48, n_steps=100, seed_k=4, r
     return _pack(f"batched{n_inst}", params, [SIGMA_13P6] * n_freq, [0.0] * n_freq, insts, src, n_steps)
 
 
+# Hydrogen photoionization cross-section: the analytic fit of Verner, Ferland,
+# Korista & Yakovlev (1996, ApJ 465, 487), which section 2.1 cites for the
+# frequency-dependent cross-sections.  For H I the fit's parameters are
+# E_0 = 0.4298 eV, sigma_0 = 5.475e4 Mb, y_a = 32.88, P = 2.963 (y_w = y_0 =
+# y_1 = 0): with x = y = E/E_0,
+#   sigma(E) = sigma_0 (x - 1)^2 y^(P/2 - 5.5) (1 + sqrt(y/y_a))^-P  for E >= 13.6 eV.
+VERNER_HI = dict(E0_ev=0.4298, sigma0_cm2=5.475e4 * 1e-18, ya=32.88, P=2.963)
+E_HI_EV = 13.6
+
+
+def sigma_hi_verner(e_ev):
+    """Verner et al. (1996) hydrogen photoionization cross-section (cm^2) at photon energy e_ev."""
+    v = VERNER_HI
+    y = np.asarray(e_ev, dtype=np.float64) / v["E0_ev"]
+    return v["sigma0_cm2"] * (y - 1.0) ** 2 * y ** (0.5 * v["P"] - 5.5) * (1.0 + np.sqrt(y / v["ya"])) ** (-v["P"])
+
+
+def blackbody_grey_bins(t_bb, edges_ev, n_per_bin=4001):
+    """Grey constants of a blackbody of temperature t_bb (K) in the photon-energy bins
+    edges_ev (section 2.1's grey approximation: the spectral shape inside a bin
+    enters as a cross-section averaged over the source spectrum): the fraction of
+    the photons (between the first and last edge) in each bin, the photon-weighted
+    cross-section <sigma> (cm^2), and the excess energy per absorption <eps> (eV),
+    E - 13.6 eV weighted by sigma times the photon spectrum (the optically thin
+    limit).  The photon spectrum is B_nu / h nu ~ E^2 / (exp(E / kT) - 1).
+    Composite Simpson quadrature on n_per_bin points per bin, uniform in log E."""
+    kt = K_BOLTZ * t_bb / EV_ERG
+    frac, sig, eps, num = [], [], [], []
+    for a, b in zip(edges_ev[:-1], edges_ev[1:]):
+        u = np.linspace(math.log(a), math.log(b), n_per_bin)
+        e = np.exp(u)
+        w = np.full(n_per_bin, 2.0)
+        w[1::2] = 4.0
+        w[0] = w[-1] = 1.0
+        w *= (u[1] - u[0]) / 3.0 * e           # dE = E du
+        nph = e * e / (np.exp(e / kt) - 1.0)   # E / kT >= 1.5 here: no cancellation
+        sg = sigma_hi_verner(e)
+        n = np.sum(w * nph)
+        sn = np.sum(w * sg * nph)
+        num.append(n)
+        sig.append(sn / n)
+        eps.append(np.sum(w * (e - E_HI_EV) * sg * nph) / sn)
+    tot = sum(num)
+    frac = [n / tot for n in num]
+    return tuple(frac), tuple(sig), tuple(eps)
+
+
 # Grey bins of a 1e5 K blackbody between 13.6, 24.6, 54.4 and 100 eV (section 4
-# uses this spectrum), with the hydrogen cross-section taken as 6.3e-18 cm^2
-# (nu / nu_0)^-3: the fraction of the photons in each bin, the photon-weighted
-# cross-section and the cross-section-weighted excess energy per absorption.
+# uses this spectrum), from the Verner cross-section: the fraction of the
+# photons in each bin, the photon-weighted cross-section and the
+# cross-section-weighted excess energy per absorption.
 BB1E5_EDGES_EV = (13.6, 24.6, 54.4, 100.0)
-BB1E5_FRAC = (0.4478, 0.4944, 0.0577)
-BB1E5_SIGMA = (2.802e-18, 4.746e-19, 6.390e-20)
-BB1E5_EPS_EV = (3.726, 17.393, 48.316)
+BB1E5_FRAC, BB1E5_SIGMA, BB1E5_EPS_EV = blackbody_grey_bins(1e5, BB1E5_EDGES_EV)
 EPS_RR_EV = 2.327      # kT at 2.7e4 K: excess energy of a recombination photon (section 4)
 
 
@@ -225,9 +274,19 @@ def shadow(n_side=128, box_kpc=6.6, n_h=2e-4, clump_nh=0.04, clump_r_kpc=0.8,
 # photons travel in one bin.
 SIGMA_BB1E5_GREY = 1.6e-18     # cm^2
 EPS_BB1E5_GREY_EV = 6.3        # eV
-# Case-A and case-B recombination coefficients of hydrogen at 1e4 K (standard
-# tabulated values), used only to size the boundary sources of the recipe below.
-ALPHA_A_1E4 = 4.18e-13         # cm^3/s
+
+
+def alpha_hg97(t):
+    """Case-A and case-B recombination coefficients of hydrogen (cm^3/s) at
+    temperature t (K): the fits of Hui & Gnedin (1997) that section 2.1 adopts,
+    with lambda = 2 T_HI / T and T_HI = 157807 K,
+      alpha_A = 1.269e-13 lambda^1.503 / (1 + (lambda / 0.522)^0.470)^1.923,
+      alpha_B = 2.753e-14 lambda^1.5 / (1 + (lambda / 2.740)^0.407)^2.242.
+    Used here only to size the boundary sources of the recipe below."""
+    lam = 2.0 * 157807.0 / t
+    a_a = 1.269e-13 * lam ** 1.503 / (1.0 + (lam / 0.522) ** 0.470) ** 1.923
+    a_b = 2.753e-14 * lam ** 1.5 / (1.0 + (lam / 2.740) ** 0.407) ** 2.242
+    return a_a, a_b
 # Boundary-source grid faces: (normal axis, side) for y = lo, y = hi, z = lo, z = hi.
 BOUNDARY_FACES = ((1, 0), (1, 1), (2, 0), (2, 1))
 
@@ -240,12 +299,15 @@ def boundary_rr_intensity(flux, n_h, sigma=SIGMA_13P6):
     E = alpha_1 n_H^2 x^2 (alpha_1 = alpha_A - alpha_B), and the mean free path
     of their photons, lambda = 1 / (sigma n_H (1 - x)); integrating
     E e^{-r/lambda} / (4 pi r^2) over the sphere of radius lambda gives the
-    intensity I = (1 - 1/e) lambda E (photons/s/cm^2), the appendix's 0.63 lambda E."""
-    a = ALPHA_B_1E4 * n_h / (sigma * flux)
+    intensity I = (1 - 1/e) lambda E (photons/s/cm^2), the appendix's 0.63 lambda E.
+    Recombination coefficients at 1e4 K from alpha_hg97."""
+    a_a, a_b = alpha_hg97(1e4)
+    a = a_b * n_h / (sigma * flux)
     x = 2.0 / (1.0 + math.sqrt(1.0 + 4.0 * a))          # positive root of a x^2 + x - 1 = 0
     lam = 1.0 / (sigma * n_h * (1.0 - x))
-    emis = (ALPHA_A_1E4 - ALPHA_B_1E4) * n_h * n_h * x * x
-    return dict(x_HII=x, mfp=lam, emissivity=emis, intensity=(1.0 - math.exp(-1.0)) * lam * emis)
+    emis = (a_a - a_b) * n_h * n_h * x * x
+    return dict(x_HII=x, mfp=lam, emissivity=emis, intensity=(1.0 - math.exp(-1.0)) * lam * emis,
+                alpha_A=a_a, alpha_B=a_b)
 
 
 def shadow_boundary(n_side=32, box_kpc=13.2, n_h=1e-3, clump_nh=1.0, clump_r=0.1,

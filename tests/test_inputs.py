@@ -24,14 +24,38 @@ def test_instances_partition_the_batch():
     assert sum(len(p["sources"]["inst"]) for p in parts) == len(cfg["sources"]["inst"])
 
 
-def test_blackbody_bins_from_the_spectrum():
-    """The grey constants of the shadow set-up: photon fractions, photon-weighted
-    cross-sections (hydrogen sigma ~ nu^-3 from 6.3e-18 cm^2 at 13.6 eV) and
-    excess energies of a 1e5 K blackbody, recomputed by quadrature."""
+def test_verner_cross_section_and_grey_bins_against_the_paper():
+    """The grey constants of the shadow set-up come from the Verner et al. (1996)
+    hydrogen cross-section averaged over a 1e5 K blackbody (section 2.1).
+    Pins: the cross-section at 13.6 eV is the paper's 6.3e-18 cm^2; all photons
+    of 13.6-100 eV in one bin give section 4's printed 1.6e-18 cm^2 and 6.3 eV."""
+    v, tol = _paper("sigma_13p6_cm2")
+    assert abs(float(I.sigma_hi_verner(13.6)) / v - 1) < tol
+    f1, s1, e1 = I.blackbody_grey_bins(1e5, (13.6, 100.0))
+    v, tol = _paper("bb1e5_grey_sigma_cm2")
+    assert abs(s1[0] / v - 1) < tol
+    v, tol = _paper("bb1e5_grey_eps_ev")
+    assert abs(e1[0] / v - 1) < tol
+    # the three bins of the shadow set-up recombine into the single bin: the
+    # photon-weighted cross-sections and the absorption-weighted energies add up
+    f, sg, ep = I.BB1E5_FRAC, I.BB1E5_SIGMA, I.BB1E5_EPS_EV
+    assert abs(sum(f) - 1) < 1e-12
+    sbar = sum(a * b for a, b in zip(f, sg))
+    assert abs(sbar / s1[0] - 1) < 1e-9
+    assert abs(sum(a * b * c for a, b, c in zip(f, sg, ep)) / sbar / e1[0] - 1) < 1e-9
+    # the cross-section falls steeply: the bins are ordered and separated
+    assert sg[0] > 5 * sg[1] > 25 * sg[2]
+    assert 0 < ep[0] < 11.0 < ep[1] < 40.8 < ep[2] < 86.4
+
+
+def test_grey_bins_quadrature_against_adaptive_quadrature():
+    """The Simpson quadrature of inputs.blackbody_grey_bins against scipy's
+    adaptive quadrature of the same integrands (photon spectrum E^2/(e^(E/kT)-1)
+    from B_nu/h nu; cross-section-weighted excess energy)."""
     from scipy.integrate import quad
     kT = 8.617333262e-5 * 1e5
     nph = lambda e: e * e / np.expm1(e / kT)
-    sig = lambda e: I.SIGMA_13P6 * (e / 13.6) ** -3
+    sig = lambda e: float(I.sigma_hi_verner(e))
     edges = I.BB1E5_EDGES_EV
     tot = quad(nph, edges[0], edges[-1])[0]
     for b in range(3):
@@ -39,9 +63,9 @@ def test_blackbody_bins_from_the_spectrum():
         n = quad(nph, a, c)[0]
         sn = quad(lambda e: sig(e) * nph(e), a, c)[0]
         en = quad(lambda e: (e - 13.6) * sig(e) * nph(e), a, c)[0]
-        assert abs(n / tot - I.BB1E5_FRAC[b]) < 1e-4
-        assert abs(sn / n / I.BB1E5_SIGMA[b] - 1) < 1e-3
-        assert abs(en / sn / I.BB1E5_EPS_EV[b] - 1) < 1e-3
+        assert abs(n / tot / I.BB1E5_FRAC[b] - 1) < 1e-8
+        assert abs(sn / n / I.BB1E5_SIGMA[b] - 1) < 1e-8
+        assert abs(en / sn / I.BB1E5_EPS_EV[b] - 1) < 1e-8
 
 
 def test_shadow_layout():
@@ -72,7 +96,14 @@ def test_boundary_rr_intensity_appendix_b():
     assert abs(b["mfp"] / I.KPC_CM / v - 1) < tol
     # ionization balance holds at the root taken
     x = b["x_HII"]
-    assert abs(I.SIGMA_13P6 * 1e6 * (1 - x) / (I.ALPHA_B_1E4 * 1e-3 * x * x) - 1) < 1e-9
+    assert abs(I.SIGMA_13P6 * 1e6 * (1 - x) / (b["alpha_B"] * 1e-3 * x * x) - 1) < 1e-9
+    # the recombination coefficients are the Hui & Gnedin (1997) fits the
+    # chemistry uses: inputs.py and the oracle code them independently
+    from oracle import oracle as O
+    r = O.rates(1e4)
+    assert abs(b["alpha_A"] / r["alpha_A"] - 1) < 1e-12
+    assert abs(b["alpha_B"] / r["alpha_B"] - 1) < 1e-12
+    assert abs(b["emissivity"] / ((r["alpha_A"] - r["alpha_B"]) * 1e-6 * x * x) - 1) < 1e-12
     # the intensity is the integral over the sphere of radius lambda_mfp ...
     lam, E = b["mfp"], b["emissivity"]
     val, err = quad(lambda r: 4 * np.pi * E * np.exp(-r / lam) / (4 * np.pi * r * r) * r * r, 0.0, lam)

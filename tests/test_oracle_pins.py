@@ -657,3 +657,201 @@ def test_rr_in_reception_cones_matches_the_original_scheme():
     # the shells move by several times the tolerance and nothing is emitted
     assert np.max(np.abs(lost[0] - orig[0])) > 5e-3
     assert lost[1] == 0.0
+
+
+# ----- clocks (section 2.1: packets move until the clock reaches c dt) ---------
+
+C_LIGHT = 2.99792458e10
+
+
+def _bins_by_particle(s):
+    Nb, d, c = s.bins()
+    G = s.G
+    return Nb.reshape(-1, G), d.reshape(-1, G, 3), c.reshape(-1, G)
+
+
+def test_clock_front_stops_at_light_travel_distance():
+    """A plane front along a straight chain (spacing 0.1 kpc) in nearly empty
+    gas, with c dt = 0.306 kpc: the clock of a packet at particle j is its path
+    along +x, x_j / c.  Step 1: packets move while that is below dt, so the
+    front stops at the first particle with x_j >= c dt (x_3 = 0.35 kpc), and
+    photons pass particles 0..3 only.  Step 2: the stopped packet resumes with
+    its clock less dt and stops again 3 particles on (clock 0.35 + 0.3 - c dt
+    kpc / c), while the new emission stops at particle 3 again."""
+    dt = 1e-3 * I.MYR_S
+    cfg = I.chain(n=12, spacing_kpc=0.1, x_hi=1e-6, dt=dt)
+    kpc = I.KPC_CM
+    cdt = C_LIGHT * dt
+    assert 0.25 * kpc < cdt < 0.35 * kpc
+    s = O.OracleSim(cfg)
+    s.step(1)
+    P = s.state()["P"][:, 0]
+    assert np.all(P[:4] > 0) and np.all(P[4:] == 0)
+    Nb, _, c = _bins_by_particle(s)
+    held = np.flatnonzero(Nb.sum(axis=1) > 0)
+    assert held.tolist() == [3]
+    q = int(np.argmax(Nb[3]))
+    assert abs(c[3, q] / (0.35 * kpc / C_LIGHT) - 1) < 1e-12
+    s.step(1)
+    P = s.state()["P"][:, 0]
+    assert np.all(P[:7] > 0) and np.all(P[7:] == 0)
+    Nb, _, c = _bins_by_particle(s)
+    held = np.flatnonzero(Nb.sum(axis=1) > 0)
+    assert held.tolist() == [3, 6]
+    q3, q6 = int(np.argmax(Nb[3])), int(np.argmax(Nb[6]))
+    assert abs(c[3, q3] / (0.35 * kpc / C_LIGHT) - 1) < 1e-12
+    assert abs(c[6, q6] / ((0.65 * kpc - cdt) / C_LIGHT) - 1) < 1e-12
+    E, A, X, R, F = s.state()["ledger"][0, 0]
+    assert abs(E - (A + X + R + F)) <= 1e-14 * E
+
+
+def _three_particles(max_hops):
+    kpc = I.KPC_CM
+    pos = np.array([[0.05, 0.52, 0.5], [0.07, 0.47, 0.5], [0.30, 0.50, 0.5]]) * kpc
+    n = pos.shape[0]
+    p = I.default_params(n_ngb=2, n_freq=1, n_em=1, freeze_chem=1, max_hops=max_hops)
+    src = dict(inst=np.zeros(1, np.int32), kind=np.array([I.SRC_PLANE_XLO], np.int32),
+               pos=np.zeros((1, 3)), rate=np.array([[1e6]]), n_side=np.array([1], np.int32))
+    inst = dict(pos=pos, nH=np.full(n, 1e-3), NH=np.full(n, 1e57), xHI=np.full(n, 1e-6), T=np.full(n, 1e4),
+                box_lo=np.zeros(3), box_hi=np.array([0.4, 1.0, 1.0]) * kpc)
+    return I._pack("three", p, [I.SIGMA_13P6], [0.0], [inst], src, 1)
+
+
+def test_clock_advances_by_the_projected_path():
+    """Section 2.1: l_ij is the distance projected onto the propagation
+    direction, and the clock measures the distance covered.  A front along +x
+    reaches two off-axis particles at x = 0.05 and 0.07 kpc: their clocks are
+    0.05 and 0.07 kpc / c (not their distances 0.0539 and 0.0762 kpc).  One
+    forward step on, both packets reach the particle at x = 0.30 kpc, each after
+    0.30 kpc of projected path, so the merged clock is 0.30 kpc / c (the
+    distances would give 0.305 and 0.308)."""
+    kpc = I.KPC_CM
+    s = O.OracleSim(_three_particles(0))
+    s.step(1)
+    Nb, d, c = _bins_by_particle(s)
+    for j, x in ((0, 0.05), (1, 0.07)):
+        q = int(np.argmax(Nb[j]))
+        assert Nb[j, q] > 0 and np.count_nonzero(Nb[j]) == 1
+        assert abs(c[j, q] / (x * kpc / C_LIGHT) - 1) < 1e-12
+        assert np.allclose(d[j, q], [1.0, 0.0, 0.0], atol=1e-15)
+    assert np.all(Nb[2] == 0)
+    s = O.OracleSim(_three_particles(1))
+    assert s.step(1) == 4          # the packets at particle 2 are still moving: hop cap
+    Nb, d, c = _bins_by_particle(s)
+    assert np.all(Nb[:2] == 0) and np.count_nonzero(Nb[2]) == 1
+    q = int(np.argmax(Nb[2]))
+    assert abs(c[2, q] / (0.30 * kpc / C_LIGHT) - 1) < 1e-12
+
+
+def test_rr_packets_enter_the_reception_cones_at_clock_zero():
+    """Section 2.2: the recombination photons of a chemistry step are emitted
+    into the particle's N_RC reception cones at the start of the next step, an
+    equal share per cone, clock zero, along the cones' directions, which are
+    the isotropic set rotated for that step.  Run with no forward step, so the
+    RR bin holds exactly that emission."""
+    cfg = I.stromgren(8, rr=True, n_ngb=16, dt_myr=0.5, max_hops=0)
+    cfg["xHI"] = np.full(cfg["pos"].shape[0], 0.3)   # partly ionized: recombinations from step 1
+    s = O.OracleSim(cfg)
+    s.step(1)
+    nrr = s.nrr()
+    assert np.all(nrr > 0)
+    s.step(1)
+    Nb, d, c = _bins_by_particle(s)
+    nrc = int(cfg["params"]["n_rc"])
+    rr = slice(nrc * cfg["params"]["rr_bin"], nrc * (cfg["params"]["rr_bin"] + 1))
+    Nr, dr, cr = Nb[:, rr], d[:, rr], c[:, rr]
+    assert np.allclose(Nr, nrr[:, None] / nrc, rtol=1e-15, atol=0)
+    assert np.all(cr == 0.0)
+    # every particle's cones share one rotated copy of the cube diagonals
+    assert np.allclose(dr, dr[0][None], rtol=0, atol=1e-15)
+    gram = dr[0] @ dr[0].T
+    assert np.allclose(gram, O.dirset(nrc) @ O.dirset(nrc).T, atol=1e-12)
+    assert not np.allclose(dr[0], O.dirset(nrc), atol=1e-3)
+
+
+# ----- virtual-particle legs (section 2.1) --------------------------------------
+
+def _vip_setup(seed_k=9, uniform=True):
+    cfg = I.stromgren(10, rr=False, n_ngb=32, seed_k=seed_k)
+    n = cfg["pos"].shape[0]
+    if not uniform:
+        rng = np.random.default_rng(I.BASE_SEED + 77)
+        cfg["xHI"] = rng.uniform(1e-4, 1.0, n)
+        cfg["nH"] = cfg["nH"] * rng.uniform(0.2, 5.0, n)
+        cfg["NH"] = cfg["NH"] * rng.uniform(0.5, 2.0, n)
+    return cfg
+
+
+def test_vip_leg_constant_field_interpolates_to_itself():
+    """SPH interpolation with normalised weights returns a constant neutral
+    density exactly (up to rounding): the leg's optical depth and absorbed
+    photons are then the closed form N (1 - exp(-sigma n_HI l)) with l the
+    path projected on the packet's direction."""
+    cfg = _vip_setup()
+    xhi = 0.37
+    cfg["xHI"] = np.full(cfg["pos"].shape[0], xhi)
+    s = O.OracleSim(cfg, with_sources=False)
+    L = cfg["box"][0][3]
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        x = rng.uniform(0.2 * L, 0.8 * L, 3)
+        d = rng.normal(size=3)
+        xv = x + rng.uniform(0.01, 0.1) * L * (d / np.linalg.norm(d)) + rng.normal(size=3) * 0.01 * L
+        N = 1e55
+        r = s.vip_leg(0, x, xv, d, N)
+        n_hi = xhi * 1e-3
+        assert abs(r["nhi"] / n_hi - 1) < 1e-14
+        l = np.dot(xv - x, d) / np.linalg.norm(d)
+        assert abs(r["l"] / l - 1) < 1e-12
+        nabs = -N * math.expm1(-I.SIGMA_13P6 * n_hi * l)
+        assert abs(r["Nabs"] / nabs - 1) < 1e-12
+        assert abs(r["Nabs"] + r["Nrem"] - N) <= 1e-15 * N
+
+
+def test_vip_leg_deposits_sum_to_the_absorbed_photons():
+    """The leg's absorbed photons are shared among the virtual particle's
+    neighbours and nothing else: the deposits sum to N_abs for any field.  The
+    cubic spline has compact support, so the farthest neighbour (at r = h, the
+    smoothing length) receives nothing, and with equal particle volumes a
+    nearer neighbour never receives less than a farther one."""
+    rng = np.random.default_rng(6)
+    for uniform in (True, False):
+        cfg = _vip_setup(uniform=uniform)
+        s = O.OracleSim(cfg, with_sources=False)
+        L = cfg["box"][0][3]
+        for _ in range(20):
+            x = rng.uniform(0.1 * L, 0.9 * L, 3)
+            xv = x + rng.normal(size=3) * 0.05 * L
+            d = xv - x + rng.normal(size=3) * 0.01 * L
+            r = s.vip_leg(0, x, xv, d, 3e57)
+            dep = r["dep"]
+            assert np.all(dep >= 0)
+            assert abs(dep.sum() / r["Nabs"] - 1) < 1e-14
+            pv = cfg["pos"][r["ngb"]]
+            dist = np.linalg.norm(pv - xv[None, :], axis=1)
+            assert abs(dist[-1] / r["h"] - 1) < 1e-14 and dep[-1] == 0.0
+            if uniform:
+                order = np.argsort(dist, kind="stable")
+                assert np.all(np.diff(dep[order]) <= 1e-15 * dep.max())
+
+
+# ----- photoheating (section 4) ---------------------------------------------------
+
+def test_photoheated_gas_temperature_section4_soft():
+    """Soft pin of the cooling functions (their coefficients come from a table
+    the paper cites but does not print): section 4's gas, n_H = 1e-3 starting at
+    100 K, lit by the plane front F = 1e6 photons/s/cm^2 of the 1e5 K blackbody
+    in one grey bin (1.6e-18 cm^2, 6.3 eV), case A, optically thin, reaches
+    T_heat ~ 27000 K, the temperature the paper quotes for gas heated by the
+    source photons, by the equilibrium time 3 t_rec it shows."""
+    nH, NH, T, y = 1e-3, 1e60, 100.0, 1.0
+    dt = 0.1 * I.MYR_S
+    sig, eps = I.SIGMA_BB1E5_GREY, I.EPS_BB1E5_GREY_EV * I.EV_ERG
+    gam = sig * 1e6
+    p = I.default_params(dt=dt, isothermal=0, recomb_mode=I.CASE_A_NO_RR)
+    t_rec = PAPER["t_rec_myr"][0]
+    for _ in range(int(round(3 * t_rec / 0.1))):
+        y, T, _, _ = O.chem_one(p, [eps], [gam * y * NH * dt], nH, NH, y, T)
+    v, tol = PAPER["T_heat_source_K"]
+    assert y < 1e-3
+    assert abs(T / v - 1) < tol, T
