@@ -338,6 +338,32 @@ __device__ inline long long push_vip(Vip* vip, long long* cnt, int list, long lo
     return b;
 }
 
+// Adds x >= 0 (in units of an accumulator) to a three-part fixed-point
+// accumulator of 64-bit integers in units of 2^-16, 2^-48 and 2^-80: every step
+// of the split is exact, integer atomics make the sum independent of the order
+// of the adds, and it keeps every bit down to 2^-80 of the unit.  A part beyond
+// 2^46 units is refused and flagged (the accumulators could wrap).
+__device__ inline void fx_add3(unsigned long long* acc, double x, long long* cnt) {
+    if (!(x > 0.0)) return;
+    const double xs = x * 65536.0;  // 2^16
+    const double c = floor(xs);
+    if (!(c < 4503599627370496.0 * 16.0)) {  // 2^56 / 2^10 of headroom per step: 2^46 units
+        atomicOr(reinterpret_cast<unsigned long long*>(&cnt[kCntFlags]), static_cast<unsigned long long>(kFlagRecOverflow));
+        return;
+    }
+    const double r1 = (xs - c) * 4294967296.0;  // 2^32
+    const double m = floor(r1);
+    const long long f = __double2ll_rn((r1 - m) * 4294967296.0);
+    if (c > 0.0) atomicAdd(acc, static_cast<unsigned long long>(c));
+    if (m > 0.0) atomicAdd(acc + 1, static_cast<unsigned long long>(m));
+    if (f) atomicAdd(acc + 2, static_cast<unsigned long long>(f));
+}
+
+__device__ inline double fx_value3(const unsigned long long* acc) {
+    return static_cast<double>(acc[0]) * (1.0 / 65536.0) + static_cast<double>(acc[1]) * (1.0 / 281474976710656.0) +
+           static_cast<double>(acc[2]) * (1.0 / 1208925819614629174706176.0);
+}
+
 __device__ inline unsigned long long emis_key(long long m, int sub, int nu, int via, int k, int depth, int arr, int kidx) {
     return (static_cast<unsigned long long>(m) << 37) | (static_cast<unsigned long long>(sub) << 25) |
            (static_cast<unsigned long long>(nu) << 21) | (static_cast<unsigned long long>(via) << 20) |
@@ -475,8 +501,9 @@ struct VipArgs {
     const double* sigma;
     const double* wrc;
     const double* ecd;
-    double* xs;      // escaped per slot
-    double* rs;      // removed per slot
+    unsigned long long* xr_fx;  // [n_inst][nf][2][3] escaped, removed photons of transport
+                                // virtual particles this step, fixed point (fx_add3)
+    const double* Ufx;          // [n_inst] unit of those accumulators: the mean N_H
     double* exs;     // escaped per emission packet
     double* ers;     // removed per emission packet
     Rec* rec;
@@ -544,6 +571,18 @@ __device__ inline bool vip_draw_group(const VipArgs& a, uint32_t step, const Vip
     return found;
 }
 
+// A virtual particle's packet leaves the transport: escaped (what = 0, its
+// point lies outside the box) or removed (what = 1, no point found, or the
+// chain too deep).  Emission cones keep per-packet sums (k_emit_tally); transport
+// packets add to their instance's fixed-point accumulators.
+__device__ inline void vip_settle(const VipArgs& a, const Vip& q, int what, double n) {
+    if (q.xr_emis) {
+        (what ? a.ers : a.exs)[q.xr] += n;
+    } else {
+        fx_add3(a.xr_fx + 3 * ((static_cast<long long>(q.inst) * a.nf + q.nu) * 2 + what), n / a.Ufx[q.inst], a.cnt);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_vip_sample(VipArgs a) {
     const long long gid = blockIdx.x * 256LL + threadIdx.x;
     if (!a.hop0) {
@@ -579,17 +618,15 @@ __global__ __launch_bounds__(256) void k_vip_sample(VipArgs a) {
         bool inside = false;
         double xv[3] = {0.0, 0.0, 0.0};
         if (live && sub == 0) {
-            double* X = q.xr_emis ? a.exs : a.xs;
-            double* Rm = q.xr_emis ? a.ers : a.rs;
             const double* bx = a.box + 6 * q.inst;
             if (!found) {
-                Rm[q.xr] += q.N;
+                vip_settle(a, q, 1, q.N);
             } else {
                 xv[0] = q.x[0] + q.h * p[0];
                 xv[1] = q.x[1] + q.h * p[1];
                 xv[2] = q.x[2] + q.h * p[2];
                 if (xv[0] < bx[0] || xv[0] > bx[3] || xv[1] < bx[1] || xv[1] > bx[4] || xv[2] < bx[2] || xv[2] > bx[5])
-                    X[q.xr] += q.N;
+                    vip_settle(a, q, 0, q.N);
                 else
                     inside = true;
             }
@@ -636,8 +673,6 @@ __global__ __launch_bounds__(256) void k_vip_chain(VipArgs a) {
     for (long long v = gw; v < n; v += nw) {
         Vip q = a.deep[v];
         const double* bx = a.box + 6 * q.inst;
-        double* X = q.xr_emis ? a.exs : a.xs;
-        double* Rm = q.xr_emis ? a.ers : a.rs;
         const GridInfo g = a.grid[q.inst];
         double xv[3] = {a.deep_x[3 * v], a.deep_x[3 * v + 1], a.deep_x[3 * v + 2]};
         for (int depth = 1;; ++depth) {
@@ -667,14 +702,14 @@ __global__ __launch_bounds__(256) void k_vip_chain(VipArgs a) {
                     }
                 }
                 if (!found) {
-                    if (lane == 0) Rm[q.xr] += q.N;
+                    if (lane == 0) vip_settle(a, q, 1, q.N);
                     break;
                 }
                 xv[0] = q.x[0] + q.h * p0;
                 xv[1] = q.x[1] + q.h * p1;
                 xv[2] = q.x[2] + q.h * p2;
                 if (xv[0] < bx[0] || xv[0] > bx[3] || xv[1] < bx[1] || xv[1] > bx[4] || xv[2] < bx[2] || xv[2] > bx[5]) {
-                    if (lane == 0) X[q.xr] += q.N;
+                    if (lane == 0) vip_settle(a, q, 0, q.N);
                     break;
                 }
             }
@@ -777,7 +812,7 @@ __global__ __launch_bounds__(256) void k_vip_chain(VipArgs a) {
                 break;
             }
             if (depth >= a.max_depth) {
-                if (lane == 0) Rm[q.xr] += nrem;
+                if (lane == 0) vip_settle(a, q, 1, nrem);
                 break;
             }
             q.x[0] = xv[0];
@@ -862,6 +897,7 @@ struct HopArgs {
     int* hot_wr;
     double* A;
     double* P;
+    double* Fp;              // [N][nf] photons resting in the particle's bins (physical)
     const Rec* rec;
     const int* rec_next;
     int* head;               // record lists of this forward step, emptied once read
@@ -1599,6 +1635,13 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
         a.P[ia] = P0 + static_cast<double>(pg) * U;
         nbytes += 32;
     }
+    // photons resting in (j, nu) after this forward step, for the ledger's
+    // in-flight total (a tile's bins change only when it runs)
+    const double fg = group_sum(valid ? static_cast<double>(nn) * U : 0.0, nrc);
+    if (valid && r == 0) {
+        a.Fp[ia] = fg;
+        nbytes += 8;
+    }
     // next forward step: cone members and downstream reception cone.  The
     // lanes of a particle with an active packet stage its neighbour offsets
     // (with the receiver-sorted index of each edge) and its neighbours.
@@ -1937,52 +1980,37 @@ __global__ __launch_bounds__(256) void k_chem(ChemArgs a) {
 // ---------------------------------------------------------------- ledger --
 
 struct LedgerArgs {
-    int nf, nrc, G, rr_bin, rr_on, f32;
+    int nf, rr_bin, rr_on;
     long long n_chunks;
     const int* chunk_inst;
     const long long* chunk_lo;
     const long long* chunk_hi;
     const double* A;
     const double* nrr_prev;
-    double* xs;
-    double* rs;
-    const void* pk;        // current bins
-    const double* U;
-    double* partial;       // [n_chunks][nf][5]: E_rr, A, X, R, F
+    const double* Fp;      // [N][nf] photons resting in the bins (written by the forward steps)
+    double* partial;       // [n_chunks][nf][3]: E_rr, A, F
 };
 
 // Per chunk of one instance's particles: fixed-order partial sums.
 __global__ __launch_bounds__(256) void k_ledger_partial(LedgerArgs a) {
     const long long c = blockIdx.x;
     const long long lo = a.chunk_lo[c], hi = a.chunk_hi[c];
-    const int inst = a.chunk_inst[c];
-    const double U = a.f32 ? a.U[inst] : 1.0;
     __shared__ double red[256];
     for (int nu = 0; nu < a.nf; ++nu) {
-        double v[5] = {0, 0, 0, 0, 0};
+        double v[3] = {0, 0, 0};
         for (long long j = lo + threadIdx.x; j < hi; j += 256) {
             if (a.rr_on && nu == a.rr_bin) v[0] += a.nrr_prev[j];
             v[1] += a.A[j * a.nf + nu];
-            for (int q = 0; q < a.nrc; ++q) {
-                const long long b = j * a.G + static_cast<long long>(nu) * a.nrc + q;
-                v[2] += a.xs[b];
-                v[3] += a.rs[b];
-                a.xs[b] = 0.0;
-                a.rs[b] = 0.0;
-                if (a.f32)
-                    v[4] += static_cast<double>(static_cast<const Bin4<float>*>(a.pk)[b].n) * U;
-                else
-                    v[4] += static_cast<const Bin4<double>*>(a.pk)[b].n;
-            }
+            v[2] += a.Fp[j * a.nf + nu];
         }
-        for (int k = 0; k < 5; ++k) {
+        for (int k = 0; k < 3; ++k) {
             red[threadIdx.x] = v[k];
             __syncthreads();
             for (int off = 128; off > 0; off >>= 1) {
                 if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
                 __syncthreads();
             }
-            if (threadIdx.x == 0) a.partial[(c * a.nf + nu) * 5 + k] = red[0];
+            if (threadIdx.x == 0) a.partial[(c * a.nf + nu) * 3 + k] = red[0];
             __syncthreads();
         }
     }
@@ -2038,7 +2066,9 @@ __global__ __launch_bounds__(kEmTallyBlock) void k_emit_tally(EmitTallyArgs a) {
 struct LedgerFinalArgs {
     int n_inst, nf, f32;
     const long long* inst_chunk0;   // [n_inst+1] chunk ranges
-    const double* partial;
+    const double* partial;          // [n_chunks][nf][3]: E_rr, A, F
+    unsigned long long* xr_fx;      // [n_inst][nf][2][3] escaped, removed (fixed point), cleared here
+    const double* Ufx;              // [n_inst] their unit
     const double* E_src;            // [n_inst][nf] source photons per step
     const double* emt;              // [n_inst][nf][2] emission-cone escaped, removed (k_emit_tally)
     double* led;                    // [n_inst][nf][5] E, A, X, R, F (F current)
@@ -2051,10 +2081,15 @@ __global__ void k_ledger_final(LedgerFinalArgs a) {
     if (t >= a.n_inst * a.nf) return;
     const int k = t / a.nf, nu = t % a.nf;
     double v[5] = {0, 0, 0, 0, 0};
-    for (long long c = a.inst_chunk0[k]; c < a.inst_chunk0[k + 1]; ++c)
-        for (int q = 0; q < 5; ++q) v[q] += a.partial[(c * a.nf + nu) * 5 + q];
-    v[2] += a.emt[2 * t];
-    v[3] += a.emt[2 * t + 1];
+    for (long long c = a.inst_chunk0[k]; c < a.inst_chunk0[k + 1]; ++c) {
+        v[0] += a.partial[(c * a.nf + nu) * 3 + 0];
+        v[1] += a.partial[(c * a.nf + nu) * 3 + 1];
+        v[4] += a.partial[(c * a.nf + nu) * 3 + 2];
+    }
+    unsigned long long* fx = a.xr_fx + 6 * static_cast<long long>(t);
+    v[2] = fx_value3(fx) * a.Ufx[k] + a.emt[2 * t];
+    v[3] = fx_value3(fx + 3) * a.Ufx[k] + a.emt[2 * t + 1];
+    for (int q = 0; q < 6; ++q) fx[q] = 0ull;
     double* L = a.led + (static_cast<long long>(k) * a.nf + nu) * 5;
     L[0] += a.E_src[k * a.nf + nu] + v[0];
     L[1] += v[1];

@@ -126,7 +126,9 @@ struct rt_ctx {
     long long* dep = nullptr;  // fixed-point deposits of virtual particles
     double* nrr[2] = {nullptr, nullptr};
     int nrr_cur = 0;
-    double *xs = nullptr, *rs = nullptr;
+    double* Fp = nullptr;                 // [N][nf] photons resting in the bins
+    unsigned long long* xr_fx = nullptr;  // [n_inst][nf][2][3] escaped, removed (fixed point)
+    double* Ufx = nullptr;                // [n_inst] mean N_H: unit of xr_fx
     Vip* vip[2] = {nullptr, nullptr};
     Vip* deep = nullptr;        // chains that landed inside their box, and their points
     double* deep_x = nullptr;
@@ -335,6 +337,7 @@ rt_status launch_hop(rt_ctx* c, int hop) {
     a.hot_wr = c->hot[(hop + 1) & 1];
     a.A = c->A;
     a.P = c->P;
+    a.Fp = c->Fp;
     a.rec = c->rec;
     a.rec_next = c->rec_next;
     a.head = c->head[hop & 1];
@@ -393,8 +396,8 @@ rt_status launch_vip(rt_ctx* c, int hop) {
     a.sigma = c->sigma_d;
     a.wrc = c->rot + 9;
     a.ecd = c->ecd;
-    a.xs = c->xs;
-    a.rs = c->rs;
+    a.xr_fx = c->xr_fx;
+    a.Ufx = c->Ufx;
     a.exs = c->exs;
     a.ers = c->ers;
     a.rec = c->rec;
@@ -658,21 +661,15 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
     TRY(time_begin(c, 2));
     LedgerArgs la{};
     la.nf = c->nf;
-    la.nrc = c->nrc;
-    la.G = c->G;
     la.rr_bin = c->p.rr_bin;
     la.rr_on = c->rr_on ? 1 : 0;
-    la.f32 = c->f32 ? 1 : 0;
     la.n_chunks = c->n_chunks;
     la.chunk_inst = c->chunk_inst;
     la.chunk_lo = c->chunk_lo;
     la.chunk_hi = c->chunk_hi;
     la.A = c->A;
     la.nrr_prev = c->nrr[c->nrr_cur];
-    la.xs = c->xs;
-    la.rs = c->rs;
-    la.pk = c->pk;
-    la.U = c->U_d;
+    la.Fp = c->Fp;
     la.partial = c->partial;
     hipLaunchKernelGGL(k_ledger_partial, dim3(static_cast<unsigned>(c->n_chunks)), dim3(256), 0, c->stream, la);
     HIPCHK(c, hipGetLastError());
@@ -693,6 +690,8 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
     lf.f32 = c->f32 ? 1 : 0;
     lf.inst_chunk0 = c->inst_chunk0;
     lf.partial = c->partial;
+    lf.xr_fx = c->xr_fx;
+    lf.Ufx = c->Ufx;
     lf.E_src = c->E_src;
     lf.emt = c->emt;
     lf.led = c->led;
@@ -824,6 +823,7 @@ rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, cons
     c->U.assign(n_inst, 1.0);
     c->L.assign(n_inst, 1.0);
     std::vector<float> clf(n_inst);
+    std::vector<double> mean_NH(n_inst);
     std::vector<GridInfo> grid(n_inst);
     long long ncell = 0;
     for (int k = 0; k < n_inst; ++k) {
@@ -841,6 +841,7 @@ rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, cons
             vol *= La;
         }
         c->U[k] = c->f32 ? sum / static_cast<double>(n) : 1.0;
+        mean_NH[k] = sum / static_cast<double>(n);
         c->L[k] = Lmax;
         clf[k] = static_cast<float>(Lmax / (kCLight * p->dt));
         const double cs = std::cbrt(2.0 * vol / static_cast<double>(n));
@@ -977,10 +978,11 @@ rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, cons
     ITRY(alloc_n(c, &c->dep, 3 * N * c->nf));
     HIPCHK(c, hipMemsetAsync(c->dep, 0, sizeof(long long) * 3 * N * c->nf, c->stream));
     ITRY(fill_f64(c, c->P, N * c->nf, 0.0));
-    ITRY(alloc_n(c, &c->xs, c->B));
-    ITRY(alloc_n(c, &c->rs, c->B));
-    ITRY(fill_f64(c, c->xs, c->B, 0.0));
-    ITRY(fill_f64(c, c->rs, c->B, 0.0));
+    ITRY(alloc_n(c, &c->Fp, N * c->nf));
+    ITRY(fill_f64(c, c->Fp, N * c->nf, 0.0));
+    ITRY(alloc_n(c, &c->xr_fx, 6ll * n_inst * c->nf));
+    HIPCHK(c, hipMemsetAsync(c->xr_fx, 0, sizeof(unsigned long long) * 6 * n_inst * c->nf, c->stream));
+    ITRY(upload(c, &c->Ufx, mean_NH.data(), n_inst));
     c->vip_cap = p->vip_capacity > 0 ? p->vip_capacity : std::max<long long>(1 << 16, c->B / 8);
     c->rec_cap = p->record_capacity > 0 ? p->record_capacity : std::max<long long>(1 << 20, c->vip_cap * 4);
     if (c->rec_cap >= (1ll << 31)) c->rec_cap = (1ll << 31) - 1;
@@ -1013,7 +1015,7 @@ rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, cons
     ITRY(upload(c, &c->chunk_lo, clo.data(), c->n_chunks));
     ITRY(upload(c, &c->chunk_hi, chi.data(), c->n_chunks));
     ITRY(upload(c, &c->inst_chunk0, c0.data(), n_inst + 1));
-    ITRY(alloc_n(c, &c->partial, c->n_chunks * c->nf * 5));
+    ITRY(alloc_n(c, &c->partial, c->n_chunks * c->nf * 3));
     if (c->f32) {
         hipLaunchKernelGGL(k_kappa_init, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, c->xHI, c->nH, c->L_d,
                            c->inst_of, c->kappa);

@@ -30,3 +30,17 @@ def test_traffic_only_for_the_measured_kernel_sources(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.md"))
     assert bench.measured_traffic() is None
 
+
+
+def test_dense_model_bytes_per_slot_update():
+    """The dense forward-step model bench.py prices the roofline with gives the
+    bytes per slot update of the workloads' table: 69 / 111 B (64^3 RR and the
+    batch, FP32 / FP64) and 48 / 90 B (128^3 shadow set-up)."""
+    import bench
+    from paper_1311_0182_amd import inputs as I
+    for k, f32, want in ((2, True, 69), (2, False, 111), (4, True, 69), (4, False, 111), (3, True, 48),
+                         (3, False, 90)):
+        cfg = I.config(k)
+        total, per_slot, slots = bench.dense_bytes_per_hop(cfg, f32)
+        assert abs(per_slot - want) < 0.6, (k, f32, per_slot)
+        assert slots == cfg["pos"].shape[0] * cfg["params"]["n_rc"] * cfg["params"]["n_freq"]
