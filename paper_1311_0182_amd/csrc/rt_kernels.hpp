@@ -43,8 +43,13 @@ enum : int {
     // per-step tallies
     kCntBytes = 40,    // algorithmic bytes moved by forward steps (for the roofline)
     kCntTiles = 41,    // forward-step tiles processed
-    kCntN = 48
+    // marked tiles listed for a forward step, ping-pong by its parity: added to
+    // by k_tile_list, read by the forward step, cleared by the one before
+    kCntTileList = 48,  // [48], [49]
+    kCntN = 56
 };
+// Alignment of the tile-mark array (k_tile_list reads 4096 marks per workgroup).
+constexpr long long kTileListChunk = 4096;
 enum : long long { kFlagHopCap = 1, kFlagVipOverflow = 2, kFlagRecOverflow = 4, kFlagNonFinite = 8 };
 // units of the two fixed-point deposit accumulators, relative to the receiving particle's N_H
 constexpr double kDepositCoarse = 1.0 / 1073741824.0;         // 2^-30
@@ -891,6 +896,8 @@ struct HopArgs {
     const R2<R>* mvc_rd;
     const Inbox<DT>* in_rd;
     const int* hot_rd;
+    const int* tlist;        // tiles marked for this forward step (k_tile_list), hop > 0
+    long long ntiles;
     Bin4<R>* mv_wr;
     R2<R>* mvc_wr;
     Inbox<DT>* in_wr;
@@ -1174,40 +1181,11 @@ struct HopLds {
 // stays (clocks carried over by -dt), the recombination photons of the last
 // chemistry step (section 2.2) and the emission records.
 template <typename R, typename DT, typename S>
-__global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
-    const long long tile = xcd_block(blockIdx.x, gridDim.x);
-    // The launch-level flags, the stamp base and the tile's mark are loaded
-    // together (every address is valid) and tested once.  A launch past the
-    // last forward step of an RT step, or past the cap, runs no tile.
-    const long long c_done = a.cnt[kCntDone];
-    const long long c_act = a.cnt[kCntAct0 + kCntLine * a.act_rd];
-    const long long c_serial = a.cnt[kCntSerial];
-    const int hot = a.hot_rd[tile];
+__device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long long tile, const int stamp) {
     // the tile's range of receiver-sorted edges (it depends on the tile alone)
     const long long tj0 = tile * a.T;
     const long long tj1 = (tj0 + a.T < a.N) ? tj0 + a.T : a.N;
     const long long e_t0 = a.rev_off[tj0 < a.N ? tj0 : a.N], e_t1 = a.rev_off[tj1];
-    const int stamp = static_cast<int>(c_serial) + a.hop;  // of this forward step
-    // (bitwise operators: no short-circuit branches between the loads)
-    const bool idle = (a.hop0 == 0) & ((c_done != 0) | (c_act == 0));
-    const bool capped = (a.hop0 == 0) & !idle & (a.hop > a.max_hops);
-    const bool runs = !idle & !capped & ((a.hop0 != 0) | (hot == stamp));
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        if (idle) {
-            a.cnt[kCntDone] = 1;
-        } else if (capped) {
-            atomicOr(reinterpret_cast<unsigned long long*>(&a.cnt[kCntFlags]), static_cast<unsigned long long>(kFlagHopCap));
-        } else {
-            if (!a.hop0) {
-                a.cnt[kCntHops] += 1;
-                a.cnt[kCntHopsStep] += 1;
-            }
-            a.cnt[kCntRec] = 0;   // records of this step were all linked before launch
-            a.cnt[kCntDeep] = 0;  // and its virtual particles all handled
-        }
-    }
-    if (!runs) return;
-
     constexpr bool f32 = sizeof(R) == 4;
     constexpr unsigned long long rsz = sizeof(R);
     using V4 = typename std::conditional<f32, float4, double4>::type;
@@ -1848,6 +1826,103 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
     const unsigned long long nupd = __popcll(__ballot(departed));
     const unsigned long long wb = f32 ? wave_sum_u64_fast(nbytes) : wave_sum_u64(nbytes);
     if (lane < 3) a.part[3 * tile + lane] = tally + (lane == 0 ? nupd : (lane == 1 ? wb : 1ull));
+    // every LDS read of this tile has been consumed before the next tile stages
+    __builtin_amdgcn_s_waitcnt(0);
+    wave_sync();
+}
+
+// The forward-step kernel: one one-wavefront workgroup per tile slot.  Hop 0
+// of an RT step runs every tile; a later forward step runs only the tiles
+// k_tile_list found marked for it, packed into the first workgroups of the
+// launch, so the real work is dispatched first and the surplus workgroups
+// read one counter and exit.  Workgroups are dispatched round-robin over the 8
+// XCDs; xcd_block gives each XCD a contiguous share of the tiles (of the list,
+// which is sorted within each k_tile_list block), so that neighbouring
+// particles share that XCD's L2.  The launch-level flags are read once: a
+// launch past the last forward step of an RT step, or past the cap, runs no
+// tile.
+template <typename R, typename DT, typename S>
+__global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
+    const long long c_done = a.cnt[kCntDone];
+    const long long c_act = a.cnt[kCntAct0 + kCntLine * a.act_rd];
+    const long long c_serial = a.cnt[kCntSerial];
+    const long long c_list = a.cnt[kCntTileList + (a.hop & 1)];
+    const int stamp = static_cast<int>(c_serial) + a.hop;  // of this forward step
+    const bool idle = (a.hop0 == 0) & ((c_done != 0) | (c_act == 0));
+    const bool capped = (a.hop0 == 0) & !idle & (a.hop > a.max_hops);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (idle) {
+            a.cnt[kCntDone] = 1;
+        } else if (capped) {
+            atomicOr(reinterpret_cast<unsigned long long*>(&a.cnt[kCntFlags]), static_cast<unsigned long long>(kFlagHopCap));
+        } else {
+            if (!a.hop0) {
+                a.cnt[kCntHops] += 1;
+                a.cnt[kCntHopsStep] += 1;
+            }
+            a.cnt[kCntRec] = 0;   // records of this step were all linked before launch
+            a.cnt[kCntDeep] = 0;  // and its virtual particles all handled
+            // the next forward step's list count starts from zero
+            a.cnt[kCntTileList + ((a.hop + 1) & 1)] = 0;
+        }
+    }
+    const long long n = a.hop0 ? a.ntiles : (c_list < a.ntiles ? c_list : a.ntiles);
+    if (idle | capped | (static_cast<long long>(blockIdx.x) >= n)) return;
+    const long long e = xcd_block(blockIdx.x, n);
+    const long long tile = a.hop0 ? e : static_cast<long long>(a.tlist[e]);
+    hop_tile<R, DT, S>(a, tile, stamp);
+}
+
+// The tiles marked for forward step `hop` (tile mark == its stamp), listed for
+// the forward-step kernel: each workgroup takes 4096 marks (16 consecutive per
+// thread, read as four 16-byte vectors), a workgroup prefix sum orders its
+// marked tiles, and one atomic per workgroup places them.  Within a workgroup
+// the list is sorted; workgroups land in any order (the forward step's result
+// does not depend on the order it runs tiles in).
+__global__ __launch_bounds__(256) void k_tile_list(const int* __restrict__ hot, long long ntiles, int hop, int act_rd,
+                                                   int* __restrict__ tlist, long long* cnt) {
+    if (cnt[kCntDone] != 0 || cnt[kCntAct0 + kCntLine * act_rd] == 0) return;
+    const int stamp = static_cast<int>(cnt[kCntSerial]) + hop;
+    const long long t0 = blockIdx.x * kTileListChunk + threadIdx.x * 16ll;
+    const int4* h4 = reinterpret_cast<const int4*>(hot + t0);  // the mark array is padded to whole chunks
+    unsigned int bits = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int4 v = h4[q];
+        bits |= (v.x == stamp ? 1u : 0u) << (4 * q);
+        bits |= (v.y == stamp ? 1u : 0u) << (4 * q + 1);
+        bits |= (v.z == stamp ? 1u : 0u) << (4 * q + 2);
+        bits |= (v.w == stamp ? 1u : 0u) << (4 * q + 3);
+    }
+    if (t0 + 16 > ntiles) bits &= t0 >= ntiles ? 0u : ((1u << (ntiles - t0)) - 1u);
+    const int mine = __popc(bits);
+    // exclusive prefix over the workgroup, in thread (= tile) order
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int incl = mine;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += v;
+    }
+    __shared__ int wtot[4];
+    __shared__ long long base;
+    if (lane == 63) wtot[wv] = incl;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int w = 0; w < 4; ++w) {
+        before += w < wv ? wtot[w] : 0;
+        total += wtot[w];
+    }
+    if (threadIdx.x == 0)
+        base = total ? static_cast<long long>(atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[kCntTileList + (hop & 1)]),
+                                                        static_cast<unsigned long long>(total)))
+                     : 0ll;
+    __syncthreads();
+    long long at = base + before + incl - mine;
+    while (bits) {
+        const int b = __builtin_ctz(bits);
+        bits &= bits - 1u;
+        tlist[at++] = static_cast<int>(t0 + b);
+    }
 }
 
 // Adds the tiles' running tallies of an RT step to the counters and clears them.
@@ -1933,8 +2008,10 @@ __global__ __launch_bounds__(256) void k_chem(ChemArgs a) {
         const double heat_y = nhi0 > 0.0 ? esum / (nhi0 * a.dt) * nH : 0.0;
         const bool caseB = a.mode == 0;
         double t = 0.0;
+        // isothermal: T, hence every rate coefficient, is fixed over the step
+        Rates rt = rates_at(Tc);
         for (int n = 0; t < a.dt && n < 1000000; ++n) {
-            const Rates rt = rates_at(Tc);
+            if (!a.isothermal && n > 0) rt = rates_at(Tc);
             const double alpha = caseB ? rt.aB : rt.aA;
             const double x = 1.0 - y;
             const double ne = nH * x;

@@ -111,6 +111,8 @@ struct rt_ctx {
     void* mvc[2] = {nullptr, nullptr};
     void* inbox[2] = {nullptr, nullptr};
     int* hot[2] = {nullptr, nullptr};
+    int* tlist = nullptr;  // tiles marked for the next forward step
+    long long hot_len = 0; // entries of each mark array: ntiles padded to whole k_tile_list chunks
     unsigned long long* part = nullptr;  // per-tile tallies of a forward step
     unsigned int* rev_ik = nullptr;
     void* rev_v = nullptr;
@@ -331,6 +333,8 @@ rt_status launch_hop(rt_ctx* c, int hop) {
     a.mvc_rd = static_cast<const R2<R>*>(c->mvc[rd]);
     a.in_rd = static_cast<const Inbox<DT>*>(c->inbox[rd]);
     a.hot_rd = c->hot[hop & 1];
+    a.tlist = c->tlist;
+    a.ntiles = c->ntiles;
     a.mv_wr = static_cast<Bin4<R>*>(c->mv[wr]);
     a.mvc_wr = static_cast<R2<R>*>(c->mvc[wr]);
     a.in_wr = static_cast<Inbox<DT>*>(c->inbox[wr]);
@@ -349,6 +353,11 @@ rt_status launch_hop(rt_ctx* c, int hop) {
     a.act_rd = hop & 1;
     a.act_wr = (hop + 1) & 1;
     const size_t lds = HopLds<R, DT, S>::bytes(c->tileT, c->K);
+    if (hop > 0) {
+        hipLaunchKernelGGL(k_tile_list, dim3(static_cast<unsigned>(c->hot_len / kTileListChunk)), dim3(256), 0, c->stream,
+                           c->hot[hop & 1], c->ntiles, hop, hop & 1, c->tlist, c->cnt);
+        HIPCHK(c, hipGetLastError());
+    }
     hipLaunchKernelGGL((k_hop<R, DT, S>), dim3(static_cast<unsigned>(c->ntiles)), dim3(64), lds, c->stream, a);
     HIPCHK(c, hipGetLastError());
     return RT_OK;
@@ -431,6 +440,8 @@ __global__ void k_step_reset(long long* cnt, long long serial) {
         cnt[kCntHopsStep] = 0;
         cnt[kCntDone] = 0;
         cnt[kCntDeep] = 0;
+        cnt[kCntTileList] = 0;
+        cnt[kCntTileList + 1] = 0;
         cnt[kCntSteps] += 1;
     }
 }
@@ -527,7 +538,7 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
     if (c->serial + c->p.max_hops + 2 >= (1ll << 30)) {
         for (int b = 0; b < 2; ++b) {
             HIPCHK(c, hipMemsetAsync(c->inbox[b], 0xff, c->inbox_bytes, c->stream));
-            TRY(fill_i32(c, c->hot[b], c->ntiles, -1));
+            TRY(fill_i32(c, c->hot[b], c->hot_len, -1));
         }
         c->serial = 0;
     }
@@ -962,10 +973,12 @@ rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, cons
                          static_cast<size_t>(N * c->K);
         ITRY(dalloc(c, &c->inbox[b], c->inbox_bytes));
         HIPCHK(c, hipMemsetAsync(c->inbox[b], 0xff, c->inbox_bytes, c->stream));
-        ITRY(alloc_n(c, &c->hot[b], c->ntiles));
-        ITRY(fill_i32(c, c->hot[b], c->ntiles, -1));
+        c->hot_len = (c->ntiles + kTileListChunk - 1) / kTileListChunk * kTileListChunk;
+        ITRY(alloc_n(c, &c->hot[b], c->hot_len));
+        ITRY(fill_i32(c, c->hot[b], c->hot_len, -1));
         if (b == 0) {
             ITRY(alloc_n(c, &c->part, 3 * c->ntiles));
+            ITRY(alloc_n(c, &c->tlist, c->ntiles));
             HIPCHK(c, hipMemsetAsync(c->part, 0, sizeof(unsigned long long) * 3 * c->ntiles, c->stream));
         }
         ITRY(alloc_n(c, &c->nrr[b], N));
@@ -1597,7 +1610,7 @@ rt_status rt_set_state_blob(rt_ctx* c, const void* blob, size_t bytes) {
     c->last_hops = hd.last_hops;
     for (int b = 0; b < 2; ++b) {  // forget the marks of this context's own earlier steps
         HIPCHK(c, hipMemsetAsync(c->inbox[b], 0xff, c->inbox_bytes, c->stream));
-        TRY(fill_i32(c, c->hot[b], c->ntiles, -1));
+        TRY(fill_i32(c, c->hot[b], c->hot_len, -1));
     }
     if (c->f32) {
         hipLaunchKernelGGL(k_kappa_init, dim3(grid_for(c->N, 256)), dim3(256), 0, c->stream, c->N, c->xHI, c->nH,
