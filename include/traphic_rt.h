@@ -208,15 +208,18 @@ rt_status rt_get_pending_rr(rt_ctx *ctx, double *nrr);
 rt_status rt_set_timing(rt_ctx *ctx, int32_t on);
 rt_status rt_get_timing(rt_ctx *ctx, double *out, int32_t n);
 
-/* Shape of the forward-step workgroups: incoming edges staged per chunk and
- * (edge, packet) pairs gathered per round.  0: 256 edges / 128 pairs, 1: 128 /
- * 64, 2: 512 / 256 (FP64 gathers half as many pairs, at least 64).  All shapes
- * give identical results.  shape = -1 (the default) lets the library choose:
- * once an RT step needs at least 16 forward steps, the next 3 steps time the
- * shapes on alternate forward steps and the fastest is kept; shape = -2 times
- * them on the next 3 steps whatever their size.  RT_EINVAL for another value.  rt_get_hop_shape reports the shape in use, whether the
- * tuner chose it, and the tuner's mean ms per launch of each shape (3 doubles,
- * 0 if not timed); any pointer may be NULL. */
+/* Launch configuration of the forward steps: incoming edges staged per chunk
+ * and (edge, packet) pairs gathered per round, shape % 3 = 0: 256 edges / 128
+ * pairs, 1: 128 / 64, 2: 512 / 256 (FP64 gathers half as many pairs, at least
+ * 64); shapes 3..5 are 0..2 with up to four tiles (independent wavefronts)
+ * per workgroup, which cuts the workgroups a launch dispatches when few tiles
+ * have work.  All configurations give identical results.  shape = -1 (the
+ * default) lets the library choose: once an RT step needs at least 16 forward
+ * steps, the next 3 steps time the configurations on alternate forward steps
+ * and the fastest is kept; shape = -2 times them on the next 3 steps whatever
+ * their size.  RT_EINVAL for another value.  rt_get_hop_shape reports the
+ * configuration in use, whether the tuner chose it, and the tuner's mean ms
+ * per launch of each (6 doubles, 0 if not timed); any pointer may be NULL. */
 rt_status rt_set_hop_shape(rt_ctx *ctx, int32_t shape);
 rt_status rt_get_hop_shape(rt_ctx *ctx, int32_t *shape, int32_t *tuned, double *ms_per_launch);
 

@@ -898,6 +898,8 @@ struct HopArgs {
     const int* hot_rd;
     const int* tlist;        // tiles marked for this forward step (k_tile_list), hop > 0
     long long ntiles;
+    int wpb;                 // wavefronts (tiles) per workgroup
+    unsigned int lds_wave;   // LDS bytes of each wavefront
     Bin4<R>* mv_wr;
     R2<R>* mvc_wr;
     Inbox<DT>* in_wr;
@@ -1128,7 +1130,10 @@ struct HopShape {
 using HopShape0 = HopShape<256, 128>;
 using HopShape1 = HopShape<128, 64>;
 using HopShape2 = HopShape<512, 256>;
-constexpr int kHopShapes = 3;
+constexpr int kHopShapeKinds = 3;
+// Launch configurations the tuner chooses among: shape c % 3, and c / 3 == 1
+// packs up to four tiles (independent wavefronts) per workgroup.
+constexpr int kHopShapes = 2 * kHopShapeKinds;
 
 template <typename R, typename DT, typename S = HopShape0>
 struct HopLds {
@@ -1181,7 +1186,8 @@ struct HopLds {
 // stays (clocks carried over by -dt), the recombination photons of the last
 // chemistry step (section 2.2) and the emission records.
 template <typename R, typename DT, typename S>
-__device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long long tile, const int stamp) {
+__device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long long tile, const int stamp,
+                                         const unsigned int tidx, unsigned char* __restrict__ lds) {
     // the tile's range of receiver-sorted edges (it depends on the tile alone)
     const long long tj0 = tile * a.T;
     const long long tj1 = (tj0 + a.T < a.N) ? tj0 + a.T : a.N;
@@ -1191,20 +1197,19 @@ __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long lon
     using V4 = typename std::conditional<f32, float4, double4>::type;
     using L = HopLds<R, DT, S>;
     constexpr int kP = L::kPairs;
-    extern __shared__ __align__(32) unsigned char lds[];
 
     const int G = a.G, nrc = a.nrc, K = a.K, T = a.T;
     const int lgG = __builtin_ctz(G), lgN = __builtin_ctz(nrc);  // both powers of two
     const long long j0 = tile * T;
-    const int jl = threadIdx.x >> lgG;
-    const int o = threadIdx.x & (G - 1);
+    const int jl = tidx >> lgG;
+    const int o = tidx & (G - 1);
     const long long j = j0 + jl;
     const bool valid = jl < T && j < a.N;
     const long long s = j * G + o;
     const int nu = o >> lgN;
     const int r = o & (nrc - 1);
     const long long jend = (j0 + T < a.N) ? j0 + T : a.N;
-    const int lane = threadIdx.x;
+    const int lane = tidx;
     // Gather staging: a chunk of the tile's incoming edges, inbox words and
     // edge words straight from memory into LDS (no registers held, all loads in
     // flight together); lanes past the end load a copy of the last edge.  The
@@ -1417,7 +1422,7 @@ __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long lon
                             const unsigned int u = static_cast<unsigned int>(__builtin_ctzll(h));
                             h &= h - 1ull;
                             if (q >= base && q < base + kP)
-                                pdesc[q - base] = ((tb + u) << 14) | (static_cast<unsigned int>(r) << 8) | threadIdx.x;
+                                pdesc[q - base] = ((tb + u) << 14) | (static_cast<unsigned int>(r) << 8) | tidx;
                             ++q;
                         }
                     }
@@ -1426,7 +1431,7 @@ __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long lon
                     int q = off0;
                     each_pair([&](int t, int pp) {
                         if (q >= base && q < base + kP)
-                            pdesc[q - base] = (static_cast<unsigned int>(t) << 14) | (static_cast<unsigned int>(pp) << 8) | threadIdx.x;
+                            pdesc[q - base] = (static_cast<unsigned int>(t) << 14) | (static_cast<unsigned int>(pp) << 8) | tidx;
                         ++q;
                     });
                 }
@@ -1627,7 +1632,7 @@ __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long lon
     wave_sync();  // the gather's LDS is free again
     const bool tile_act = __ballot(act) != 0;
     if (valid && o == 0 && hd >= 0) a.head[j] = -1;  // every lane of j has read its records
-    if (tile_act && threadIdx.x == 0) a.hot_wr[tile] = stamp + 1;  // its leaving packets empty their bins
+    if (tile_act && tidx == 0) a.hot_wr[tile] = stamp + 1;  // its leaving packets empty their bins
     const int gbase = lane & ~(G - 1);
     const unsigned long long gmaskG = G >= 64 ? ~0ull : ((1ull << G) - 1ull);
     const unsigned long long wact = __ballot(act);
@@ -1831,18 +1836,20 @@ __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long lon
     wave_sync();
 }
 
-// The forward-step kernel: one one-wavefront workgroup per tile slot.  Hop 0
-// of an RT step runs every tile; a later forward step runs only the tiles
-// k_tile_list found marked for it, packed into the first workgroups of the
-// launch, so the real work is dispatched first and the surplus workgroups
-// read one counter and exit.  Workgroups are dispatched round-robin over the 8
-// XCDs; xcd_block gives each XCD a contiguous share of the tiles (of the list,
-// which is sorted within each k_tile_list block), so that neighbouring
-// particles share that XCD's L2.  The launch-level flags are read once: a
-// launch past the last forward step of an RT step, or past the cap, runs no
-// tile.
+// The forward-step kernel: workgroups of a.wpb independent wavefronts, one
+// tile each, each wavefront with its own share of the LDS.  Hop 0 of an RT
+// step runs every tile; a later forward step runs only the tiles k_tile_list
+// found marked for it, packed into the first workgroups of the launch, so the
+// real work is dispatched first and the surplus workgroups read one counter
+// and exit (several tiles per workgroup cut their number).  Workgroups are
+// dispatched round-robin over the 8 XCDs; xcd_block gives each XCD a
+// contiguous share of the tiles (of the list, sorted within each k_tile_list
+// block), so that neighbouring particles share that XCD's L2.  The
+// launch-level flags are read once: a launch past the last forward step of an
+// RT step, or past the cap, runs no tile.
 template <typename R, typename DT, typename S>
-__global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
+__global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
+    extern __shared__ __align__(32) unsigned char lds_all[];
     const long long c_done = a.cnt[kCntDone];
     const long long c_act = a.cnt[kCntAct0 + kCntLine * a.act_rd];
     const long long c_serial = a.cnt[kCntSerial];
@@ -1867,10 +1874,13 @@ __global__ __launch_bounds__(64) void k_hop(HopArgs<R, DT> a) {
         }
     }
     const long long n = a.hop0 ? a.ntiles : (c_list < a.ntiles ? c_list : a.ntiles);
-    if (idle | capped | (static_cast<long long>(blockIdx.x) >= n)) return;
-    const long long e = xcd_block(blockIdx.x, n);
+    const long long nb = (n + a.wpb - 1) / a.wpb;  // workgroups with tiles
+    if (idle | capped | (static_cast<long long>(blockIdx.x) >= nb)) return;
+    const unsigned int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
+    const long long e = xcd_block(blockIdx.x, nb) * a.wpb + wv;
+    if (e >= n) return;
     const long long tile = a.hop0 ? e : static_cast<long long>(a.tlist[e]);
-    hop_tile<R, DT, S>(a, tile, stamp);
+    hop_tile<R, DT, S>(a, tile, stamp, threadIdx.x & 63u, lds_all + static_cast<size_t>(wv) * a.lds_wave);
 }
 
 // The tiles marked for forward step `hop` (tile mark == its stamp), listed for

@@ -157,8 +157,8 @@ struct rt_ctx {
     int hop_shape = 0;
     int tune_mode = -1;        // -1 automatic, -2 tune now, 0..kHopShapes-1 fixed by the caller
     int tune_steps_left = 3;   // RT steps that time the shapes (alternating per forward step)
-    double tune_ms[kHopShapes] = {0, 0, 0};
-    long long tune_n[kHopShapes] = {0, 0, 0};
+    double tune_ms[kHopShapes] = {};
+    long long tune_n[kHopShapes] = {};
     bool tuned = false;
     bool tuning_now = false;   // this RT step times the shapes
     bool graphs_ok = true;
@@ -282,7 +282,7 @@ void direction_set(int n, std::vector<double>& u) {
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 template <typename R, typename DT, typename S>
-rt_status launch_hop(rt_ctx* c, int hop) {
+rt_status launch_hop(rt_ctx* c, int hop, bool pack) {
     HopArgs<R, DT> a{};
     a.N = c->N;
     a.G = c->G;
@@ -352,30 +352,37 @@ rt_status launch_hop(rt_ctx* c, int hop) {
     a.part = c->part;
     a.act_rd = hop & 1;
     a.act_wr = (hop + 1) & 1;
-    const size_t lds = HopLds<R, DT, S>::bytes(c->tileT, c->K);
+    // up to four tiles (wavefronts) per workgroup, as many as 64 KiB of LDS hold
+    const size_t lds_wave = (HopLds<R, DT, S>::bytes(c->tileT, c->K) + 31) / 32 * 32;
+    a.wpb = pack ? static_cast<int>(std::max<size_t>(1, std::min<size_t>(4, 65536 / lds_wave))) : 1;
+    a.lds_wave = static_cast<unsigned int>(lds_wave);
+    const size_t lds = lds_wave * a.wpb;
+    const long long n_wg = (c->ntiles + a.wpb - 1) / a.wpb;
     if (hop > 0) {
         hipLaunchKernelGGL(k_tile_list, dim3(static_cast<unsigned>(c->hot_len / kTileListChunk)), dim3(256), 0, c->stream,
                            c->hot[hop & 1], c->ntiles, hop, hop & 1, c->tlist, c->cnt);
         HIPCHK(c, hipGetLastError());
     }
-    hipLaunchKernelGGL((k_hop<R, DT, S>), dim3(static_cast<unsigned>(c->ntiles)), dim3(64), lds, c->stream, a);
+    hipLaunchKernelGGL((k_hop<R, DT, S>), dim3(static_cast<unsigned>(n_wg)), dim3(64 * a.wpb), lds, c->stream, a);
     HIPCHK(c, hipGetLastError());
     return RT_OK;
 }
 
 
 template <typename S>
-rt_status launch_hop_shape(rt_ctx* c, int hop) {
-    if (c->f32) return c->dl64 ? launch_hop<float, unsigned long long, S>(c, hop) : launch_hop<float, unsigned int, S>(c, hop);
-    return c->dl64 ? launch_hop<double, unsigned long long, S>(c, hop) : launch_hop<double, unsigned int, S>(c, hop);
+rt_status launch_hop_shape(rt_ctx* c, int hop, bool pack) {
+    if (c->f32) return c->dl64 ? launch_hop<float, unsigned long long, S>(c, hop, pack) : launch_hop<float, unsigned int, S>(c, hop, pack);
+    return c->dl64 ? launch_hop<double, unsigned long long, S>(c, hop, pack) : launch_hop<double, unsigned int, S>(c, hop, pack);
 }
 
 // shape: the tuned one, or (during tuning) the one this forward step times
 rt_status launch_hop_any(rt_ctx* c, int hop, int shape = -1) {
     if (shape < 0) shape = c->hop_shape;
-    if (shape == 1) return launch_hop_shape<HopShape1>(c, hop);
-    if (shape == 2) return launch_hop_shape<HopShape2>(c, hop);
-    return launch_hop_shape<HopShape0>(c, hop);
+    const bool pack = shape >= kHopShapeKinds;
+    const int kind = shape % kHopShapeKinds;
+    if (kind == 1) return launch_hop_shape<HopShape1>(c, hop, pack);
+    if (kind == 2) return launch_hop_shape<HopShape2>(c, hop, pack);
+    return launch_hop_shape<HopShape0>(c, hop, pack);
 }
 
 rt_status launch_vip(rt_ctx* c, int hop) {

@@ -254,7 +254,7 @@ class Context:
 
     def hop_shape(self):
         sh, tu = C.c_int32(0), C.c_int32(0)
-        ms = np.zeros(3)
+        ms = np.zeros(6)
         self._check(load().rt_get_hop_shape(self.h, C.byref(sh), C.byref(tu), _p(ms, C.c_double)))
         return dict(shape=int(sh.value), tuned=bool(tu.value), ms_per_launch=[float(x) for x in ms])
 

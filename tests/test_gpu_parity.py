@@ -189,7 +189,7 @@ def test_hop_shapes_identical_and_tuner():
     RT = _rt()
     for prec in ("fp64", "fp32"):
         blobs = []
-        for shape in (0, 1, 2, -2):
+        for shape in (0, 1, 2, 3, 4, 5, -2):
             ctx = RT.Context(cfg, precision=prec)
             ctx.set_hop_shape(shape)
             ctx.step(12)
@@ -199,10 +199,10 @@ def test_hop_shapes_identical_and_tuner():
             if shape >= 0:
                 assert info["shape"] == shape and not info["tuned"]
             else:
-                assert info["tuned"] and 0 <= info["shape"] <= 2 and all(m > 0 for m in info["ms_per_launch"])
+                assert info["tuned"] and 0 <= info["shape"] <= 5 and all(m > 0 for m in info["ms_per_launch"])
         assert all(b == blobs[0] for b in blobs[1:]), prec
     with pytest.raises(RT.RTError):
-        RT.Context(cfg).set_hop_shape(3)
+        RT.Context(cfg).set_hop_shape(6)
 
 
 def test_checkpoint_restore_bitwise():
