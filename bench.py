@@ -85,10 +85,15 @@ def dense_bytes_per_hop(cfg, fp32):
     return total, total / slots, slots
 
 
+FORCE_SHAPE = -1   # --hop-shape
+
+
 def run_timed(cfg, precision, W, K, timing=False, shape=None):
     import torch
     from paper_1311_0182_amd import traphic_rt as RT
     ctx = RT.Context(cfg, precision=precision)
+    if FORCE_SHAPE >= 0:
+        shape = FORCE_SHAPE
     if shape is not None:
         ctx.set_hop_shape(shape)
     if W:
@@ -112,6 +117,9 @@ def side_by_side(cfg, steps):
     import numpy as np
     from paper_1311_0182_amd import traphic_rt as RT
     a, b = RT.Context(cfg, precision="fp32"), RT.Context(cfg, precision="fp64")
+    if FORCE_SHAPE >= 0:
+        a.set_hop_shape(FORCE_SHAPE)
+        b.set_hop_shape(FORCE_SHAPE)
     worst, at = 0.0, 0
     res32 = res64 = 0.0
     for k in range(steps):
@@ -230,6 +238,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--headline-only", action="store_true", help="skip the extra rows")
+    ap.add_argument("--hop-shape", type=int, default=-1,
+                    help="forward-step launch configuration 0..5 for every run (-1: the library's tuner picks)")
+    ap.add_argument("--only", choices=["stromgren64_rr", "shadow128"], default=None,
+                    help="run one extra row alone and print it (for profiling); no headline line")
     ap.add_argument("--c3-warmup", type=int, default=2)
     ap.add_argument("--c3-steps", type=int, default=3)
     ap.add_argument("--calib-copy-mb", type=float, default=0.0,
@@ -256,6 +268,15 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     K, W = args.steps, args.warmup
+    global FORCE_SHAPE
+    FORCE_SHAPE = args.hop_shape
+    if args.only == "stromgren64_rr":
+        print(json.dumps({"stromgren64_rr": pair_row(I.config(2), W, K, "64^3 Stromgren with RR")}), flush=True)
+        return
+    if args.only == "shadow128":
+        print(json.dumps({"shadow128": pair_row(I.config(3), args.c3_warmup, args.c3_steps, "128^3 shadow set-up")}),
+              flush=True)
+        return
     cfg = I.config(4)
     n_inst = len(cfg["inst_off"]) - 1
     import numpy as np

@@ -89,6 +89,13 @@ __device__ inline long long xcd_block(long long b, long long nb) {
     return (x < rem) ? x * (q + 1) + l : rem * (q + 1) + (x - rem) * q + l;
 }
 
+// xcd_block for 32-bit counts (shifts and masks only).
+__device__ inline unsigned int xcd_block32(unsigned int b, unsigned int nb) {
+    const unsigned int q = nb >> 3, rem = nb & 7u;
+    const unsigned int x = b & 7u, l = b >> 3;
+    return (x < rem) ? x * (q + 1u) + l : rem * (q + 1u) + (x - rem) * q + l;
+}
+
 // ------------------------------------------------------------------ set-up --
 
 __global__ void k_fill_i32(int* p, long long n, int v) {
@@ -896,9 +903,10 @@ struct HopArgs {
     const R2<R>* mvc_rd;
     const Inbox<DT>* in_rd;
     const int* hot_rd;
-    const int* tlist;        // tiles marked for this forward step (k_tile_list), hop > 0
+    const int4* tlist;       // tiles marked for this forward step (k_tile_list), hop > 0: {tile,
+                             // first and end receiver-sorted edge of its particles, 0}
     long long ntiles;
-    int wpb;                 // wavefronts (tiles) per workgroup
+    int lg_wpb;              // log2 of the wavefronts (tiles) per workgroup: 0, 1 or 2
     unsigned int lds_wave;   // LDS bytes of each wavefront
     Bin4<R>* mv_wr;
     R2<R>* mvc_wr;
@@ -1186,12 +1194,10 @@ struct HopLds {
 // stays (clocks carried over by -dt), the recombination photons of the last
 // chemistry step (section 2.2) and the emission records.
 template <typename R, typename DT, typename S>
-__device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long long tile, const int stamp,
-                                         const unsigned int tidx, unsigned char* __restrict__ lds) {
-    // the tile's range of receiver-sorted edges (it depends on the tile alone)
-    const long long tj0 = tile * a.T;
-    const long long tj1 = (tj0 + a.T < a.N) ? tj0 + a.T : a.N;
-    const long long e_t0 = a.rev_off[tj0 < a.N ? tj0 : a.N], e_t1 = a.rev_off[tj1];
+__device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long long tile, const long long e_t0,
+                                         const long long e_t1, const int stamp, const unsigned int tidx,
+                                         unsigned char* __restrict__ lds) {
+    // e_t0 .. e_t1: the tile's range of receiver-sorted edges
     constexpr bool f32 = sizeof(R) == 4;
     constexpr unsigned long long rsz = sizeof(R);
     using V4 = typename std::conditional<f32, float4, double4>::type;
@@ -1873,24 +1879,39 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
             a.cnt[kCntTileList + ((a.hop + 1) & 1)] = 0;
         }
     }
-    const long long n = a.hop0 ? a.ntiles : (c_list < a.ntiles ? c_list : a.ntiles);
-    const long long nb = (n + a.wpb - 1) / a.wpb;  // workgroups with tiles
-    if (idle | capped | (static_cast<long long>(blockIdx.x) >= nb)) return;
+    // 32-bit arithmetic and shifts only: every workgroup, also the surplus
+    // ones, runs this before it exits
+    const unsigned int n = static_cast<unsigned int>(a.hop0 ? a.ntiles : (c_list < a.ntiles ? c_list : a.ntiles));
+    const unsigned int nb = (n + (1u << a.lg_wpb) - 1u) >> a.lg_wpb;  // workgroups with tiles
+    if (idle | capped | (blockIdx.x >= nb)) return;
     const unsigned int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
-    const long long e = xcd_block(blockIdx.x, nb) * a.wpb + wv;
+    const unsigned int e = (xcd_block32(blockIdx.x, nb) << a.lg_wpb) + wv;
     if (e >= n) return;
-    const long long tile = a.hop0 ? e : static_cast<long long>(a.tlist[e]);
-    hop_tile<R, DT, S>(a, tile, stamp, threadIdx.x & 63u, lds_all + static_cast<size_t>(wv) * a.lds_wave);
+    long long tile, e_t0, e_t1;
+    if (a.hop0) {
+        tile = e;
+        const long long tj0 = tile * a.T;
+        const long long tj1 = (tj0 + a.T < a.N) ? tj0 + a.T : a.N;
+        e_t0 = a.rev_off[tj0];
+        e_t1 = a.rev_off[tj1];
+    } else {
+        const int4 w = a.tlist[e];  // the tile and its edge range in one load
+        tile = w.x;
+        e_t0 = static_cast<unsigned int>(w.y);
+        e_t1 = static_cast<unsigned int>(w.z);
+    }
+    hop_tile<R, DT, S>(a, tile, e_t0, e_t1, stamp, threadIdx.x & 63u, lds_all + static_cast<size_t>(wv) * a.lds_wave);
 }
 
-// The tiles marked for forward step `hop` (tile mark == its stamp), listed for
-// the forward-step kernel: each workgroup takes 4096 marks (16 consecutive per
+// The tiles marked for forward step `hop` (tile mark == its stamp), listed with
+// their edge ranges for the forward-step kernel: each workgroup takes 4096 marks (16 consecutive per
 // thread, read as four 16-byte vectors), a workgroup prefix sum orders its
 // marked tiles, and one atomic per workgroup places them.  Within a workgroup
 // the list is sorted; workgroups land in any order (the forward step's result
 // does not depend on the order it runs tiles in).
 __global__ __launch_bounds__(256) void k_tile_list(const int* __restrict__ hot, long long ntiles, int hop, int act_rd,
-                                                   int* __restrict__ tlist, long long* cnt) {
+                                                   const int* __restrict__ rev_off, long long N, int T,
+                                                   int4* __restrict__ tlist, long long* cnt) {
     if (cnt[kCntDone] != 0 || cnt[kCntAct0 + kCntLine * act_rd] == 0) return;
     const int stamp = static_cast<int>(cnt[kCntSerial]) + hop;
     const long long t0 = blockIdx.x * kTileListChunk + threadIdx.x * 16ll;
@@ -1931,7 +1952,8 @@ __global__ __launch_bounds__(256) void k_tile_list(const int* __restrict__ hot, 
     while (bits) {
         const int b = __builtin_ctz(bits);
         bits &= bits - 1u;
-        tlist[at++] = static_cast<int>(t0 + b);
+        const long long t = t0 + b, j0 = t * T, j1 = (j0 + T < N) ? j0 + T : N;
+        tlist[at++] = make_int4(static_cast<int>(t), rev_off[j0], rev_off[j1], 0);
     }
 }
 

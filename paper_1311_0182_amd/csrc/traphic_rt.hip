@@ -111,7 +111,7 @@ struct rt_ctx {
     void* mvc[2] = {nullptr, nullptr};
     void* inbox[2] = {nullptr, nullptr};
     int* hot[2] = {nullptr, nullptr};
-    int* tlist = nullptr;  // tiles marked for the next forward step
+    int4* tlist = nullptr;  // tiles marked for the next forward step, with their edge ranges
     long long hot_len = 0; // entries of each mark array: ntiles padded to whole k_tile_list chunks
     unsigned long long* part = nullptr;  // per-tile tallies of a forward step
     unsigned int* rev_ik = nullptr;
@@ -352,18 +352,15 @@ rt_status launch_hop(rt_ctx* c, int hop, bool pack) {
     a.part = c->part;
     a.act_rd = hop & 1;
     a.act_wr = (hop + 1) & 1;
-    // up to four tiles (wavefronts) per workgroup, as many as 64 KiB of LDS hold
+    // 1, 2 or 4 tiles (wavefronts) per workgroup, as many as 64 KiB of LDS hold
     const size_t lds_wave = (HopLds<R, DT, S>::bytes(c->tileT, c->K) + 31) / 32 * 32;
-    a.wpb = pack ? static_cast<int>(std::max<size_t>(1, std::min<size_t>(4, 65536 / lds_wave))) : 1;
+    a.lg_wpb = 0;
+    while (pack && a.lg_wpb < 2 && (lds_wave << (a.lg_wpb + 1)) <= 65536) ++a.lg_wpb;
+    const int wpb = 1 << a.lg_wpb;
     a.lds_wave = static_cast<unsigned int>(lds_wave);
-    const size_t lds = lds_wave * a.wpb;
-    const long long n_wg = (c->ntiles + a.wpb - 1) / a.wpb;
-    if (hop > 0) {
-        hipLaunchKernelGGL(k_tile_list, dim3(static_cast<unsigned>(c->hot_len / kTileListChunk)), dim3(256), 0, c->stream,
-                           c->hot[hop & 1], c->ntiles, hop, hop & 1, c->tlist, c->cnt);
-        HIPCHK(c, hipGetLastError());
-    }
-    hipLaunchKernelGGL((k_hop<R, DT, S>), dim3(static_cast<unsigned>(n_wg)), dim3(64 * a.wpb), lds, c->stream, a);
+    const size_t lds = lds_wave * wpb;
+    const long long n_wg = (c->ntiles + wpb - 1) / wpb;
+    hipLaunchKernelGGL((k_hop<R, DT, S>), dim3(static_cast<unsigned>(n_wg)), dim3(64 * wpb), lds, c->stream, a);
     HIPCHK(c, hipGetLastError());
     return RT_OK;
 }
@@ -433,6 +430,13 @@ rt_status launch_vip(rt_ctx* c, int hop) {
     hipLaunchKernelGGL(k_vip_sample, dim3(nsb), dim3(256), 0, c->stream, a);
     hipLaunchKernelGGL(k_vip_chain, dim3(1024), dim3(256), 0, c->stream, a);
     HIPCHK(c, hipGetLastError());
+    // the tiles marked for this forward step (by the previous one and by the
+    // virtual-particle chains just launched); hop 0 runs every tile
+    if (hop > 0) {
+        hipLaunchKernelGGL(k_tile_list, dim3(static_cast<unsigned>(c->hot_len / kTileListChunk)), dim3(256), 0, c->stream,
+                           c->hot[hop & 1], c->ntiles, hop, hop & 1, c->rev_off, c->N, c->tileT, c->tlist, c->cnt);
+        HIPCHK(c, hipGetLastError());
+    }
     return RT_OK;
 }
 
