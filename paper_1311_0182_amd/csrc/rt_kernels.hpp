@@ -371,6 +371,46 @@ __device__ inline void fx_add3(unsigned long long* acc, double x, long long* cnt
     if (f) atomicAdd(acc + 2, static_cast<unsigned long long>(f));
 }
 
+// fx_add3 for a whole wavefront (every lane calls it; lanes with on = false
+// add nothing): the lanes' parts are summed per key across the wavefront
+// first (integers: exact, in any order), so each distinct key costs one set
+// of atomics instead of one per lane.  key selects acc + 3 key.
+__device__ inline void fx_add3_wave(unsigned long long* acc, long long key, double x, bool on, long long* cnt) {
+    unsigned long long c = 0, m = 0, f = 0;
+    if (on && x > 0.0) {
+        const double xs = x * 65536.0;  // 2^16
+        const double cd = floor(xs);
+        if (!(cd < 4503599627370496.0 * 16.0)) {
+            atomicOr(reinterpret_cast<unsigned long long*>(&cnt[kCntFlags]), static_cast<unsigned long long>(kFlagRecOverflow));
+        } else {
+            const double r1 = (xs - cd) * 4294967296.0;  // 2^32
+            const double md = floor(r1);
+            c = static_cast<unsigned long long>(cd);
+            m = static_cast<unsigned long long>(md);
+            f = static_cast<unsigned long long>(__double2ll_rn((r1 - md) * 4294967296.0));
+        }
+    }
+    const int lane = static_cast<int>(threadIdx.x & 63u);
+    unsigned long long pend = __ballot((c | m | f) != 0ull);
+    while (pend) {
+        const int ld = __ffsll(static_cast<long long>(pend)) - 1;
+        const long long k = __shfl(key, ld, 64);
+        const bool mine = ((pend >> lane) & 1ull) && key == k;
+        unsigned long long sc = mine ? c : 0ull, sm = mine ? m : 0ull, sf = mine ? f : 0ull;
+        for (int off = 32; off > 0; off >>= 1) {
+            sc += __shfl_xor(sc, off, 64);
+            sm += __shfl_xor(sm, off, 64);
+            sf += __shfl_xor(sf, off, 64);
+        }
+        if (lane == ld) {
+            if (sc) atomicAdd(acc + 3 * k, sc);
+            if (sm) atomicAdd(acc + 3 * k + 1, sm);
+            if (sf) atomicAdd(acc + 3 * k + 2, sf);
+        }
+        pend &= ~__ballot(mine);
+    }
+}
+
 __device__ inline double fx_value3(const unsigned long long* acc) {
     return static_cast<double>(acc[0]) * (1.0 / 65536.0) + static_cast<double>(acc[1]) * (1.0 / 281474976710656.0) +
            static_cast<double>(acc[2]) * (1.0 / 1208925819614629174706176.0);
@@ -629,20 +669,26 @@ __global__ __launch_bounds__(256) void k_vip_sample(VipArgs a) {
         const bool found = vip_draw_group(a, step, q, live, 1, sub, gshift, p);
         bool inside = false;
         double xv[3] = {0.0, 0.0, 0.0};
+        int what = -1;  // 0 escaped, 1 removed (no point found)
         if (live && sub == 0) {
             const double* bx = a.box + 6 * q.inst;
             if (!found) {
-                vip_settle(a, q, 1, q.N);
+                what = 1;
             } else {
                 xv[0] = q.x[0] + q.h * p[0];
                 xv[1] = q.x[1] + q.h * p[1];
                 xv[2] = q.x[2] + q.h * p[2];
                 if (xv[0] < bx[0] || xv[0] > bx[3] || xv[1] < bx[1] || xv[1] > bx[4] || xv[2] < bx[2] || xv[2] > bx[5])
-                    vip_settle(a, q, 0, q.N);
+                    what = 0;
                 else
                     inside = true;
             }
+            if (what >= 0 && q.xr_emis) (what ? a.ers : a.exs)[q.xr] += q.N;
         }
+        // transport packets: one set of atomics per (instance, bin, kind) in the wavefront
+        const bool tr = what >= 0 && !q.xr_emis;
+        fx_add3_wave(a.xr_fx, tr ? (static_cast<long long>(q.inst) * a.nf + q.nu) * 2 + what : 0, tr ? q.N / a.Ufx[q.inst] : 0.0,
+                     tr, a.cnt);
         // append the inside ones, one atomic per wavefront
         const unsigned long long b = __ballot(inside);
         if (b) {
@@ -1776,6 +1822,16 @@ __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long lon
             }
         }
     }
+    // virtual particles of this wavefront's empty cones: one list atomic per wavefront
+    const unsigned long long wvip = __ballot(vip);
+    long long vbase = 0;
+    if (wvip) {
+        const int ld = __ffsll(static_cast<long long>(wvip)) - 1;
+        if (lane == ld)
+            vbase = static_cast<long long>(atomicAdd(reinterpret_cast<unsigned long long*>(&a.cnt[kCntVipCnt0 + a.list_wr]),
+                                                     static_cast<unsigned long long>(__popcll(wvip))));
+        vbase = __shfl(vbase, ld, 64);
+    }
     if (valid) {
         if (a.hop0 || narr > 0 || departed || floored) {
             Bin4<R> w;
@@ -1805,8 +1861,10 @@ __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long lon
             nbytes += 6 * rsz;
         }
         if (vip) {
-            const long long v = push_vip(a.vip_out, a.cnt, a.list_wr, a.vip_cap);
-            if (v >= 0) {
+            const long long v = vbase + __popcll(wvip & ((1ull << lane) - 1ull));
+            if (v >= a.vip_cap) {
+                atomicOr(reinterpret_cast<unsigned long long*>(&a.cnt[kCntFlags]), static_cast<unsigned long long>(kFlagVipOverflow));
+            } else {
                 Vip q;
                 q.x[0] = a.pos[3 * j];
                 q.x[1] = a.pos[3 * j + 1];
