@@ -39,7 +39,14 @@ typedef enum {
     RT_EHOPCAP = 4,     /* a step stopped at max_hops; unfinished packets stay in flight */
     RT_ENONFINITE = 5,  /* a ledger entry is not finite */
     RT_ESTATE = 6,      /* call out of order (e.g. state blob of the wrong size) */
-    RT_EOVERFLOW = 7    /* the virtual-particle or record buffer overflowed; photons were dropped */
+    RT_EOVERFLOW = 7,   /* the virtual-particle or record buffer overflowed; the packets that
+                           found no room left the transport and are counted as removed (the
+                           ledger still closes); raise vip_capacity / record_capacity */
+    RT_EDRIFT = 8       /* FP32 transport: the photons in flight differ from the ledger's
+                           emitted - absorbed - escaped - removed by more than 1e-3 of
+                           themselves and more than 1e-5 of the photons emitted (more
+                           than rounding), so they were not rescaled (the state stays
+                           consistent; the ledger reports the residual) */
 } rt_status;
 
 /* Treatment of recombinations (section 2.1 "case B with on-the-spot", "case A";
@@ -114,7 +121,9 @@ rt_status rt_add_sources(rt_ctx *ctx, int32_t n_src, const int32_t *inst, const 
  * emission of the RR photons into the reception cones (sections 2.1, 2.2).
  * Returns RT_EHOPCAP if a step hit max_hops (the state stays consistent),
  * RT_EOVERFLOW if a work buffer overflowed, RT_ENONFINITE on a non-finite
- * ledger, RT_EDEVICE on a HIP failure. */
+ * ledger, RT_EDRIFT if the FP32 in-flight rescale was refused, RT_EDEVICE on
+ * a HIP failure.  The first of these ends the call after its step; the next
+ * call starts afresh. */
 rt_status rt_step(rt_ctx *ctx, int32_t n_steps);
 
 /* Copy the state out (synchronises).  Any pointer may be NULL.

@@ -50,7 +50,7 @@ enum : int {
 };
 // Alignment of the tile-mark array (k_tile_list reads 4096 marks per workgroup).
 constexpr long long kTileListChunk = 4096;
-enum : long long { kFlagHopCap = 1, kFlagVipOverflow = 2, kFlagRecOverflow = 4, kFlagNonFinite = 8 };
+enum : long long { kFlagHopCap = 1, kFlagVipOverflow = 2, kFlagRecOverflow = 4, kFlagNonFinite = 8, kFlagDrift = 16 };
 // units of the two fixed-point deposit accumulators, relative to the receiving particle's N_H
 constexpr double kDepositCoarse = 1.0 / 1073741824.0;         // 2^-30
 constexpr double kDepositFine = 1.0 / 4611686018427387904.0;  // 2^-62
@@ -325,6 +325,8 @@ struct EmitArgs {
     Vip* vip;
     long long vip_cap;
     long long* cnt;
+    unsigned long long* xr_fx;  // removed photons of full lists (fixed point, per instance and bin)
+    const double* Ufx;
 };
 
 __device__ inline int alloc_records(long long* cnt, int n, long long cap) {
@@ -487,7 +489,11 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
             rc.j = j;
             rc.o = nu * a.nrc + r;
             const int idx = alloc_records(a.cnt, 1, a.rec_cap);
-            if (idx >= 0) push_record(a.rec, a.rec_next, a.head, idx, rc);
+            if (idx >= 0)
+                push_record(a.rec, a.rec_next, a.head, idx, rc);
+            else  // no room: the member's share leaves the transport as removed
+                fx_add3(a.xr_fx + 3 * ((static_cast<long long>(a.em_inst[m]) * a.nf + nu) * 2 + 1), nin / a.Ufx[a.em_inst[m]],
+                        a.cnt);
         }
         // Empty cones become virtual particles (thread mem handles cones mem, mem + K, ...).
         const int nk = kind == 0 ? a.nec : 1;
@@ -508,7 +514,11 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
             }
             if (cntk != 0) continue;
             const long long v = push_vip(a.vip, a.cnt, 0, a.vip_cap);
-            if (v < 0) continue;
+            if (v < 0) {  // no room: the empty cone's packet leaves the transport as removed
+                fx_add3(a.xr_fx + 3 * ((static_cast<long long>(a.em_inst[m]) * a.nf + nu) * 2 + 1), pk / a.Ufx[a.em_inst[m]],
+                        a.cnt);
+                continue;
+            }
             Vip q;
             q.x[0] = ex;
             q.x[1] = ey;
@@ -703,7 +713,9 @@ __global__ __launch_bounds__(256) void k_vip_sample(VipArgs a) {
                     a.deep_x[3 * d + 1] = xv[1];
                     a.deep_x[3 * d + 2] = xv[2];
                 } else {
+                    // no room to follow it: its photons leave the transport as removed
                     atomicOr(reinterpret_cast<unsigned long long*>(&a.cnt[kCntFlags]), static_cast<unsigned long long>(kFlagVipOverflow));
+                    vip_settle(a, q, 1, q.N);
                 }
             }
         }
@@ -846,6 +858,7 @@ __global__ __launch_bounds__(256) void k_vip_chain(VipArgs a) {
                 int idx1 = 0;
                 if (lane == 0) idx1 = alloc_records(a.cnt, nc, a.rec_cap);
                 idx1 = __shfl(idx1, 0, 64);
+                if (idx1 < 0 && lane == 0) vip_settle(a, q, 1, nrem);  // no room: removed
                 if (member && idx1 >= 0) {
                     const int w8 = __popcll(bm & ((1ull << lane) - 1ull));
                     const double lk = (vx * q.d[0] + vy * q.d[1] + vz * q.d[2]) / dd;
@@ -961,6 +974,8 @@ struct HopArgs {
     double* A;
     double* P;
     double* Fp;              // [N][nf] photons resting in the particle's bins (physical)
+    unsigned long long* xr_fx;  // escaped/removed fixed-point accumulators (a full virtual-particle list)
+    const double* Ufx;          // their unit per instance
     const Rec* rec;
     const int* rec_next;
     int* head;               // record lists of this forward step, emptied once read
@@ -1863,7 +1878,10 @@ __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long lon
         if (vip) {
             const long long v = vbase + __popcll(wvip & ((1ull << lane) - 1ull));
             if (v >= a.vip_cap) {
+                // no room to follow it: its photons leave the transport as removed
                 atomicOr(reinterpret_cast<unsigned long long*>(&a.cnt[kCntFlags]), static_cast<unsigned long long>(kFlagVipOverflow));
+                fx_add3(a.xr_fx + 3 * ((static_cast<long long>(inst) * a.nf + nu) * 2 + 1), static_cast<double>(nn) * U / a.Ufx[inst],
+                        a.cnt);
             } else {
                 Vip q;
                 q.x[0] = a.pos[3 * j];
@@ -2263,10 +2281,20 @@ __global__ void k_ledger_final(LedgerFinalArgs a) {
     L[2] += v[2];
     L[3] += v[3];
     L[4] = v[4];
+    // FP32 transport: the photons in flight are rescaled to what the FP64
+    // ledger says is left.  Rounding moves them by ~1e-7 of the photons
+    // handled, which can be a large part of few photons in flight, so a
+    // difference within 1e-3 of the photons in flight or 1e-5 of those
+    // emitted is rounding; anything else (or nothing left to carry) is not
+    // rescaled, and reported.
     double s = 1.0;
     if (a.f32 && v[4] > 0.0) {
         const double target = L[0] - L[1] - L[2] - L[3];
-        if (fabs(target - v[4]) <= 1e-3 * v[4]) s = target / v[4];
+        const double diff = fabs(target - v[4]);
+        if (target > 0.0 && (diff <= 1e-3 * v[4] || diff <= 1e-5 * L[0]))
+            s = target / v[4];
+        else
+            atomicOr(reinterpret_cast<unsigned long long*>(&a.cnt[kCntFlags]), static_cast<unsigned long long>(kFlagDrift));
     }
     a.scale[k * a.nf + nu] = s;
     for (int q = 0; q < 5; ++q)

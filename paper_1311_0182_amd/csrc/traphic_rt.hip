@@ -342,6 +342,8 @@ rt_status launch_hop(rt_ctx* c, int hop, bool pack) {
     a.A = c->A;
     a.P = c->P;
     a.Fp = c->Fp;
+    a.xr_fx = c->xr_fx;
+    a.Ufx = c->Ufx;
     a.rec = c->rec;
     a.rec_next = c->rec_next;
     a.head = c->head[hop & 1];
@@ -453,6 +455,7 @@ __global__ void k_step_reset(long long* cnt, long long serial) {
         cnt[kCntDeep] = 0;
         cnt[kCntTileList] = 0;
         cnt[kCntTileList + 1] = 0;
+        cnt[kCntFlags] = 0;  // a step's flags are checked after it
         cnt[kCntSteps] += 1;
     }
 }
@@ -606,6 +609,8 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
         ea.vip = c->vip[0];
         ea.vip_cap = c->vip_cap;
         ea.cnt = c->cnt;
+        ea.xr_fx = c->xr_fx;
+        ea.Ufx = c->Ufx;
         hipLaunchKernelGGL(k_emit, dim3(grid_for(c->n_emit * c->nsub * c->K, 256)), dim3(256), 0, c->stream, ea);
         HIPCHK(c, hipGetLastError());
     }
@@ -1235,6 +1240,8 @@ rt_status rt_step(rt_ctx* c, int32_t n_steps) {
         const long long flags = c->h_cnt[kCntFlags];
         if (flags & (kFlagVipOverflow | kFlagRecOverflow)) return fail(c, RT_EOVERFLOW, "work buffer overflow");
         if (flags & kFlagNonFinite) return fail(c, RT_ENONFINITE, "non-finite ledger");
+        if (flags & kFlagDrift)
+            return fail(c, RT_EDRIFT, "FP32 photons in flight drifted more than 1e-3 from the ledger: not rescaled");
     }
     if (hopcap) return fail(c, RT_EHOPCAP, "a step reached max_hops");
     return RT_OK;

@@ -15,9 +15,9 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtraphic_rt.so")
 
-RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_EHOPCAP, RT_ENONFINITE, RT_ESTATE, RT_EOVERFLOW = range(8)
+RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_EHOPCAP, RT_ENONFINITE, RT_ESTATE, RT_EOVERFLOW, RT_EDRIFT = range(9)
 STATUS = {0: "RT_OK", 1: "RT_EINVAL", 2: "RT_ENOMEM", 3: "RT_EDEVICE", 4: "RT_EHOPCAP",
-          5: "RT_ENONFINITE", 6: "RT_ESTATE", 7: "RT_EOVERFLOW"}
+          5: "RT_ENONFINITE", 6: "RT_ESTATE", 7: "RT_EOVERFLOW", 8: "RT_EDRIFT"}
 RT_FP64, RT_FP32 = 0, 1
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t)
@@ -117,6 +117,29 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
+def params_struct(p, alloc_cb, dealloc_cb):
+    """rt_params from a parameter dict of paper_1311_0182_amd.inputs."""
+    return Params(
+        int(p["n_ngb"]), int(p["n_tc"]), int(p["n_rc"]), int(p["n_ec"]), int(p["n_freq"]),
+        int(p["rr_bin"]), int(p["recomb_mode"]), int(p["isothermal"]), int(p.get("freeze_chem", 0)),
+        int(p.get("precision", RT_FP64)), int(p["n_em"]), int(p["max_hops"]), int(p["max_vip_depth"]),
+        int(p.get("hop_batch", 0)), float(p["dt"]), float(p["floor_rel"]), float(p["chem_frac"]),
+        int(p["seed"]) & 0xFFFFFFFFFFFFFFFF, int(p.get("vip_capacity", 0)),
+        int(p.get("record_capacity", 0)), alloc_cb, dealloc_cb, None)
+
+
+def init_call(handle, params, cfg, stream_ptr):
+    """rt_init on a workload dict's arrays; returns the status."""
+    keep = [_f64(cfg["sigma"]), _f64(cfg["eps"]), np.ascontiguousarray(cfg["inst_off"], dtype=np.int64),
+            _f64(cfg["box"]), _f64(cfg["pos"]), _f64(cfg["nH"]), _f64(cfg["NH"]), _f64(cfg["xHI"]),
+            _f64(cfg["T"])]
+    n_inst = int(cfg["inst_off"].shape[0] - 1)
+    return load().rt_init(C.byref(handle), C.byref(params), _p(keep[0], C.c_double), _p(keep[1], C.c_double),
+                          n_inst, _p(keep[2], C.c_int64), _p(keep[3], C.c_double), _p(keep[4], C.c_double),
+                          _p(keep[5], C.c_double), _p(keep[6], C.c_double), _p(keep[7], C.c_double),
+                          _p(keep[8], C.c_double), C.c_void_p(stream_ptr))
+
+
 class Context:
     """One library context built from a workload dict of paper_1311_0182_amd.inputs.
 
@@ -159,21 +182,9 @@ class Context:
         else:
             self._alloc_cb = ALLOC_FN()
             self._dealloc_cb = DEALLOC_FN()
-        self._params = Params(
-            int(p["n_ngb"]), int(p["n_tc"]), int(p["n_rc"]), int(p["n_ec"]), int(p["n_freq"]),
-            int(p["rr_bin"]), int(p["recomb_mode"]), int(p["isothermal"]), int(p.get("freeze_chem", 0)),
-            int(p.get("precision", RT_FP64)), int(p["n_em"]), int(p["max_hops"]), int(p["max_vip_depth"]),
-            int(p.get("hop_batch", 0)), float(p["dt"]), float(p["floor_rel"]), float(p["chem_frac"]),
-            int(p["seed"]) & 0xFFFFFFFFFFFFFFFF, int(p.get("vip_capacity", 0)),
-            int(p.get("record_capacity", 0)), self._alloc_cb, self._dealloc_cb, None)
-        keep = [_f64(cfg["sigma"]), _f64(cfg["eps"]), np.ascontiguousarray(cfg["inst_off"], dtype=np.int64),
-                _f64(cfg["box"]), _f64(cfg["pos"]), _f64(cfg["nH"]), _f64(cfg["NH"]), _f64(cfg["xHI"]),
-                _f64(cfg["T"])]
+        self._params = params_struct(p, self._alloc_cb, self._dealloc_cb)
         h = C.c_void_p()
-        st = L.rt_init(C.byref(h), C.byref(self._params), _p(keep[0], C.c_double), _p(keep[1], C.c_double),
-                       self.n_inst, _p(keep[2], C.c_int64), _p(keep[3], C.c_double), _p(keep[4], C.c_double),
-                       _p(keep[5], C.c_double), _p(keep[6], C.c_double), _p(keep[7], C.c_double),
-                       _p(keep[8], C.c_double), C.c_void_p(self.stream.cuda_stream))
+        st = init_call(h, self._params, cfg, self.stream.cuda_stream)
         if st != RT_OK:
             raise RTError(st, "rt_init failed")
         self.h = h

@@ -341,3 +341,78 @@ def test_full_size_rr64_fp32():
     assert dx <= 1e-3
     assert np.max(residual(s32["ledger"])) <= 1e-6
     _fp32_window_against_fp64(cfg, 100)
+
+
+def test_overflow_reports_and_counts_dropped_photons_as_removed():
+    """A virtual-particle list far too small: rt_step returns RT_EOVERFLOW, the
+    packets that found no room leave the transport as removed photons, so the
+    ledger still closes; the next call starts afresh."""
+    RT = _rt()
+    cfg = I.stromgren(8, rr=True, n_ngb=16, dt_myr=0.5)
+    ctx = RT.Context(cfg, precision="fp64", vip_capacity=2, record_capacity=1 << 20)
+    assert ctx.step(1, allow=(RT.RT_EOVERFLOW,)) == RT.RT_EOVERFLOW
+    led = ctx.state()["ledger"]
+    assert np.max(residual(led)) < 1e-12
+    assert led[..., 3].sum() > 0          # removed photons
+    assert ctx.step(1, allow=(RT.RT_EOVERFLOW,)) in (RT.RT_OK, RT.RT_EOVERFLOW)
+    assert np.max(residual(ctx.state()["ledger"])) < 1e-12
+    ctx.close()
+    # records too: emission and virtual-particle arrival records
+    ctx = RT.Context(cfg, precision="fp32", record_capacity=8)
+    assert ctx.step(2, allow=(RT.RT_EOVERFLOW,)) == RT.RT_EOVERFLOW
+    assert np.max(residual(ctx.state()["ledger"])) < 1e-6
+    ctx.close()
+
+
+def test_allocator_failure_returns_enomem_and_frees_everything():
+    """rt_init with a device allocator that fails at its k-th call: RT_ENOMEM, no
+    context, and every buffer allocated before the failure handed back."""
+    import ctypes as C
+    import torch
+    RT = _rt()
+    cfg = I.stromgren(8, rr=True, n_ngb=16)
+    stream = torch.cuda.Stream()
+    dev = torch.cuda.current_device()
+    for fail_at in (1, 7, 30, 60):
+        live, calls = {}, [0]
+
+        def _alloc(user, n):
+            calls[0] += 1
+            if calls[0] >= fail_at:
+                return None
+            ptr = torch.cuda.caching_allocator_alloc(int(n), dev, stream)
+            live[ptr] = n
+            return ptr
+
+        def _dealloc(user, ptr):
+            live.pop(ptr)
+            torch.cuda.caching_allocator_delete(ptr)
+
+        acb, dcb = RT.ALLOC_FN(_alloc), RT.DEALLOC_FN(_dealloc)
+        params = RT.params_struct(cfg["params"], acb, dcb)
+        h = C.c_void_p()
+        st = RT.init_call(h, params, cfg, stream.cuda_stream)
+        say("allocator fails at call", fail_at, "status", RT.STATUS.get(st), "live", len(live))
+        assert st == RT.RT_ENOMEM and not h.value
+        assert not live
+
+
+def test_refused_fp32_rescale_is_reported():
+    """A checkpoint whose ledger was tampered with (emitted photons +1%): the
+    FP32 rescale of the photons in flight would exceed 1e-3, so it is refused
+    and rt_step says so (RT_EDRIFT) instead of passing silently."""
+    import struct
+    RT = _rt()
+    # c dt = 0.6 kpc in a 6.6 kpc box: packets are still in flight at the step's end
+    cfg = I.stromgren(10, rr=True, n_ngb=32, dt_myr=0.002, n_em=1)
+    ctx = RT.Context(cfg, precision="fp32")
+    assert ctx.step(3) == RT.RT_OK
+    assert ctx.state()["ledger"][0, 0, 4] > 0
+    blob = bytearray(ctx.get_blob())
+    N, B = ctx.N, ctx.N * ctx.G
+    off = 9 * 8 + 5 * 4 * B + 3 * 8 * N      # header, FP32 bins and clocks, x_HI, T, pending RR
+    E, = struct.unpack_from("<d", blob, off)
+    struct.pack_into("<d", blob, off, E * 1.01)
+    ctx.set_blob(bytes(blob))
+    assert ctx.step(1, allow=(RT.RT_EDRIFT,)) == RT.RT_EDRIFT
+    ctx.close()
