@@ -82,6 +82,10 @@ def lib():
         L.or_merge_packets.argtypes = [C.c_int32, dp, dp, dp, dp, dp, dp]
         L.or_vip_leg.argtypes = [C.c_void_p, C.c_int32, dp, dp, dp, C.c_double, C.c_int32, ip, dp, dp, dp, dp,
                                  dp, dp]
+        L.or_set_barrier.restype = C.c_int
+        L.or_set_barrier.argtypes = [C.c_void_p, C.c_int32, dp, C.c_double]
+        L.or_leg_crosses_disk.restype = C.c_int
+        L.or_leg_crosses_disk.argtypes = [dp, dp, dp, C.c_double]
         L.or_shell_profile.restype = C.c_int
         L.or_shell_profile.argtypes = [C.c_int64, C.c_int32, dp, dp, C.c_double, dp, dp, C.c_double,
                                        C.c_double, C.c_int32, C.c_int32, C.c_double, dp, i64p]
@@ -135,6 +139,9 @@ class OracleSim:
         self.h = h
         if with_sources and cfg.get("sources") is not None:
             self.add_sources(cfg["sources"])
+        if cfg.get("barrier") is not None:
+            b = cfg["barrier"]
+            self.set_barrier(b["inst"], b["center"], b["radius"])
 
     def add_sources(self, s):
         L = lib()
@@ -204,6 +211,11 @@ class OracleSim:
         h = np.empty(q.shape[0])
         lib().or_knn_points(self.h, int(inst), q.shape[0], qp, _ptr(nb, C.c_int32), _ptr(h, C.c_double))
         return nb.reshape(-1, k), h
+
+    def set_barrier(self, inst, center, radius):
+        c, cp = _d(np.asarray(center, dtype=float).reshape(3))
+        if lib().or_set_barrier(self.h, int(inst), cp, float(radius)):
+            raise ValueError("oracle: " + lib().or_error().decode())
 
     def vip_leg(self, inst, x, xv, d, N, nu=0):
         """One virtual-particle leg (or_vip_leg): dict of neighbours, h, deposits,
@@ -277,6 +289,13 @@ def chem_one(params, eps, A, nH, NH, xHI, T):
     n = C.c_int64(0)
     lib().or_chem_one(C.byref(p), ep, ap, float(nH), float(NH), C.byref(x), C.byref(t), C.byref(r), C.byref(n))
     return x.value, t.value, r.value, n.value
+
+
+def leg_crosses_disk(a, b, c, r):
+    a_, ap = _d(np.asarray(a, dtype=float).reshape(3))
+    b_, bp = _d(np.asarray(b, dtype=float).reshape(3))
+    c_, cp = _d(np.asarray(c, dtype=float).reshape(3))
+    return bool(lib().or_leg_crosses_disk(ap, bp, cp, float(r)))
 
 
 def vip_sample(seed, tag, step, ida, idb, d, n_tc):

@@ -74,6 +74,14 @@ static int run(int recomb_mode, int n_side, int two_instances)
         fprintf(stderr, "or_add_sources: %s\n", or_error());
         return 1;
     }
+    if (two_instances) {
+        /* a barrier disk in the first instance, across the point source's light */
+        const double bc[3] = {0.4 * L, L / 2, L / 2};
+        if (or_set_barrier(S, 0, bc, 0.2 * L)) {
+            fprintf(stderr, "or_set_barrier: %s\n", or_error());
+            return 1;
+        }
+    }
     or_step(S, 3);
     const int nf = 2, G = 16;
     double *x = malloc(sizeof(double) * N), *t = malloc(sizeof(double) * N), *A = malloc(sizeof(double) * N * nf);
@@ -138,6 +146,8 @@ int main(void)
     (void)or_vip_sample(7, 2, 3, 4, 5, dd, 8, pp);
     double N2[2] = {1, 2}, d2[6] = {1, 0, 0, 0, 1, 0}, c2[2] = {0, 1}, oN, od[3], oc;
     or_merge_packets(2, N2, d2, c2, &oN, od, &oc);
+    const double la[3] = {-1, 0, 0}, lb[3] = {1, 0.5, 0}, lc[3] = {0, 0, 0};
+    (void)or_leg_crosses_disk(la, lb, lc, 1.0);
     /* one instance with a point source; two instances, the second lit by a plane front */
     int bad = run(OR_RR_TRANSPORT, 6, 0) | run(OR_RR_ORIGINAL, 5, 0) | run(OR_CASE_A_NO_RR, 4, 0) |
               run(OR_CASE_B_OTS, 5, 1) | run(OR_RR_TRANSPORT, 5, 1);

@@ -328,6 +328,7 @@ struct or_sim {
     int64_t *cell_idx;
     double rc_rot[9];
     double *w_rc;               /* rotated reception directions of this step */
+    double *barrier;            /* [n_inst][4]: centre and radius of a barrier disk (radius 0: none) */
 };
 
 static void *xcalloc(size_t n, size_t s)
@@ -533,6 +534,7 @@ or_sim *or_create(const or_params *p, const double *sigma, const double *eps, in
     S->P = xcalloc((size_t)N * S->nf, sizeof(double));
     S->nrr = xcalloc((size_t)N, sizeof(double));
     S->led = xcalloc((size_t)n_inst * S->nf * 4, sizeof(double));
+    S->barrier = xcalloc((size_t)n_inst * 4, sizeof(double));
     build_grid(S);
     /* Neighbour lists (section 2.1), built once: the density field is static. */
     for (int64_t i = 0; i < N; ++i) knn(S, S->inst_of[i], S->pos + 3 * i, i, p->n_ngb, S->ngb + i * p->n_ngb, &S->h[i]);
@@ -542,6 +544,7 @@ or_sim *or_create(const or_params *p, const double *sigma, const double *eps, in
 void or_destroy(or_sim *S)
 {
     if (!S) return;
+    free(S->barrier);
     for (int64_t m = 0; m < S->n_emit; ++m) {
         free(S->em[m].pk);
         free(S->em[m].ngb);
@@ -700,6 +703,40 @@ static void leg_to_particle(or_sim *S, int64_t j, int nu, const double d[3], dou
     S->P[j * S->nf + nu] += N_in;
     int r = nearest_dir(S->w_rc, S->p.n_rc, d);
     merge_in(S, slot_of(S, j, nu, r), Nout, d, c_prev + l / C_LIGHT);
+}
+
+/* Section 4's artificial barrier: a disk of radius r around c in the plane
+ * x = c_x, which removes every photon packet that passes through it.
+ * Reading: a packet passes through it when the straight leg it travels, from
+ * a to b, meets the disk: the ends are not strictly on one side of the plane,
+ * the leg does not lie in the plane, and the point where it meets the plane is
+ * within r of c (inclusive).  The removed photons are tallied as removed. */
+int or_leg_crosses_disk(const double a[3], const double b[3], const double c[3], double r)
+{
+    double da = a[0] - c[0], db = b[0] - c[0];
+    if ((da > 0.0 && db > 0.0) || (da < 0.0 && db < 0.0)) return 0;
+    if (da == db) return 0;
+    double t = da / (da - db);
+    double py = (a[1] + t * (b[1] - a[1])) - c[1];
+    double pz = (a[2] + t * (b[2] - a[2])) - c[2];
+    return py * py + pz * pz <= r * r;
+}
+
+static int blocked(const or_sim *S, int inst, const double a[3], const double b[3])
+{
+    const double *bar = S->barrier + 4 * (int64_t)inst;
+    return bar[3] > 0.0 && or_leg_crosses_disk(a, b, bar, bar[3]);
+}
+
+int or_set_barrier(or_sim *S, int32_t inst, const double center[3], double radius)
+{
+    if (inst < 0 || inst >= S->n_inst || !(radius >= 0.0)) {
+        set_err("bad barrier");
+        return 1;
+    }
+    for (int a = 0; a < 3; ++a) S->barrier[4 * inst + a] = center[a];
+    S->barrier[4 * inst + 3] = radius;
+    return 0;
 }
 
 /* Members of the transmission cone of a packet at position x with direction d
@@ -884,6 +921,10 @@ static void vip_chain(or_sim *S, vip_req q, double *X, double *R)
             return;
         }
         double xv[3] = {q.x[0] + q.h * p[0], q.x[1] + q.h * p[1], q.x[2] + q.h * p[2]};
+        if (blocked(S, q.inst, q.x, xv)) {  /* the leg to the virtual particle meets the barrier */
+            *R += q.N;
+            return;
+        }
         for (int a = 0; a < 3; ++a) {
             if (xv[a] < bx[a] || xv[a] > bx[3 + a]) {
                 *X += q.N;
@@ -906,6 +947,10 @@ static void vip_chain(or_sim *S, vip_req q, double *X, double *R)
             for (int t = 0; t < nc; ++t) {
                 int64_t j = vn[mem[t]];
                 const double *xk = S->pos + 3 * j;
+                if (blocked(S, q.inst, xv, xk)) {
+                    *R += Nin;
+                    continue;
+                }
                 double v[3] = {xk[0] - xv[0], xk[1] - xv[1], xk[2] - xv[2]};
                 double lk = dot3(v, q.d) / dd;
                 leg_to_particle(S, j, q.nu, q.d, Nin, lk, cv);
@@ -1047,6 +1092,10 @@ static void emit_sources(or_sim *S, double *Xled, double *Rled)
                         int k = kc[t];
                         int64_t j = e->ngb[t];
                         const double *xj = S->pos + 3 * j;
+                        if (blocked(S, e->inst, e->pos, xj)) {
+                            Rled[e->inst * nf + nu] += e->pk[nu] / (double)ncount[k];
+                            continue;
+                        }
                         double v[3] = {xj[0] - e->pos[0], xj[1] - e->pos[1], xj[2] - e->pos[2]};
                         double *dk = ecd + 3 * k;
                         double l = dot3(v, dk) / sqrt(dot3(dk, dk));
@@ -1081,6 +1130,10 @@ static void emit_sources(or_sim *S, double *Xled, double *Rled)
                         for (int t = 0; t < nc; ++t) {
                             int64_t j = e->ngb[mem[t]];
                             const double *xj = S->pos + 3 * j;
+                            if (blocked(S, e->inst, e->pos, xj)) {
+                                Rled[e->inst * nf + nu] += e->pk[nu] / (double)nc;
+                                continue;
+                            }
                             double v[3] = {xj[0] - e->pos[0], xj[1] - e->pos[1], xj[2] - e->pos[2]};
                             double l = dot3(v, d) / sqrt(dot3(d, d));
                             leg_to_particle(S, j, nu, d, e->pk[nu] / (double)nc, l, 0.0);
@@ -1147,6 +1200,10 @@ static void emit_rr_original(or_sim *S, uint32_t step, double *Xled, double *Rle
                 int k = kc[t];
                 int64_t j = nb[t];
                 const double *xj = S->pos + 3 * j;
+                if (blocked(S, inst, xi, xj)) {
+                    Rled[inst * nf + nu] += pk / (double)ncount[k];
+                    continue;
+                }
                 double v[3] = {xj[0] - xi[0], xj[1] - xi[1], xj[2] - xi[2]};
                 double *dk = ecd + 3 * k;
                 double l = dot3(v, dk) / sqrt(dot3(dk, dk));
@@ -1260,6 +1317,10 @@ static int one_step(or_sim *S)
             for (int m = 0; m < nc; ++m) {
                 int64_t j = nb[mem[m]];
                 const double *xi = S->pos + 3 * i, *xj = S->pos + 3 * j;
+                if (blocked(S, S->inst_of[i], xi, xj)) {
+                    Rs[S->inst_of[i] * nf + nu] += Nin;
+                    continue;
+                }
                 double v[3] = {xj[0] - xi[0], xj[1] - xi[1], xj[2] - xi[2]};
                 double l = dot3(v, d) / sqrt(dot3(d, d));
                 leg_to_particle(S, j, nu, d, Nin, l, S->bc[t]);

@@ -81,7 +81,13 @@ void or_get_nrr(const or_sim *S, double *nrr);
 void or_destroy(or_sim *S);
 const char *or_error(void);
 
+/* Section 4's artificial barrier for instance inst: a disk of the given
+ * radius around center in the plane x = center[0]; every packet whose leg
+ * meets it is removed (tallied as removed).  radius 0 removes the barrier. */
+int or_set_barrier(or_sim *S, int32_t inst, const double center[3], double radius);
+
 /* Primitives exposed for the pin tests. */
+int or_leg_crosses_disk(const double a[3], const double b[3], const double c[3], double r);
 void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 void or_dirset(int32_t n, double *u);
 void or_rotation(uint64_t seed, uint32_t tag, uint32_t step, uint32_t a, uint32_t b, double R[9]);

@@ -312,7 +312,8 @@ def boundary_rr_intensity(flux, n_h, sigma=SIGMA_13P6):
 
 def shadow_boundary(n_side=32, box_kpc=13.2, n_h=1e-3, clump_nh=1.0, clump_r=0.1,
                     clump_c=(0.27, 0.5, 0.5), flux=1e6, n_pp=100, n_bd=50, n_ngb=48, n_tc=16,
-                    n_rc=8, n_ec=8, t0=1e4, n_steps=100, seed_k=4, dt_myr=0.1, **pkw):
+                    n_rc=8, n_ec=8, t0=1e4, n_steps=100, seed_k=4, dt_myr=0.1, barrier=False,
+                    barrier_r=0.2, barrier_c=(0.27, 0.5, 0.5), **pkw):
     """Shadow set-up of section 4 with recombination radiation from outside the
     box (appendix B): 32^3 particles in a 13.2 kpc box at n_H = 1e-3, a plane
     front of 1e6 photons/s/cm^2 from the x = 0 face (n_pp^2 emitters) in one grey
@@ -327,14 +328,18 @@ def shadow_boundary(n_side=32, box_kpc=13.2, n_h=1e-3, clump_nh=1.0, clump_r=0.1
     appendix's equilibrium estimate for monochromatic 13.6 eV photons).
     They start radiating once the I-front has passed them, which the caller
     decides between steps: cfg["boundary"] holds their positions and rates and
-    boundary_sources(cfg, on) gives the source set with those switched on."""
+    boundary_sources(cfg, on) gives the source set with those switched on.
+    barrier=True: section 4's own obstacle instead of the clump, uniform gas
+    and an artificial disk of radius barrier_r L at barrier_c L in the plane
+    parallel to the x = 0 face that removes every packet passing through it
+    (cfg["barrier"]: instance, centre and radius in cm)."""
     rng = np.random.default_rng(BASE_SEED + seed_k)
     L = box_kpc * KPC_CM
     lo = np.zeros(3)
     pos = jittered_lattice(n_side, lo, L, rng)
     c = np.asarray(clump_c, dtype=np.float64) * L
     inside = np.sum((pos - c[None, :]) ** 2, axis=1) <= (clump_r * L) ** 2
-    nh = np.where(inside, clump_nh, n_h)
+    nh = np.full(pos.shape[0], float(n_h)) if barrier else np.where(inside, clump_nh, n_h)
     NH = nh * (L ** 3 / pos.shape[0])
     n_freq = 4
     params = default_params(
@@ -350,7 +355,10 @@ def shadow_boundary(n_side=32, box_kpc=13.2, n_h=1e-3, clump_nh=1.0, clump_r=0.1
                pos=np.zeros((1, 3)), rate=rate, n_side=np.array([n_pp], np.int32))
     inst = dict(pos=pos, nH=nh, NH=NH, xHI=np.ones(pos.shape[0]), T=np.full(pos.shape[0], t0),
                 box_lo=lo, box_hi=lo + L)
-    cfg = _pack(f"shadow_boundary{n_side}", params, sigma, eps, [inst], src, n_steps)
+    cfg = _pack(f"shadow_{'barrier' if barrier else 'boundary'}{n_side}", params, sigma, eps, [inst], src, n_steps)
+    if barrier:
+        cfg["barrier"] = dict(inst=0, center=np.asarray(barrier_c, dtype=np.float64) * L + lo,
+                              radius=float(barrier_r) * L)
     bi = boundary_rr_intensity(flux, n_h)
     g = (np.arange(n_bd) + 0.5) * (L / n_bd)
     bpos = []
@@ -367,6 +375,18 @@ def shadow_boundary(n_side=32, box_kpc=13.2, n_h=1e-3, clump_nh=1.0, clump_r=0.1
     brate[:, 2] = bi["intensity"] * L * L / (n_bd * n_bd)
     cfg["boundary"] = dict(pos=np.array(bpos), rate=brate, flux=flux, n_h=n_h, **bi)
     return cfg
+
+
+def shadow_barrier(n_side=32, n_tc=128, **kw):
+    """Section 4's shadow test as the paper runs it: 32^3 particles in 13.2 kpc
+    of uniform gas at n_H = 1e-3, the artificial barrier disk (radius 0.2 L at
+    (0.27, 0.5, 0.5) L), the plane front, boundary recombination sources on the
+    four faces parallel to it, N_TC = 128 and N_RC = 8.  At N_TC = 128 most
+    transmission cones hold no neighbour, so virtual particles carry much of
+    the transport; chains may run 15 deep (at depth 4 a fifth or more of the
+    front's photons would end as removed)."""
+    kw.setdefault("max_vip_depth", 15)
+    return shadow_boundary(n_side=n_side, n_tc=n_tc, barrier=True, **kw)
 
 
 def boundary_schedule(cfg, t):

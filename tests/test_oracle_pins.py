@@ -855,3 +855,123 @@ def test_photoheated_gas_temperature_section4_soft():
     v, tol = PAPER["T_heat_source_K"]
     assert y < 1e-3
     assert abs(T / v - 1) < tol, T
+
+
+# --- the artificial barrier (section 4) --------------------------------------
+
+@pytest.mark.parametrize("flip", [False, True])
+def test_barrier_leg_exact_cases(flip):
+    # a disk of radius 1 around the origin in the plane x = 0; each case's
+    # crossing point is exact in binary, so membership is decided exactly
+    c = (0.0, 0.0, 0.0)
+    cases = [
+        ((-1, 0, 0), (1, 0, 0), True),         # through the centre
+        ((-1, 0.9, 0), (1, 0.9, 0), True),
+        ((-1, 1.1, 0), (1, 1.1, 0), False),     # passes beside the disk
+        ((-1, 1, 0), (1, 1, 0), True),          # meets the rim: inclusive
+        ((-1, 0, 0), (3, 4, 0), True),          # oblique, meets the plane at y = 1
+        ((-1, 0, 0), (3, 4.5, 0), False),       # oblique, meets the plane at y = 1.125
+        ((-1, -0.5, 0.5), (3, 1.5, -1.5), True),  # at (0, 0, 0)
+        ((0, 0.5, 0), (1, 0.5, 0), True),       # starts on the disk
+        ((-2, 0.5, 0), (0, 0.5, 0), True),      # ends on the disk
+        ((0.1, 0, 0), (0.5, 0, 0), False),      # entirely on one side
+        ((-0.5, 0, 0), (-0.1, 0, 0), False),
+        ((0, 0, 0), (0, 0.5, 0), False),        # lies in the plane
+    ]
+    for a, b, want in cases:
+        if flip:
+            a, b = b, a
+        assert O.leg_crosses_disk(a, b, c, 1.0) == want, (a, b)
+    # a shifted, scaled disk: the same geometry around (5, 2, -3) with radius 0.25
+    cs = (5.0, 2.0, -3.0)
+    assert O.leg_crosses_disk((4.5, 2.0, -3.0), (5.5, 2.25, -3.0), cs, 0.25)
+    assert not O.leg_crosses_disk((4.5, 2.0, -3.0), (5.5, 2.75, -3.0), cs, 0.25)
+
+
+def test_barrier_leg_against_dense_sampling():
+    # brute force: walk the leg in 20001 steps, find where the sign of x - c_x
+    # changes and measure the distance from the axis there; cases within the
+    # walk's resolution of the rim or of the plane are skipped
+    rng = np.random.default_rng(7)
+    c = np.array([0.3, -0.2, 0.1])
+    r = 0.5
+    t = np.linspace(0.0, 1.0, 20001)
+    n_hit = n_miss = 0
+    for _ in range(400):
+        a = rng.uniform(-1.5, 1.5, 3)
+        b = rng.uniform(-1.5, 1.5, 3)
+        p = a[None, :] + t[:, None] * (b - a)[None, :]
+        s = p[:, 0] - c[0]
+        if min(abs(s[0]), abs(s[-1])) < 1e-6:
+            continue
+        k = np.nonzero(np.sign(s[:-1]) != np.sign(s[1:]))[0]
+        if len(k) == 0:
+            want = False
+        else:
+            q = p[k[0]]
+            rho = math.hypot(q[1] - c[1], q[2] - c[2])
+            step = np.linalg.norm(b - a) / 20000
+            if abs(rho - r) < 2 * step:
+                continue
+            want = rho < r
+        got = O.leg_crosses_disk(a, b, c, r)
+        assert got == want
+        n_hit += want
+        n_miss += not want
+    assert n_hit > 20 and n_miss > 100
+
+
+def _transparent_barrier(n_side, n_tc, radius, n_ngb=32, **kw):
+    return I.shadow_barrier(n_side=n_side, n_pp=16, n_bd=4, n_ngb=n_ngb, n_tc=n_tc, n_h=1e-7,
+                            barrier_r=radius, **kw)
+
+
+def test_barrier_covering_the_box_casts_a_complete_shadow():
+    # A disk wider than the box removes every packet whose leg crosses its
+    # plane.  No photon then arrives at a particle behind the plane, and
+    # nothing is absorbed beyond the reach of virtual particles in front of it:
+    # their absorptions go to their N_ngb nearest neighbours, which lie within
+    # |v - p| + h_p <= 2 h_p of a virtual particle v whose nearest particle is p.
+    for r in (0.0, 2.0):
+        cfg = _transparent_barrier(12, 16, r)
+        s = O.OracleSim(cfg)
+        s.step(3)
+        st = s.state()
+        h = s.ngb()[1]
+        s.close()
+        L = float(cfg["box"][0][3])
+        x = cfg["pos"][:, 0]
+        behind = x > 0.27 * L
+        near = np.abs(x - 0.27 * L) < 0.3 * L
+        far = x > 0.27 * L + 2.0 * h[near].max()
+        assert far.sum() > 50
+        E, A, X, R, F = st["ledger"][0, 0]
+        assert abs(E - A - X - R - F) <= 1e-12 * E
+        if r == 0.0:
+            assert R == 0.0
+            assert np.mean(st["P"][behind, 0] > 0) > 0.9   # the front reaches behind the plane
+        else:
+            # the source bin (recombination photons of the gas behind the
+            # plane, ionized collisionally, start there)
+            assert np.all(st["P"][behind, 0] == 0.0)
+            assert np.all(st["A"][far, 0] == 0.0)
+            assert R > 0.99 * E   # the front is removed at the plane (x_HI n_H is tiny)
+
+
+@pytest.mark.parametrize("n_tc,n_ngb", [(16, 32), (128, 48)])
+def test_barrier_removes_its_geometric_share_of_a_plane_front(n_tc, n_ngb):
+    # In (nearly) transparent gas a plane front crosses the plane of the disk
+    # with uniform flux, so the disk removes the fraction of the front it
+    # covers: pi (0.2 L)^2 / L^2 = 0.1257 of the photons emitted.  TRAPHIC's
+    # cones spread the packets sideways a little; the band allows 15%.  At
+    # N_TC = 128 most transmission cones are empty and virtual particles carry
+    # the front (chains up to depth 15).
+    cfg = _transparent_barrier(16, n_tc, 0.2, n_ngb=n_ngb, max_vip_depth=15)
+    s = O.OracleSim(cfg)
+    s.step(2)
+    st = s.state()
+    s.close()
+    E, A, X, R, F = st["ledger"][0, 0]
+    assert abs(E - A - X - R - F) <= 1e-12 * E
+    geo = math.pi * 0.2 ** 2
+    assert abs(R / E - geo) <= 0.15 * geo, R / E
