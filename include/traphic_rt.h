@@ -80,8 +80,10 @@ typedef struct {
     double floor_rel;      /* packets below floor_rel * N_H of their particle are absorbed there */
     double chem_frac;      /* chemistry sub-step: max relative change of x_HI or T */
     uint64_t seed;         /* key of every random draw (rotations, virtual particles) */
-    int64_t vip_capacity;  /* virtual particles per forward step (0: default) */
-    int64_t record_capacity; /* arrival/deposit records per forward step (0: default) */
+    int64_t vip_capacity;  /* virtual particles per forward step (0: default, the larger of
+                              2^16, B/8 and B (1 - 1/n_tc)^n_ngb for B = N n_freq n_rc slots) */
+    int64_t record_capacity; /* arrival/deposit records per forward step (0: default, the
+                                larger of 2^20 and 4 vip_capacity) */
     /* Optional device allocator (e.g. PyTorch's caching allocator).  NULL: hipMalloc/hipFree. */
     void *(*alloc)(void *user, size_t bytes);
     void (*dealloc)(void *user, void *ptr);
@@ -185,6 +187,20 @@ rt_status rt_shell_profile(rt_ctx *ctx, int32_t inst, const double *passing, con
 rt_status rt_shell_profile_noalloc(rt_ctx *ctx, int32_t inst, const double *passing_dev, const double *center,
                                    const double *axis, double half_height, double r_max, int32_t n_shells,
                                    int32_t mean, double norm, double *prof, int64_t *count);
+
+/* The artificial barrier of the shadow test (section 4): a disk of the given
+ * radius (cm) around center[3] in the plane x = center[0], placed in instance
+ * inst, which removes every photon packet passing through it.  A packet passes
+ * through it when the straight leg it travels (particle to neighbour, emitter
+ * to neighbour, to and from a virtual particle) meets the disk: the ends not
+ * strictly on one side of the plane, the leg not in the plane, the point where
+ * it meets the plane within the radius (inclusive).  Removed photons appear in
+ * the ledger as removed.  One disk per instance; radius 0 takes it away (center
+ * may then be NULL).  Between steps only; synchronises the stream.  While a
+ * disk is set, forward steps run a barrier-aware kernel in the default staging
+ * shape (launch configurations then differ in packing only).
+ * Errors: RT_EINVAL (nothing changed), RT_EDEVICE. */
+rt_status rt_set_barrier(rt_ctx *ctx, int32_t inst, const double *center, double radius);
 
 /* Packet bins [N][n_freq][n_rc] in physical units: photons, unit direction
  * (3 per bin) and clock in s since the start of the last step.  Any pointer may be NULL. */

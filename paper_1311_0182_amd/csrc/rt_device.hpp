@@ -153,6 +153,31 @@ __host__ __device__ inline int nearest_direction(const R* w, int n, R dx, R dy, 
     return best;
 }
 
+// The artificial barrier of the shadow test (section 4): a disk of radius r
+// around c in the plane x = c_x that removes every photon packet passing
+// through it.  A packet passes through it when the straight leg it travels,
+// from a to b, meets the disk: the ends not strictly on one side of the plane,
+// the leg not in the plane, and the point where it meets the plane within r of
+// c (inclusive).  Plain FP64 operations in a fixed order, so the decision is
+// the same wherever it is taken.
+__host__ __device__ inline bool leg_crosses_disk(const double a[3], const double b[3], const double c[3], double r) {
+    const double da = a[0] - c[0], db = b[0] - c[0];
+    if ((da > 0.0 && db > 0.0) || (da < 0.0 && db < 0.0)) return false;
+    if (da == db) return false;
+    const double t = da / (da - db);
+    const double py = (a[1] + t * (b[1] - a[1])) - c[1];
+    const double pz = (a[2] + t * (b[2] - a[2])) - c[2];
+    return py * py + pz * pz <= r * r;
+}
+
+// bar: [n_inst][4] centre and radius of each instance's barrier (radius 0:
+// none); a null bar when no instance has one
+__host__ __device__ inline bool barrier_blocks(const double* bar, int inst, const double a[3], const double b[3]) {
+    if (!bar) return false;
+    const double* d = bar + 4 * inst;
+    return d[3] > 0.0 && leg_crosses_disk(a, b, d, d[3]);
+}
+
 // Half-width of the band around a threshold inside which an FP32 decision of
 // the transport (cone membership, reception cone) is handed to FP64.  The
 // FP32 dot products of unit vectors that decide them are within 1e-6 of the

@@ -262,6 +262,23 @@ __global__ void k_edge_vectors(long long N, int K, const double* __restrict__ po
     }
 }
 
+// Marks the receiver-sorted edges whose leg meets the barrier of their
+// instance (section 4): fourth component of the edge vector 1, else 0.
+template <typename V4>
+__global__ void k_barrier_edges(long long N, const double* __restrict__ pos, const int* __restrict__ rev_off,
+                                const unsigned int* __restrict__ rev_ik, const int* __restrict__ inst_of,
+                                const double* __restrict__ bar, V4* __restrict__ rev_v) {
+    const long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    const double xj[3] = {pos[3 * j], pos[3 * j + 1], pos[3 * j + 2]};
+    const int k = inst_of[j];
+    for (int e = rev_off[j]; e < rev_off[j + 1]; ++e) {
+        const long long i = rev_ik[e] >> 6;
+        const double xi[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+        rev_v[e].w = barrier_blocks(bar, k, xi, xj) ? 1 : 0;
+    }
+}
+
 // ---------------------------------------------------------------- per step --
 
 struct StepBeginArgs {
@@ -327,6 +344,7 @@ struct EmitArgs {
     long long* cnt;
     unsigned long long* xr_fx;  // removed photons of full lists (fixed point, per instance and bin)
     const double* Ufx;
+    const double* bar;          // [n_inst][4] barrier disks (section 4)
 };
 
 __device__ inline int alloc_records(long long* cnt, int n, long long cap) {
@@ -471,7 +489,13 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
         if (!(pk > 0.0)) continue;
         if (mem == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&a.cnt[kCntUpdates]),
                                 static_cast<unsigned long long>(kind == 0 ? a.nec : 1));
-        if (member) {
+        const double xj[3] = {a.pos[3 * (long long)j], a.pos[3 * (long long)j + 1], a.pos[3 * (long long)j + 2]};
+        const double xe[3] = {ex, ey, ez};
+        if (member && barrier_blocks(a.bar, a.em_inst[m], xe, xj)) {
+            // the leg meets the barrier: the member's share is removed
+            fx_add3(a.xr_fx + 3 * ((static_cast<long long>(a.em_inst[m]) * a.nf + nu) * 2 + 1),
+                    pk / static_cast<double>(ncone) / a.Ufx[a.em_inst[m]], a.cnt);
+        } else if (member) {
             const double l = (vx * dx + vy * dy + vz * dz) / sqrt(dx * dx + dy * dy + dz * dz);
             const double nin = pk / static_cast<double>(ncone);
             const double tau = a.sigma[nu] * a.xHI[j] * a.nH[j] * l;
@@ -566,6 +590,7 @@ struct VipArgs {
     unsigned long long* xr_fx;  // [n_inst][nf][2][3] escaped, removed photons of transport
                                 // virtual particles this step, fixed point (fx_add3)
     const double* Ufx;          // [n_inst] unit of those accumulators: the mean N_H
+    const double* bar;          // [n_inst][4] barrier disks (section 4)
     double* exs;     // escaped per emission packet
     double* ers;     // removed per emission packet
     Rec* rec;
@@ -688,7 +713,9 @@ __global__ __launch_bounds__(256) void k_vip_sample(VipArgs a) {
                 xv[0] = q.x[0] + q.h * p[0];
                 xv[1] = q.x[1] + q.h * p[1];
                 xv[2] = q.x[2] + q.h * p[2];
-                if (xv[0] < bx[0] || xv[0] > bx[3] || xv[1] < bx[1] || xv[1] > bx[4] || xv[2] < bx[2] || xv[2] > bx[5])
+                if (barrier_blocks(a.bar, q.inst, q.x, xv))
+                    what = 1;  // the leg to the virtual particle meets the barrier
+                else if (xv[0] < bx[0] || xv[0] > bx[3] || xv[1] < bx[1] || xv[1] > bx[4] || xv[2] < bx[2] || xv[2] > bx[5])
                     what = 0;
                 else
                     inside = true;
@@ -778,6 +805,10 @@ __global__ __launch_bounds__(256) void k_vip_chain(VipArgs a) {
                 xv[0] = q.x[0] + q.h * p0;
                 xv[1] = q.x[1] + q.h * p1;
                 xv[2] = q.x[2] + q.h * p2;
+                if (barrier_blocks(a.bar, q.inst, q.x, xv)) {
+                    if (lane == 0) vip_settle(a, q, 1, q.N);
+                    break;
+                }
                 if (xv[0] < bx[0] || xv[0] > bx[3] || xv[1] < bx[1] || xv[1] > bx[4] || xv[2] < bx[2] || xv[2] > bx[5]) {
                     if (lane == 0) vip_settle(a, q, 0, q.N);
                     break;
@@ -859,7 +890,17 @@ __global__ __launch_bounds__(256) void k_vip_chain(VipArgs a) {
                 if (lane == 0) idx1 = alloc_records(a.cnt, nc, a.rec_cap);
                 idx1 = __shfl(idx1, 0, 64);
                 if (idx1 < 0 && lane == 0) vip_settle(a, q, 1, nrem);  // no room: removed
-                if (member && idx1 >= 0) {
+                // members whose leg meets the barrier: their shares are removed
+                const double xk[3] = {pxk, pyk, pzk};
+                const bool cut = member && idx1 >= 0 && barrier_blocks(a.bar, q.inst, xv, xk);
+                if (q.xr_emis) {
+                    const unsigned long long bc = __ballot(cut);
+                    if (bc && lane == 0) a.ers[q.xr] += nin * static_cast<double>(__popcll(bc));
+                } else {
+                    fx_add3_wave(a.xr_fx, (static_cast<long long>(q.inst) * a.nf + q.nu) * 2 + 1,
+                                 cut ? nin / a.Ufx[q.inst] : 0.0, cut, a.cnt);
+                }
+                if (member && idx1 >= 0 && !cut) {
                     const int w8 = __popcll(bm & ((1ull << lane) - 1ull));
                     const double lk = (vx * q.d[0] + vy * q.d[1] + vz * q.d[2]) / dd;
                     const double tk = a.sigma[q.nu] * xHk * nHk * lk;
@@ -1254,7 +1295,7 @@ struct HopLds {
 // marks the tiles that will receive it.  Hop 0 of a step also merges what
 // stays (clocks carried over by -dt), the recombination photons of the last
 // chemistry step (section 2.2) and the emission records.
-template <typename R, typename DT, typename S>
+template <typename R, typename DT, typename S, bool kBar>
 __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long long tile, const long long e_t0,
                                          const long long e_t1, const int stamp, const unsigned int tidx,
                                          unsigned char* __restrict__ lds) {
@@ -1336,6 +1377,7 @@ __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long lon
     Acc<R> acc = {};
     int narr = 0;            // packets merged into the bin besides the one that stays
     R asum = 0, aerr = 0, psum = 0, perr = 0;
+    R rsum = 0;  // photons of arrivals removed by the barrier on their way
     Bin4<R> q0 = {};
     R c0 = 0;
     bool have_stay = false, departed = false;
@@ -1557,8 +1599,11 @@ __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long lon
                         pval[2 * kP + u] = f32 ? nout * q[i].y : q[i].y;
                         pval[3 * kP + u] = f32 ? nout * q[i].z : q[i].z;
                         pval[4 * kP + u] = f32 ? nout * cl : cl;
-                        pval[5 * kP + u] = nabs;
-                        pval[6 * kP + u] = q[i].n;
+                        // an edge that meets the barrier removes the packet on the
+                        // way (marked by nin = -2, its photons where nabs would be)
+                        const bool cut = kBar && v[i].w != static_cast<decltype(v[i].w)>(0);
+                        pval[5 * kP + u] = cut ? q[i].n : nabs;
+                        pval[6 * kP + u] = cut ? R(-2) : q[i].n;
                     }
                 }
                 wave_sync();
@@ -1575,13 +1620,17 @@ __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long lon
                         const R v0 = pval[u], v1 = pval[kP + u], v2 = pval[2 * kP + u], v3 = pval[3 * kP + u],
                                 v4 = pval[4 * kP + u], v5 = pval[5 * kP + u];
                         const bool ok = nin >= R(0);
+                        if constexpr (kBar) rsum += nin == R(-2) ? v5 : R(0);
                         sum_add(asum, aerr, ok ? v5 : R(0));
                         sum_add(psum, perr, ok ? nin : R(0));
                         acc_addp(acc, ok ? v0 : R(0), ok ? v1 : R(0), ok ? v2 : R(0), ok ? v3 : R(0), ok ? v4 : R(0));
                         narr += ok ? 1 : 0;
                     } else {
                         const R nin = pval[6 * kP + u];
-                        if (nin < R(0)) continue;
+                        if (nin < R(0)) {
+                            if (kBar && nin == R(-2)) rsum += pval[5 * kP + u];
+                            continue;
+                        }
                         sum_add(asum, aerr, pval[5 * kP + u]);
                         sum_add(psum, perr, nin);
                         acc_add(acc, pval[u], pval[kP + u], pval[2 * kP + u], pval[3 * kP + u], pval[4 * kP + u]);
@@ -1684,6 +1733,13 @@ __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long lon
         a.A[ia] = A0 + static_cast<double>(ag) * U;
         a.P[ia] = P0 + static_cast<double>(pg) * U;
         nbytes += 32;
+    }
+    // arrivals the barrier removed: one set of atomics per (instance, bin),
+    // in the (rare) wavefronts that saw any
+    if constexpr (kBar) {
+        if (__ballot(valid && rsum > R(0)) != 0ull)
+            fx_add3_wave(a.xr_fx, (static_cast<long long>(inst) * a.nf + nu) * 2 + 1,
+                         valid ? static_cast<double>(rsum) * U / a.Ufx[inst] : 0.0, valid && rsum > R(0), a.cnt);
     }
     // photons resting in (j, nu) after this forward step, for the ledger's
     // in-flight total (a tile's bins change only when it runs)
@@ -1929,7 +1985,9 @@ __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long lon
 // block), so that neighbouring particles share that XCD's L2.  The
 // launch-level flags are read once: a launch past the last forward step of an
 // RT step, or past the cap, runs no tile.
-template <typename R, typename DT, typename S>
+// kBar: some instance has a barrier disk (its edges carry a flag, see
+// k_barrier_edges); without one the flag is never read
+template <typename R, typename DT, typename S, bool kBar>
 __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
     extern __shared__ __align__(32) unsigned char lds_all[];
     const long long c_done = a.cnt[kCntDone];
@@ -1976,7 +2034,7 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
         e_t0 = static_cast<unsigned int>(w.y);
         e_t1 = static_cast<unsigned int>(w.z);
     }
-    hop_tile<R, DT, S>(a, tile, e_t0, e_t1, stamp, threadIdx.x & 63u, lds_all + static_cast<size_t>(wv) * a.lds_wave);
+    hop_tile<R, DT, S, kBar>(a, tile, e_t0, e_t1, stamp, threadIdx.x & 63u, lds_all + static_cast<size_t>(wv) * a.lds_wave);
 }
 
 // The tiles marked for forward step `hop` (tile mark == its stamp), listed with

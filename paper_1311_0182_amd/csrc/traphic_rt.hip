@@ -131,6 +131,9 @@ struct rt_ctx {
     double* Fp = nullptr;                 // [N][nf] photons resting in the bins
     unsigned long long* xr_fx = nullptr;  // [n_inst][nf][2][3] escaped, removed (fixed point)
     double* Ufx = nullptr;                // [n_inst] mean N_H: unit of xr_fx
+    double* bar_d = nullptr;              // [n_inst][4] barrier disks (radius 0: none)
+    std::vector<double> bar;              // host copy
+    bool any_bar = false;                 // some instance has a barrier
     Vip* vip[2] = {nullptr, nullptr};
     Vip* deep = nullptr;        // chains that landed inside their box, and their points
     double* deep_x = nullptr;
@@ -281,7 +284,7 @@ void direction_set(int n, std::vector<double>& u) {
 
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
-template <typename R, typename DT, typename S>
+template <typename R, typename DT, typename S, bool kBar>
 rt_status launch_hop(rt_ctx* c, int hop, bool pack) {
     HopArgs<R, DT> a{};
     a.N = c->N;
@@ -362,16 +365,19 @@ rt_status launch_hop(rt_ctx* c, int hop, bool pack) {
     a.lds_wave = static_cast<unsigned int>(lds_wave);
     const size_t lds = lds_wave * wpb;
     const long long n_wg = (c->ntiles + wpb - 1) / wpb;
-    hipLaunchKernelGGL((k_hop<R, DT, S>), dim3(static_cast<unsigned>(n_wg)), dim3(64 * wpb), lds, c->stream, a);
+    hipLaunchKernelGGL((k_hop<R, DT, S, kBar>), dim3(static_cast<unsigned>(n_wg)), dim3(64 * wpb), lds, c->stream, a);
     HIPCHK(c, hipGetLastError());
     return RT_OK;
 }
 
 
-template <typename S>
+template <typename S, bool kBar = false>
 rt_status launch_hop_shape(rt_ctx* c, int hop, bool pack) {
-    if (c->f32) return c->dl64 ? launch_hop<float, unsigned long long, S>(c, hop, pack) : launch_hop<float, unsigned int, S>(c, hop, pack);
-    return c->dl64 ? launch_hop<double, unsigned long long, S>(c, hop, pack) : launch_hop<double, unsigned int, S>(c, hop, pack);
+    if (c->f32)
+        return c->dl64 ? launch_hop<float, unsigned long long, S, kBar>(c, hop, pack)
+                       : launch_hop<float, unsigned int, S, kBar>(c, hop, pack);
+    return c->dl64 ? launch_hop<double, unsigned long long, S, kBar>(c, hop, pack)
+                   : launch_hop<double, unsigned int, S, kBar>(c, hop, pack);
 }
 
 // shape: the tuned one, or (during tuning) the one this forward step times
@@ -379,6 +385,10 @@ rt_status launch_hop_any(rt_ctx* c, int hop, int shape = -1) {
     if (shape < 0) shape = c->hop_shape;
     const bool pack = shape >= kHopShapeKinds;
     const int kind = shape % kHopShapeKinds;
+    // with a barrier disk the forward step runs the barrier-aware kernel,
+    // built in the default staging shape only (256 edges, 128 pairs a round):
+    // the configurations differ in packing alone
+    if (c->any_bar) return launch_hop_shape<HopShape0, true>(c, hop, pack);
     if (kind == 1) return launch_hop_shape<HopShape1>(c, hop, pack);
     if (kind == 2) return launch_hop_shape<HopShape2>(c, hop, pack);
     return launch_hop_shape<HopShape0>(c, hop, pack);
@@ -413,6 +423,7 @@ rt_status launch_vip(rt_ctx* c, int hop) {
     a.ecd = c->ecd;
     a.xr_fx = c->xr_fx;
     a.Ufx = c->Ufx;
+    a.bar = c->any_bar ? c->bar_d : nullptr;
     a.exs = c->exs;
     a.ers = c->ers;
     a.rec = c->rec;
@@ -611,6 +622,7 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
         ea.cnt = c->cnt;
         ea.xr_fx = c->xr_fx;
         ea.Ufx = c->Ufx;
+        ea.bar = c->any_bar ? c->bar_d : nullptr;
         hipLaunchKernelGGL(k_emit, dim3(grid_for(c->n_emit * c->nsub * c->K, 256)), dim3(256), 0, c->stream, ea);
         HIPCHK(c, hipGetLastError());
     }
@@ -1012,7 +1024,15 @@ rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, cons
     ITRY(alloc_n(c, &c->xr_fx, 6ll * n_inst * c->nf));
     HIPCHK(c, hipMemsetAsync(c->xr_fx, 0, sizeof(unsigned long long) * 6 * n_inst * c->nf, c->stream));
     ITRY(upload(c, &c->Ufx, mean_NH.data(), n_inst));
-    c->vip_cap = p->vip_capacity > 0 ? p->vip_capacity : std::max<long long>(1 << 16, c->B / 8);
+    c->bar.assign(4 * static_cast<size_t>(n_inst), 0.0);
+    ITRY(upload(c, &c->bar_d, c->bar.data(), 4ll * n_inst));
+    // default: room for every slot whose transmission cone is empty, the
+    // chance of which is (1 - 1/N_TC)^N_ngb for neighbours spread evenly over
+    // directions (a cone covers 1/N_TC of the sphere): ~5% at N_TC = 16,
+    // ~70% at N_TC = 128 with 48 neighbours
+    const double f_empty = std::pow(1.0 - 1.0 / p->n_tc, static_cast<double>(p->n_ngb));
+    c->vip_cap = p->vip_capacity > 0 ? p->vip_capacity
+                                     : std::max({1ll << 16, c->B / 8, static_cast<long long>(std::ceil(c->B * f_empty))});
     c->rec_cap = p->record_capacity > 0 ? p->record_capacity : std::max<long long>(1 << 20, c->vip_cap * 4);
     if (c->rec_cap >= (1ll << 31)) c->rec_cap = (1ll << 31) - 1;
     for (int b = 0; b < 2; ++b) ITRY(alloc_n(c, &c->vip[b], c->vip_cap));
@@ -1387,6 +1407,31 @@ rt_status rt_shell_profile_noalloc(rt_ctx* c, int32_t inst, const double* passin
     unsigned long long* cnt_d = reinterpret_cast<unsigned long long*>(base + sizeof(double) * kProfMaxCells);
     return shell_profile_run(c, inst, Pd, center, axis, half_height, r_max, n_shells, mean, norm, sum, cnt_d, prof,
                              count);
+}
+
+rt_status rt_set_barrier(rt_ctx* c, int32_t inst, const double* center, double radius) {
+    if (!c) return RT_EINVAL;
+    if (c->sticky) return RT_EDEVICE;
+    if (inst < 0 || inst >= c->n_inst || (radius > 0.0 && !center) || !(radius >= 0.0) || !std::isfinite(radius))
+        return fail(c, RT_EINVAL, "barrier: bad instance, centre or radius");
+    if (radius > 0.0)
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(center[a])) return fail(c, RT_EINVAL, "barrier: centre must be finite");
+    for (int a = 0; a < 3; ++a) c->bar[4 * inst + a] = radius > 0.0 ? center[a] : 0.0;
+    c->bar[4 * inst + 3] = radius;
+    c->any_bar = false;
+    for (int k = 0; k < c->n_inst; ++k) c->any_bar = c->any_bar || c->bar[4 * k + 3] > 0.0;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(c->bar_d, c->bar.data(), sizeof(double) * c->bar.size(), hipMemcpyHostToDevice));
+    if (c->f32)
+        hipLaunchKernelGGL(k_barrier_edges<float4>, dim3(grid_for(c->N, 256)), dim3(256), 0, c->stream, c->N, c->pos,
+                           c->rev_off, c->rev_ik, c->inst_of, c->bar_d, static_cast<float4*>(c->rev_v));
+    else
+        hipLaunchKernelGGL(k_barrier_edges<double4>, dim3(grid_for(c->N, 256)), dim3(256), 0, c->stream, c->N, c->pos,
+                           c->rev_off, c->rev_ik, c->inst_of, c->bar_d, static_cast<double4*>(c->rev_v));
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return RT_OK;
 }
 
 rt_status rt_get_bins(rt_ctx* c, double* N, double* dir, double* clock) {

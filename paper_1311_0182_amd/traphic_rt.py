@@ -26,7 +26,7 @@ DEALLOC_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 EXPORTS = ["rt_init", "rt_add_sources", "rt_step", "rt_get_state", "rt_get_bins", "rt_get_neighbours",
            "rt_n_emitters", "rt_get_emitter_neighbours", "rt_get_cone_masks", "rt_get_pending_rr",
            "rt_set_timing", "rt_get_timing", "rt_set_hop_shape", "rt_get_hop_shape", "rt_get_state_blob",
-           "rt_set_state_blob", "rt_shell_profile", "rt_shell_profile_noalloc", "rt_destroy",
+           "rt_set_state_blob", "rt_shell_profile", "rt_shell_profile_noalloc", "rt_set_barrier", "rt_destroy",
            "rt_last_error"]
 
 
@@ -101,6 +101,8 @@ def load():
     L.rt_shell_profile_noalloc.restype = C.c_int
     L.rt_shell_profile_noalloc.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, dp, dp, C.c_double, C.c_double,
                                            C.c_int32, C.c_int32, C.c_double, dp, i64p]
+    L.rt_set_barrier.restype = C.c_int
+    L.rt_set_barrier.argtypes = [C.c_void_p, C.c_int32, dp, C.c_double]
     L.rt_destroy.restype = None
     L.rt_destroy.argtypes = [C.c_void_p]
     L.rt_last_error.restype = C.c_char_p
@@ -190,6 +192,9 @@ class Context:
         self.h = h
         if add_sources and cfg.get("sources") is not None:
             self.add_sources(cfg["sources"])
+        if cfg.get("barrier") is not None:
+            b = cfg["barrier"]
+            self.set_barrier(b["inst"], b["center"], b["radius"])
 
     def _check(self, st, allow=()):
         if st != RT_OK and st not in allow:
@@ -204,6 +209,10 @@ class Context:
         ns = np.ascontiguousarray(s["n_side"], dtype=np.int32)
         return self._check(load().rt_add_sources(self.h, len(inst), _p(inst, C.c_int32), _p(kind, C.c_int32),
                                                  _p(pos, C.c_double), _p(rate, C.c_double), _p(ns, C.c_int32)))
+
+    def set_barrier(self, inst, center, radius):
+        c = _f64(np.asarray(center, dtype=np.float64).reshape(3))
+        return self._check(load().rt_set_barrier(self.h, int(inst), _p(c, C.c_double), float(radius)))
 
     def step(self, n=1, allow=(RT_EHOPCAP,)):
         return self._check(load().rt_step(self.h, int(n)), allow)
