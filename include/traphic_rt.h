@@ -75,7 +75,8 @@ typedef struct {
     int32_t n_em;          /* emission sub-steps per step (dt / dt_em), >= 1 */
     int32_t max_hops;      /* cap on forward steps per RT step, >= 0 */
     int32_t max_vip_depth; /* virtual particles chained at most this deep, 1..15 */
-    int32_t hop_batch;     /* forward steps enqueued between termination checks (0: 8) */
+    int32_t hop_batch;     /* forward steps enqueued between termination checks (0: one
+                              more than the previous step needed, then one at a time) */
     double dt;             /* RT and chemistry step, s */
     double floor_rel;      /* packets below floor_rel * N_H of their particle are absorbed there */
     double chem_frac;      /* chemistry sub-step: max relative change of x_HI or T */

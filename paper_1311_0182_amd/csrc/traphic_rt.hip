@@ -632,10 +632,10 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
     TRY(launch_hop_any(c, 0));
     TRY(time_end(c, 3));
     // Forward steps are enqueued in batches between host checks of the device
-    // counters.  Automatic batching starts with the previous step's count less
-    // a margin, then goes one step at a time, so that almost no launch finds
-    // the step already finished.
-    int batch = c->p.hop_batch > 0 ? c->p.hop_batch : std::max(1, static_cast<int>(c->last_hops) - 3);
+    // counters.  Automatic batching enqueues one more than the previous step
+    // needed (a step rarely needs more than one extra: launches past the end
+    // exit at once, cheaper than a host round trip), then goes one at a time.
+    int batch = c->p.hop_batch > 0 ? c->p.hop_batch : std::max(1, static_cast<int>(c->last_hops) + 1);
     long long H = 0;
     int h = 1;
     for (;;) {
