@@ -27,7 +27,8 @@ emission and the photon ledger.
             bytes per launch from hardware counters (profiles/), if they were
             taken on the current kernel sources.
 
-Extra rows: the 64^3 Stromgren workload (FP32 vs FP64), the 128^3 shadow
+Extra rows: the 64^3 Stromgren workload (FP32 vs FP64), the two schemes of
+emitting recombination radiation on it (section 2.2), the 128^3 shadow
 set-up (three blackbody bins + RR, N_TC = N_RC = N_EC = 16, heating and
 cooling; FP32 vs FP64), the batch solved one instance at a time in FP64, the
 intensity-profile diagnostic and the CPU oracle (the baseline, not the
@@ -209,6 +210,39 @@ def shell_profile_timing(ctx, cfg, reps=50):
     return out
 
 
+def rr_scheme_row(cfg, W, K):
+    """Section 2.2's comparison on one workload: recombination photons emitted
+    into the reception cones against the predecessor scheme (every particle a
+    point source with its own rotated emission cones on every emission
+    sub-step), FP32 transport, the same steps; the emission's share of the step
+    (time split with every launch timed) and the ionization state reached."""
+    import numpy as np
+    from paper_1311_0182_amd import inputs as I
+    out = {}
+    states = {}
+    for name, mode in (("reception_cones", I.RR_TRANSPORT), ("predecessor", I.RR_ORIGINAL)):
+        c = dict(cfg)
+        c["params"] = dict(cfg["params"], recomb_mode=mode)
+        sh = tuned_shape(c, W + K)["shape"]
+        r = run_timed(c, "fp32", W, K, shape=sh)
+        r["ctx"].close()
+        rt = run_timed(c, "fp32", W, K, timing=True, shape=sh)
+        tm = rt["timing"]
+        rt["ctx"].close()
+        states[name] = r["state"]
+        out[name] = {"ms_per_step": r["t"] / K * 1e3, "updates_per_s": r["updates"] / r["t"],
+                     "rr_photons_emitted": float(r["state"]["ledger"][0, 1, 0]),
+                     "time_split_ms_per_step": {k: tm[k] / K for k in ("hop_ms", "vip_ms", "chem_ms", "emit_ms",
+                                                                       "ledger_ms")}}
+        print(f"RR scheme {name}: {r['t'] / K * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+    out["predecessor_over_reception_cones_time"] = (out["predecessor"]["ms_per_step"] /
+                                                    out["reception_cones"]["ms_per_step"])
+    out["max_abs_dx_HI_between_schemes"] = float(np.max(np.abs(states["predecessor"]["xHI"] -
+                                                                states["reception_cones"]["xHI"])))
+    out["steps"] = f"{W}..{W + K - 1}"
+    return out
+
+
 def pair_row(cfg, W, K, label):
     """FP32 and FP64 over the same window: rates (work counted on FP64), the
     forward-step kernel's time per launch and the dense-model bandwidth, and
@@ -262,7 +296,7 @@ def main():
     ap.add_argument("--headline-only", action="store_true", help="skip the extra rows")
     ap.add_argument("--hop-shape", type=int, default=-1,
                     help="forward-step launch configuration 0..5 for every run (-1: the library's tuner picks)")
-    ap.add_argument("--only", choices=["stromgren64_rr", "shadow128"], default=None,
+    ap.add_argument("--only", choices=["stromgren64_rr", "shadow128", "rr_schemes"], default=None,
                     help="run one extra row alone and print it (for profiling); no headline line")
     ap.add_argument("--c3-warmup", type=int, default=2)
     ap.add_argument("--c3-steps", type=int, default=3)
@@ -294,6 +328,9 @@ def main():
     FORCE_SHAPE = args.hop_shape
     if args.only == "stromgren64_rr":
         print(json.dumps({"stromgren64_rr": pair_row(I.config(2), W, K, "64^3 Stromgren with RR")}), flush=True)
+        return
+    if args.only == "rr_schemes":
+        print(json.dumps({"rr_schemes_stromgren64": rr_scheme_row(I.config(2), W, K)}), flush=True)
         return
     if args.only == "shadow128":
         print(json.dumps({"shadow128": pair_row(I.config(3), args.c3_warmup, args.c3_steps, "128^3 shadow set-up")}),
@@ -394,6 +431,7 @@ def main():
         rp = run_timed(c2, "fp32", W, K)
         out["stromgren64_rr"]["shell_profile"] = shell_profile_timing(rp["ctx"], c2)
         rp["ctx"].close()
+        out["rr_schemes_stromgren64"] = rr_scheme_row(c2, W, K)
         c3 = I.config(3)
         out["shadow128"] = pair_row(c3, args.c3_warmup, args.c3_steps,
                                     "128^3 shadow set-up (2097152 particles, plane front, 3 blackbody bins + RR, "

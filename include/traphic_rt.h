@@ -50,8 +50,11 @@ typedef enum {
 } rt_status;
 
 /* Treatment of recombinations (section 2.1 "case B with on-the-spot", "case A";
- * section 2.2 explicit transport of the ground-state recombination photons). */
-enum { RT_CASE_B_OTS = 0, RT_CASE_A_NO_RR = 1, RT_RR_TRANSPORT = 2 };
+ * section 2.2 explicit transport of the ground-state recombination photons,
+ * emitted into the reception cones; RT_RR_ORIGINAL: the predecessor scheme that
+ * section 2.2 compares with, every particle emitting them like a point source
+ * in N_EC emission cones rotated per particle and emission sub-step). */
+enum { RT_CASE_B_OTS = 0, RT_CASE_A_NO_RR = 1, RT_RR_TRANSPORT = 2, RT_RR_ORIGINAL = 3 };
 /* Arithmetic of the packet transport, absorption and merging.  Positions,
  * chemistry and the photon ledger are FP64 in both. */
 enum { RT_FP64 = 0, RT_FP32 = 1 };
@@ -68,7 +71,7 @@ typedef struct {
     int32_t n_ec;          /* emission cones of point sources, 1..64 */
     int32_t n_freq;        /* grey frequency bins, 1..15 */
     int32_t rr_bin;        /* bin that carries RR photons, or -1 */
-    int32_t recomb_mode;   /* RT_CASE_B_OTS, RT_CASE_A_NO_RR or RT_RR_TRANSPORT */
+    int32_t recomb_mode;   /* RT_CASE_B_OTS, RT_CASE_A_NO_RR, RT_RR_TRANSPORT or RT_RR_ORIGINAL */
     int32_t isothermal;    /* 1: T fixed; 0: photoheating and radiative cooling */
     int32_t freeze_chem;   /* 1: ionization state and T frozen (transport-only runs) */
     int32_t precision;     /* RT_FP64 or RT_FP32 */

@@ -19,7 +19,7 @@ constexpr int kMaxNgb = 64;
 constexpr uint32_t kVipAttempts = 65536;
 
 // Purposes of random draws (first counter word).
-enum : uint32_t { kTagRC = 1, kTagEC = 2, kTagVipT = 3, kTagVipE = 4 };
+enum : uint32_t { kTagRC = 1, kTagEC = 2, kTagVipT = 3, kTagVipE = 4, kTagRREC = 5, kTagVipRR = 6 };
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two

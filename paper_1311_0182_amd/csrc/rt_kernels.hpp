@@ -568,7 +568,178 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
     }
 }
 
+// The predecessor scheme of emitting recombination radiation (section 2.2),
+// kept to compare with the reception-cone scheme: every particle with RR
+// photons from its last chemistry step emits them like a point source, in the
+// Voronoi cells of N_EC directions rotated afresh per particle and emission
+// sub-step, into its own neighbours (clock 0); empty cells become virtual
+// particles.  k_rr_send (thread per particle and sub-step) assigns the
+// neighbours to cells and leaves each edge's share and cell on the edge's
+// receiver-sorted index; k_rr_recv (thread per particle) attenuates the legs
+// arriving at the particle in edge order and sums the packets entering each
+// reception cone of the RR bin, which the first forward step merges.
+struct RrArgs {
+    long long N;
+    int K, nf, nrc, nec, nsub, rr_bin;
+    uint64_t seed;
+    uint32_t step;
+    long long m0;               // key index of particle 0's emission (after the sources)
+    const double* u_ec;
+    const double* pos;
+    const double* h;
+    const int* ngb;
+    const int* inst_of;
+    const void* fwd_v;          // fourth component: the edge's receiver-sorted index
+    int f32;
+    const int* rev_off;
+    const unsigned int* rev_ik;
+    const double* nrr_prev;
+    const double* xHI;
+    const double* nH;
+    const double* sigma;
+    const double* wrc;          // rotated reception directions of this step
+    const double* bar;
+    double* rr_ecd;             // [N][nsub][nec][3] rotated emission directions
+    double* rr_share;           // [edges][nsub] photons per leg (0: none)
+    unsigned char* rr_cone;     // [edges][nsub] the leg's cell
+    double* rr_pre;             // [N][nrc][6] sums of arrivals: N, N d (3), N c, count
+    double* A;
+    double* P;
+    Vip* vip;
+    long long vip_cap;
+    unsigned long long* xr_fx;
+    const double* Ufx;
+    long long* cnt;
+};
+
+__global__ __launch_bounds__(64) void k_rr_send(RrArgs a) {
+    __shared__ unsigned char kc_s[64 * kMaxNgb];
+    __shared__ unsigned char cnt_s[64 * 64];
+    const long long t = blockIdx.x * 64ll + threadIdx.x;
+    const bool live = t < a.N * a.nsub;
+    const long long i = live ? t / a.nsub : 0;
+    const int sub = live ? static_cast<int>(t % a.nsub) : 0;
+    const double nrr = live ? a.nrr_prev[i] : 0.0;
+    const bool emit = live && nrr > 0.0;
+    const int nu = a.rr_bin;
+    // N_EC packet updates per emitting particle and sub-step, one atomic per wavefront
+    const unsigned long long be = __ballot(emit);
+    if ((threadIdx.x & 63u) == 0 && be)
+        atomicAdd(reinterpret_cast<unsigned long long*>(&a.cnt[kCntUpdates]),
+                  static_cast<unsigned long long>(__popcll(be)) * static_cast<unsigned long long>(a.nec));
+    const int inst = a.inst_of[i];
+    double removed = 0.0;
+    if (emit) {
+        const double pk = nrr / static_cast<double>(a.nsub * a.nec);
+        double R[9];
+        random_rotation(a.seed, kTagRREC, a.step, static_cast<uint32_t>(i), static_cast<uint32_t>(sub), R);
+        double* E = a.rr_ecd + 3 * ((i * a.nsub + sub) * a.nec);
+        for (int k = 0; k < a.nec; ++k) rotate3(R, a.u_ec + 3 * k, E + 3 * k);
+        unsigned char* kc = kc_s + threadIdx.x * kMaxNgb;
+        unsigned char* cn = cnt_s + threadIdx.x * 64;
+        for (int k = 0; k < a.nec; ++k) cn[k] = 0;
+        const double xi[3] = {a.pos[3 * i], a.pos[3 * i + 1], a.pos[3 * i + 2]};
+        for (int u = 0; u < a.K; ++u) {
+            const long long j = a.ngb[i * a.K + u];
+            const int k = nearest_direction(E, a.nec, a.pos[3 * j] - xi[0], a.pos[3 * j + 1] - xi[1], a.pos[3 * j + 2] - xi[2]);
+            kc[u] = static_cast<unsigned char>(k);
+            cn[k] = static_cast<unsigned char>(cn[k] + 1);
+        }
+        for (int u = 0; u < a.K; ++u) {
+            const long long j = a.ngb[i * a.K + u];
+            const int k = kc[u];
+            long long e;
+            if (a.f32)
+                e = __float_as_int(static_cast<const float4*>(a.fwd_v)[i * a.K + u].w);
+            else
+                e = __double_as_longlong(static_cast<const double4*>(a.fwd_v)[i * a.K + u].w);
+            double share = pk / static_cast<double>(cn[k]);
+            const double xj[3] = {a.pos[3 * j], a.pos[3 * j + 1], a.pos[3 * j + 2]};
+            if (barrier_blocks(a.bar, inst, xi, xj)) {  // the leg meets the barrier: removed
+                removed += share;
+                share = 0.0;
+            }
+            a.rr_share[e * a.nsub + sub] = share;
+            a.rr_cone[e * a.nsub + sub] = static_cast<unsigned char>(k);
+        }
+        for (int k = 0; k < a.nec; ++k) {
+            if (cn[k] != 0) continue;
+            const long long v = push_vip(a.vip, a.cnt, 0, a.vip_cap);
+            if (v < 0) {  // no room: the empty cell's packet leaves the transport as removed
+                removed += pk;
+                continue;
+            }
+            Vip q;
+            q.x[0] = xi[0];
+            q.x[1] = xi[1];
+            q.x[2] = xi[2];
+            q.h = a.h[i];
+            q.d[0] = E[3 * k];
+            q.d[1] = E[3 * k + 1];
+            q.d[2] = E[3 * k + 2];
+            q.N = pk;
+            q.c = 0.0;
+            q.nu = nu;
+            q.inst = inst;
+            q.ec = -2 - static_cast<int>(i * a.nsub + sub);  // its cell: the particle's own direction set
+            q.ek = k;
+            q.tag = kTagVipRR;
+            q.ida = static_cast<unsigned int>(i);
+            q.idb = (static_cast<unsigned int>(sub) << 20) | (static_cast<unsigned int>(k) << 4);
+            q.xr = 0;
+            q.xr_emis = 0;
+            q.key = emis_key(a.m0 + i, sub, nu, 1, k, 0, 0, 0);
+            a.vip[v] = q;
+        }
+    }
+    fx_add3_wave(a.xr_fx, (static_cast<long long>(inst) * a.nf + nu) * 2 + 1, removed / a.Ufx[inst], removed > 0.0, a.cnt);
+}
+
+// thread per particle; each thread's per-cone sums in LDS ([nrc][6] doubles,
+// blockDim.x threads per workgroup)
+__global__ __launch_bounds__(64) void k_rr_recv(RrArgs a) {
+    extern __shared__ __align__(16) unsigned char rr_lds[];
+    const long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (j >= a.N) return;
+    const int nu = a.rr_bin, nrc = a.nrc;
+    double* acc = reinterpret_cast<double*>(rr_lds) + static_cast<size_t>(threadIdx.x) * nrc * 6;
+    for (int q = 0; q < 6 * nrc; ++q) acc[q] = 0.0;
+    const double xj[3] = {a.pos[3 * j], a.pos[3 * j + 1], a.pos[3 * j + 2]};
+    const double sx = a.sigma[nu] * a.xHI[j] * a.nH[j];
+    double Aj = 0.0, Pj = 0.0;
+    for (int e = a.rev_off[j]; e < a.rev_off[j + 1]; ++e) {
+        const long long i = a.rev_ik[e] >> 6;
+        if (!(a.nrr_prev[i] > 0.0)) continue;
+        const double vx = xj[0] - a.pos[3 * i], vy = xj[1] - a.pos[3 * i + 1], vz = xj[2] - a.pos[3 * i + 2];
+        for (int sub = 0; sub < a.nsub; ++sub) {
+            const double share = a.rr_share[static_cast<long long>(e) * a.nsub + sub];
+            if (!(share > 0.0)) continue;
+            const int k = a.rr_cone[static_cast<long long>(e) * a.nsub + sub];
+            const double* d = a.rr_ecd + 3 * ((i * a.nsub + sub) * a.nec + k);
+            const double l = (vx * d[0] + vy * d[1] + vz * d[2]) / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            double nabs, nout;
+            attenuate(share, sx * l, nabs, nout);
+            Aj += nabs;
+            Pj += share;
+            double* s6 = acc + 6 * nearest_direction(a.wrc, nrc, d[0], d[1], d[2]);
+            s6[0] += nout;
+            s6[1] += nout * d[0];
+            s6[2] += nout * d[1];
+            s6[3] += nout * d[2];
+            s6[4] += nout * (0.0 + l / kCLight);
+            s6[5] += 1.0;
+        }
+    }
+    double* pr = a.rr_pre + 6 * j * nrc;
+    for (int q = 0; q < 6 * nrc; ++q) pr[q] = acc[q];
+    if (Pj > 0.0) {
+        a.A[j * a.nf + nu] += Aj;
+        a.P[j * a.nf + nu] += Pj;
+    }
+}
+
 struct VipArgs {
+    const double* rr_ecd;  // direction sets of the predecessor RR scheme (virtual particles with ec <= -2)
     int hop, hop0, max_hops, K, nf, nrc, nec, max_depth;
     long long* dep;  // [N*nf][3] deposited photons of virtual-particle legs, fixed point
     uint64_t seed;
@@ -623,7 +794,12 @@ constexpr int kVipLanes = 4;
 
 __device__ inline bool vip_draw_group(const VipArgs& a, uint32_t step, const Vip& q, bool live, int depth, int sub,
                                       int gshift, double p[3]) {
-    const double* ecs = (q.ec >= 0 && depth == 1) ? a.ecd + 3 * (static_cast<long long>(q.ec) * a.nec) : nullptr;
+    // depth 1 of an emission cone: its Voronoi cell (a source's set, or with
+    // ec <= -2 a particle's set of the predecessor RR scheme)
+    const double* ecs = depth != 1 ? nullptr
+                        : q.ec >= 0 ? a.ecd + 3 * (static_cast<long long>(q.ec) * a.nec)
+                        : q.ec <= -2 ? a.rr_ecd + 3 * ((-2ll - q.ec) * a.nec)
+                                     : nullptr;
     const ConeFrame fr = cone_frame(q.d, a.c2);
     const unsigned long long gm = (kVipLanes >= 64 ? ~0ull : ((1ull << kVipLanes) - 1ull)) << gshift;
     bool done = !live;
@@ -993,6 +1169,7 @@ struct HopArgs {
     const double* U;         // photons per bin unit per instance (1 in FP64)
     const double* scale;     // [n_inst*nf] rescale of in-flight photons at hop 0 (FP32)
     const double* nrr_prev;  // RR photons to emit at hop 0
+    const double* rr_pre;    // predecessor RR scheme: arrivals summed per slot of the RR bin (or null)
     const double* wrc;
     const float* wrcf;
     double dt;
@@ -1295,7 +1472,7 @@ struct HopLds {
 // marks the tiles that will receive it.  Hop 0 of a step also merges what
 // stays (clocks carried over by -dt), the recombination photons of the last
 // chemistry step (section 2.2) and the emission records.
-template <typename R, typename DT, typename S, bool kBar>
+template <typename R, typename DT, typename S, bool kExt>
 __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long long tile, const long long e_t0,
                                          const long long e_t1, const int stamp, const unsigned int tidx,
                                          unsigned char* __restrict__ lds) {
@@ -1412,6 +1589,22 @@ __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long lon
                 else
                     acc_add(acc, per, R(a.wrc[3 * r]), R(a.wrc[3 * r + 1]), R(a.wrc[3 * r + 2]), R(0));
                 ++narr;
+            }
+        }
+        if constexpr (kExt) {
+            if (a.hop0 && a.rr_pre && nu == a.rr_bin) {
+                // the predecessor RR scheme's arrivals in this cone, summed in edge order
+                const double* pr = a.rr_pre + 6 * (j * nrc + r);
+                if (pr[5] > 0.0) {
+                    if constexpr (f32) {
+                        const double iu = 1.0 / U;
+                        acc_addp(acc, static_cast<R>(pr[0] * iu), static_cast<R>(pr[1] * iu), static_cast<R>(pr[2] * iu),
+                                 static_cast<R>(pr[3] * iu), static_cast<R>(pr[4] * iu / a.dt));
+                    } else {
+                        acc_addp(acc, R(pr[0]), R(pr[1]), R(pr[2]), R(pr[3]), R(pr[4]));
+                    }
+                    ++narr;
+                }
             }
         }
     }
@@ -1601,7 +1794,7 @@ __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long lon
                         pval[4 * kP + u] = f32 ? nout * cl : cl;
                         // an edge that meets the barrier removes the packet on the
                         // way (marked by nin = -2, its photons where nabs would be)
-                        const bool cut = kBar && v[i].w != static_cast<decltype(v[i].w)>(0);
+                        const bool cut = kExt && v[i].w != static_cast<decltype(v[i].w)>(0);
                         pval[5 * kP + u] = cut ? q[i].n : nabs;
                         pval[6 * kP + u] = cut ? R(-2) : q[i].n;
                     }
@@ -1620,7 +1813,7 @@ __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long lon
                         const R v0 = pval[u], v1 = pval[kP + u], v2 = pval[2 * kP + u], v3 = pval[3 * kP + u],
                                 v4 = pval[4 * kP + u], v5 = pval[5 * kP + u];
                         const bool ok = nin >= R(0);
-                        if constexpr (kBar) rsum += nin == R(-2) ? v5 : R(0);
+                        if constexpr (kExt) rsum += nin == R(-2) ? v5 : R(0);
                         sum_add(asum, aerr, ok ? v5 : R(0));
                         sum_add(psum, perr, ok ? nin : R(0));
                         acc_addp(acc, ok ? v0 : R(0), ok ? v1 : R(0), ok ? v2 : R(0), ok ? v3 : R(0), ok ? v4 : R(0));
@@ -1628,7 +1821,7 @@ __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long lon
                     } else {
                         const R nin = pval[6 * kP + u];
                         if (nin < R(0)) {
-                            if (kBar && nin == R(-2)) rsum += pval[5 * kP + u];
+                            if (kExt && nin == R(-2)) rsum += pval[5 * kP + u];
                             continue;
                         }
                         sum_add(asum, aerr, pval[5 * kP + u]);
@@ -1736,7 +1929,7 @@ __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long lon
     }
     // arrivals the barrier removed: one set of atomics per (instance, bin),
     // in the (rare) wavefronts that saw any
-    if constexpr (kBar) {
+    if constexpr (kExt) {
         if (__ballot(valid && rsum > R(0)) != 0ull)
             fx_add3_wave(a.xr_fx, (static_cast<long long>(inst) * a.nf + nu) * 2 + 1,
                          valid ? static_cast<double>(rsum) * U / a.Ufx[inst] : 0.0, valid && rsum > R(0), a.cnt);
@@ -1985,9 +2178,10 @@ __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long lon
 // block), so that neighbouring particles share that XCD's L2.  The
 // launch-level flags are read once: a launch past the last forward step of an
 // RT step, or past the cap, runs no tile.
-// kBar: some instance has a barrier disk (its edges carry a flag, see
-// k_barrier_edges); without one the flag is never read
-template <typename R, typename DT, typename S, bool kBar>
+// kExt: the variant for the rarely used features, a barrier disk (its edges
+// carry a flag, see k_barrier_edges) and the predecessor RR scheme's arrivals
+// at the first forward step; the plain variant reads neither
+template <typename R, typename DT, typename S, bool kExt>
 __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
     extern __shared__ __align__(32) unsigned char lds_all[];
     const long long c_done = a.cnt[kCntDone];
@@ -2034,7 +2228,7 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
         e_t0 = static_cast<unsigned int>(w.y);
         e_t1 = static_cast<unsigned int>(w.z);
     }
-    hop_tile<R, DT, S, kBar>(a, tile, e_t0, e_t1, stamp, threadIdx.x & 63u, lds_all + static_cast<size_t>(wv) * a.lds_wave);
+    hop_tile<R, DT, S, kExt>(a, tile, e_t0, e_t1, stamp, threadIdx.x & 63u, lds_all + static_cast<size_t>(wv) * a.lds_wave);
 }
 
 // The tiles marked for forward step `hop` (tile mark == its stamp), listed with

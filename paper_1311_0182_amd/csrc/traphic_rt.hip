@@ -52,7 +52,7 @@ struct rt_ctx {
 
     long long N = 0, B = 0;
     int n_inst = 0, G = 0, nf = 0, K = 0, nrc = 0, nec = 0, nsub = 1;
-    bool f32 = false, rr_on = false;
+    bool f32 = false, rr_on = false, rr_orig = false;  // RR photons produced; predecessor scheme
     double c2 = 0.0;
     std::vector<long long> inst_off;
     std::vector<double> box, sigma, eps, U, L;
@@ -132,6 +132,13 @@ struct rt_ctx {
     unsigned long long* xr_fx = nullptr;  // [n_inst][nf][2][3] escaped, removed (fixed point)
     double* Ufx = nullptr;                // [n_inst] mean N_H: unit of xr_fx
     double* bar_d = nullptr;              // [n_inst][4] barrier disks (radius 0: none)
+    // predecessor RR scheme: rotated directions per particle and sub-step,
+    // per edge and sub-step the leg's photons and cell, per slot of the RR bin
+    // the arrivals' sums
+    double* rr_ecd = nullptr;
+    double* rr_share = nullptr;
+    unsigned char* rr_cone = nullptr;
+    double* rr_pre = nullptr;
     std::vector<double> bar;              // host copy
     bool any_bar = false;                 // some instance has a barrier
     Vip* vip[2] = {nullptr, nullptr};
@@ -294,7 +301,8 @@ rt_status launch_hop(rt_ctx* c, int hop, bool pack) {
     a.K = c->K;
     a.T = c->tileT;
     a.rr_bin = c->p.rr_bin;
-    a.rr_on = c->rr_on ? 1 : 0;
+    a.rr_on = c->rr_on && !c->rr_orig ? 1 : 0;  // into the reception cones
+    a.rr_pre = c->rr_orig ? c->rr_pre : nullptr;
     a.hop = hop;
     a.hop0 = hop == 0;
     a.max_hops = c->p.max_hops;
@@ -385,10 +393,10 @@ rt_status launch_hop_any(rt_ctx* c, int hop, int shape = -1) {
     if (shape < 0) shape = c->hop_shape;
     const bool pack = shape >= kHopShapeKinds;
     const int kind = shape % kHopShapeKinds;
-    // with a barrier disk the forward step runs the barrier-aware kernel,
-    // built in the default staging shape only (256 edges, 128 pairs a round):
-    // the configurations differ in packing alone
-    if (c->any_bar) return launch_hop_shape<HopShape0, true>(c, hop, pack);
+    // with a barrier disk or the predecessor RR scheme the forward step runs
+    // the extended kernel, built in the default staging shape only (256
+    // edges, 128 pairs a round): the configurations differ in packing alone
+    if (c->any_bar || c->rr_orig) return launch_hop_shape<HopShape0, true>(c, hop, pack);
     if (kind == 1) return launch_hop_shape<HopShape1>(c, hop, pack);
     if (kind == 2) return launch_hop_shape<HopShape2>(c, hop, pack);
     return launch_hop_shape<HopShape0>(c, hop, pack);
@@ -421,6 +429,7 @@ rt_status launch_vip(rt_ctx* c, int hop) {
     a.sigma = c->sigma_d;
     a.wrc = c->rot + 9;
     a.ecd = c->ecd;
+    a.rr_ecd = c->rr_ecd;
     a.xr_fx = c->xr_fx;
     a.Ufx = c->Ufx;
     a.bar = c->any_bar ? c->bar_d : nullptr;
@@ -554,6 +563,55 @@ rt_status launch_hops_graph(rt_ctx* c, int n, bool* done) {
 
 // One RT step (sections 2.1 and 2.2): rotations, emission, forward steps
 // until no packet is active, chemistry, ledger.
+// The predecessor RR scheme's emission (before the first forward step):
+// legs and cells from every emitting particle, then the arrivals per slot.
+rt_status launch_rr_original(rt_ctx* c) {
+    if (c->n_emit + c->N >= (1ll << 27)) return fail(c, RT_EINVAL, "predecessor RR scheme: too many emitters and particles");
+    RrArgs r{};
+    r.N = c->N;
+    r.K = c->K;
+    r.nf = c->nf;
+    r.nrc = c->nrc;
+    r.nec = c->nec;
+    r.nsub = c->nsub;
+    r.rr_bin = c->p.rr_bin;
+    r.seed = c->p.seed;
+    r.step = static_cast<uint32_t>(c->step);
+    r.m0 = c->n_emit;
+    r.u_ec = c->u_ec;
+    r.pos = c->pos;
+    r.h = c->h;
+    r.ngb = c->ngb;
+    r.inst_of = c->inst_of;
+    r.fwd_v = c->fwd_v;
+    r.f32 = c->f32 ? 1 : 0;
+    r.rev_off = c->rev_off;
+    r.rev_ik = c->rev_ik;
+    r.nrr_prev = c->nrr[c->nrr_cur];
+    r.xHI = c->xHI;
+    r.nH = c->nH;
+    r.sigma = c->sigma_d;
+    r.wrc = c->rot + 9;
+    r.bar = c->any_bar ? c->bar_d : nullptr;
+    r.rr_ecd = c->rr_ecd;
+    r.rr_share = c->rr_share;
+    r.rr_cone = c->rr_cone;
+    r.rr_pre = c->rr_pre;
+    r.A = c->A;
+    r.P = c->P;
+    r.vip = c->vip[0];
+    r.vip_cap = c->vip_cap;
+    r.xr_fx = c->xr_fx;
+    r.Ufx = c->Ufx;
+    r.cnt = c->cnt;
+    hipLaunchKernelGGL(k_rr_send, dim3(grid_for(c->N * c->nsub, 64)), dim3(64), 0, c->stream, r);
+    HIPCHK(c, hipGetLastError());
+    const int tpb = c->nrc <= 16 ? 64 : 32;  // LDS: tpb * nrc * 48 bytes
+    hipLaunchKernelGGL(k_rr_recv, dim3(grid_for(c->N, tpb)), dim3(tpb), static_cast<size_t>(tpb) * c->nrc * 48, c->stream, r);
+    HIPCHK(c, hipGetLastError());
+    return RT_OK;
+}
+
 rt_status one_step(rt_ctx* c, bool* hopcap) {
     // The autotuner times the forward-step shapes on steps whose work is
     // representative (at least 16 forward steps in the previous step),
@@ -626,6 +684,7 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
         hipLaunchKernelGGL(k_emit, dim3(grid_for(c->n_emit * c->nsub * c->K, 256)), dim3(256), 0, c->stream, ea);
         HIPCHK(c, hipGetLastError());
     }
+    if (c->rr_orig) TRY(launch_rr_original(c));
     TRY(launch_vip(c, 0));
     TRY(time_end(c, 0));
     TRY(time_begin(c, 3));
@@ -789,7 +848,8 @@ rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, cons
     *out = nullptr;
     if (p->n_ngb < 1 || p->n_ngb > kMaxNgb || p->n_tc < 3 || !pow2(p->n_rc) || p->n_rc > 32 || p->n_ec < 1 ||
         p->n_ec > 64 || p->n_freq < 1 || p->n_freq > 15 || p->rr_bin >= p->n_freq || p->rr_bin < -1 ||
-        p->recomb_mode < 0 || p->recomb_mode > 2 || (p->recomb_mode == RT_RR_TRANSPORT && p->rr_bin < 0) ||
+        p->recomb_mode < 0 || p->recomb_mode > 3 ||
+        ((p->recomb_mode == RT_RR_TRANSPORT || p->recomb_mode == RT_RR_ORIGINAL) && p->rr_bin < 0) ||
         p->precision < 0 || p->precision > 1 || p->n_em < 1 || p->n_em > 4095 || p->max_hops < 0 ||
         p->max_hops > 4095 || p->max_vip_depth < 1 || p->max_vip_depth > 15 || !(p->dt > 0.0) ||
         !(p->floor_rel >= 0.0) || !(p->chem_frac > 0.0) || n_inst < 1)
@@ -840,7 +900,8 @@ rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, cons
         c->tileT = T;
         while ((1 << c->lgT) < T) ++c->lgT;
     }
-    c->rr_on = p->recomb_mode == RT_RR_TRANSPORT;
+    c->rr_on = p->recomb_mode == RT_RR_TRANSPORT || p->recomb_mode == RT_RR_ORIGINAL;
+    c->rr_orig = p->recomb_mode == RT_RR_ORIGINAL;
     const double cc = 1.0 - 2.0 / static_cast<double>(p->n_tc);
     c->c2 = cc * cc;
     c->inst_off.assign(inst_off, inst_off + n_inst + 1);
@@ -1012,6 +1073,12 @@ rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, cons
         ITRY(alloc_n(c, &c->nrr[b], N));
         ITRY(fill_f64(c, c->nrr[b], N, 0.0));
         ITRY(alloc_n(c, &c->head[b], N));
+    }
+    if (c->rr_orig) {
+        ITRY(alloc_n(c, &c->rr_ecd, 3ll * N * c->nsub * c->nec));
+        ITRY(alloc_n(c, &c->rr_share, N * c->K * static_cast<long long>(c->nsub)));
+        ITRY(alloc_n(c, &c->rr_cone, N * c->K * static_cast<long long>(c->nsub)));
+        ITRY(alloc_n(c, &c->rr_pre, 6ll * N * c->nrc));
     }
     ITRY(alloc_n(c, &c->A, N * c->nf));
     ITRY(alloc_n(c, &c->P, N * c->nf));

@@ -37,7 +37,7 @@ SIGMA_13P6 = 6.3e-18          # cm^2, hydrogen cross-section at 13.6 eV (section
 ALPHA_B_1E4 = 2.59e-13        # cm^3/s, only to size batched boxes (R_S/L recipe)
 
 # Enumerations mirrored from include/traphic_rt.h
-CASE_B_OTS, CASE_A_NO_RR, RR_TRANSPORT = 0, 1, 2
+CASE_B_OTS, CASE_A_NO_RR, RR_TRANSPORT, RR_ORIGINAL = 0, 1, 2, 3
 FP64, FP32 = 0, 1
 SRC_POINT, SRC_PLANE_XLO = 0, 1
 
