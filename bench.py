@@ -110,7 +110,7 @@ def tuned_shape(cfg, steps, precision="fp32"):
     return out
 
 
-def run_timed(cfg, precision, W, K, timing=False, shape=None):
+def run_timed(cfg, precision, W, K, timing=False, shape=None, step_graphs=False):
     import torch
     from paper_1311_0182_amd import traphic_rt as RT
     ctx = RT.Context(cfg, precision=precision)
@@ -118,6 +118,8 @@ def run_timed(cfg, precision, W, K, timing=False, shape=None):
         shape = FORCE_SHAPE
     if shape is not None:
         ctx.set_hop_shape(shape)
+    if step_graphs:
+        ctx.set_step_graphs(True)
     if W:
         ctx.step(W)
     s0 = ctx.state()
@@ -415,6 +417,13 @@ def main():
     if not acc["met"]:
         out["value_bar_missed"] = rate
     if not args.headline_only:
+        # the same timed steps with whole-step graphs (one host check per call)
+        rg = run_timed(cfg, "fp32", W, K, shape=shape["shape"], step_graphs=True)
+        rg["ctx"].close()
+        out["whole_step_graphs"] = {"ms_per_step": rg["t"] / K * 1e3, "updates_per_s": work / rg["t"],
+                                    "same_updates": rg["updates"] == r32["updates"],
+                                    "time_vs_default": rg["t"] / r32["t"]}
+        print(f"whole-step graphs: {rg['t'] / K * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
         # the same instances solved one after another in FP64
         tseq, useq = 0.0, 0
         for k in range(n_inst):

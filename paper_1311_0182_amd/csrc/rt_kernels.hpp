@@ -40,9 +40,13 @@ enum : int {
     // read at the start of every launch, written rarely
     kCntDone = 32,     // set once a forward step finds no active packet; later launches of the step exit
     kCntSerial = 33,   // stamp of hop 0 of the current RT step (stamps number the forward steps of the run)
+    kCntHalt = 34,     // nonzero: every step kernel exits at once (1: a step needs more forward steps
+                       // than its graph holds; 2: a step raised an error flag; the forward step
+                       // tests the done flag, set with it); cleared by the host
     // per-step tallies
     kCntBytes = 40,    // algorithmic bytes moved by forward steps (for the roofline)
     kCntTiles = 41,    // forward-step tiles processed
+    kCntLastHops = 42, // forward steps the last finished RT step ran
     // marked tiles listed for a forward step, ping-pong by its parity: added to
     // by k_tile_list, read by the forward step, cleared by the one before
     kCntTileList = 48,  // [48], [49]
@@ -282,8 +286,9 @@ __global__ void k_barrier_edges(long long N, const double* __restrict__ pos, con
 // ---------------------------------------------------------------- per step --
 
 struct StepBeginArgs {
+    int halt_on;  // steps replayed from a graph: exit at once while the halt word is set
+    const long long* cnt;  // the step number (counted at the step's start) and the halt word
     uint64_t seed;
-    uint32_t step;
     int nrc, nec, nsub;
     long long n_emit;
     const double* u_rc;
@@ -295,10 +300,12 @@ struct StepBeginArgs {
 };
 
 __global__ void k_step_rotations(StepBeginArgs a) {
+    if (a.halt_on && a.cnt[kCntHalt] != 0) return;
+    const uint32_t step = static_cast<uint32_t>(a.cnt[kCntSteps] - 1);
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (t == 0) {
         double R[9];
-        random_rotation(a.seed, kTagRC, a.step, 0u, 0u, R);
+        random_rotation(a.seed, kTagRC, step, 0u, 0u, R);
         for (int i = 0; i < 9; ++i) a.rot[i] = R[i];
         for (int q = 0; q < a.nrc; ++q) {
             double w[3];
@@ -314,12 +321,13 @@ __global__ void k_step_rotations(StepBeginArgs a) {
         const int sub = static_cast<int>(t % a.nsub);
         if (a.em_kind[m] != 0) return;  // plane fronts are not rotated
         double R[9];
-        random_rotation(a.seed, kTagEC, a.step, static_cast<uint32_t>(m), static_cast<uint32_t>(sub), R);
+        random_rotation(a.seed, kTagEC, step, static_cast<uint32_t>(m), static_cast<uint32_t>(sub), R);
         for (int k = 0; k < a.nec; ++k) rotate3(R, a.u_ec + 3 * k, a.ecd + 3 * ((t * a.nec) + k));
     }
 }
 
 struct EmitArgs {
+    int halt_on;  // steps replayed from a graph: exit at once while the halt word is set
     long long n_emit;
     int K, nf, nrc, nec, nsub, n_em;
     double c2;
@@ -448,6 +456,7 @@ __device__ inline unsigned long long emis_key(long long m, int sub, int nu, int 
 // rotated direction; a packet is split equally among its cone's members.
 // Plane fronts: one packet along +x into the transmission cone.
 __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
+    if (a.halt_on && a.cnt[kCntHalt] != 0) return;
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (t >= a.n_emit * a.nsub * a.K) return;
     const int mem = static_cast<int>(t % a.K);
@@ -579,10 +588,10 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
 // arriving at the particle in edge order and sums the packets entering each
 // reception cone of the RR bin, which the first forward step merges.
 struct RrArgs {
+    int halt_on;  // steps replayed from a graph: exit at once while the halt word is set
     long long N;
     int K, nf, nrc, nec, nsub, rr_bin;
     uint64_t seed;
-    uint32_t step;
     long long m0;               // key index of particle 0's emission (after the sources)
     const double* u_ec;
     const double* pos;
@@ -615,6 +624,8 @@ struct RrArgs {
 __global__ __launch_bounds__(64) void k_rr_send(RrArgs a) {
     __shared__ unsigned char kc_s[64 * kMaxNgb];
     __shared__ unsigned char cnt_s[64 * 64];
+    if (a.halt_on && a.cnt[kCntHalt] != 0) return;
+    const uint32_t step = static_cast<uint32_t>(a.cnt[kCntSteps] - 1);
     const long long t = blockIdx.x * 64ll + threadIdx.x;
     const bool live = t < a.N * a.nsub;
     const long long i = live ? t / a.nsub : 0;
@@ -632,7 +643,7 @@ __global__ __launch_bounds__(64) void k_rr_send(RrArgs a) {
     if (emit) {
         const double pk = nrr / static_cast<double>(a.nsub * a.nec);
         double R[9];
-        random_rotation(a.seed, kTagRREC, a.step, static_cast<uint32_t>(i), static_cast<uint32_t>(sub), R);
+        random_rotation(a.seed, kTagRREC, step, static_cast<uint32_t>(i), static_cast<uint32_t>(sub), R);
         double* E = a.rr_ecd + 3 * ((i * a.nsub + sub) * a.nec);
         for (int k = 0; k < a.nec; ++k) rotate3(R, a.u_ec + 3 * k, E + 3 * k);
         unsigned char* kc = kc_s + threadIdx.x * kMaxNgb;
@@ -699,6 +710,7 @@ __global__ __launch_bounds__(64) void k_rr_send(RrArgs a) {
 // blockDim.x threads per workgroup)
 __global__ __launch_bounds__(64) void k_rr_recv(RrArgs a) {
     extern __shared__ __align__(16) unsigned char rr_lds[];
+    if (a.halt_on && a.cnt[kCntHalt] != 0) return;
     const long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (j >= a.N) return;
     const int nu = a.rr_bin, nrc = a.nrc;
@@ -739,6 +751,7 @@ __global__ __launch_bounds__(64) void k_rr_recv(RrArgs a) {
 }
 
 struct VipArgs {
+    int halt_on;  // steps replayed from a graph: exit at once while the halt word is set
     const double* rr_ecd;  // direction sets of the predecessor RR scheme (virtual particles with ec <= -2)
     int hop, hop0, max_hops, K, nf, nrc, nec, max_depth;
     long long* dep;  // [N*nf][3] deposited photons of virtual-particle legs, fixed point
@@ -847,6 +860,7 @@ __device__ inline void vip_settle(const VipArgs& a, const Vip& q, int what, doub
 }
 
 __global__ __launch_bounds__(256) void k_vip_sample(VipArgs a) {
+    if (a.halt_on && a.cnt[kCntHalt] != 0) return;
     const long long gid = blockIdx.x * 256LL + threadIdx.x;
     if (!a.hop0) {
         // Once one forward step has found nothing to move, every later launch
@@ -931,6 +945,7 @@ __global__ __launch_bounds__(256) void k_vip_sample(VipArgs a) {
 __global__ __launch_bounds__(256) void k_vip_chain(VipArgs a) {
     __shared__ WaveKnn lds[4];
     __shared__ double rcd[96];  // the step's reception-cone directions
+    if (a.halt_on && a.cnt[kCntHalt] != 0) return;
     if (threadIdx.x < 3 * a.nrc) rcd[threadIdx.x] = a.wrc[threadIdx.x];
     __syncthreads();
     const int lane = threadIdx.x & 63;
@@ -2189,7 +2204,9 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
     const long long c_serial = a.cnt[kCntSerial];
     const long long c_list = a.cnt[kCntTileList + (a.hop & 1)];
     const int stamp = static_cast<int>(c_serial) + a.hop;  // of this forward step
-    const bool idle = (a.hop0 == 0) & ((c_done != 0) | (c_act == 0));
+    // a step halted on the device (steps replayed from graphs) also sets the
+    // done flag, which its hop 0 otherwise never sees: the launch is idle
+    const bool idle = (c_done != 0) | ((a.hop0 == 0) & (c_act == 0));
     const bool capped = (a.hop0 == 0) & !idle & (a.hop > a.max_hops);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (idle) {
@@ -2239,8 +2256,8 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
 // does not depend on the order it runs tiles in).
 __global__ __launch_bounds__(256) void k_tile_list(const int* __restrict__ hot, long long ntiles, int hop, int act_rd,
                                                    const int* __restrict__ rev_off, long long N, int T,
-                                                   int4* __restrict__ tlist, long long* cnt) {
-    if (cnt[kCntDone] != 0 || cnt[kCntAct0 + kCntLine * act_rd] == 0) return;
+                                                   int4* __restrict__ tlist, long long* cnt, int halt_on) {
+    if ((halt_on && cnt[kCntHalt] != 0) || cnt[kCntDone] != 0 || cnt[kCntAct0 + kCntLine * act_rd] == 0) return;
     const int stamp = static_cast<int>(cnt[kCntSerial]) + hop;
     const long long t0 = blockIdx.x * kTileListChunk + threadIdx.x * 16ll;
     const int4* h4 = reinterpret_cast<const int4*>(hot + t0);  // the mark array is padded to whole chunks
@@ -2286,8 +2303,23 @@ __global__ __launch_bounds__(256) void k_tile_list(const int* __restrict__ hot, 
 }
 
 // Adds the tiles' running tallies of an RT step to the counters and clears them.
-__global__ __launch_bounds__(256) void k_step_tally(long long* cnt, unsigned long long* part, long long ntiles) {
+// End of a step's forward steps: the per-tile tallies summed, the stamp base
+// advanced past the forward steps launched, the step's forward-step count kept.
+// graph: the forward steps were a fixed number enqueued in advance; if packets
+// are still active after them, the step is left unfinished (halt 1) for the
+// host to continue, and nothing is tallied.
+__global__ __launch_bounds__(256) void k_step_tally(long long* cnt, unsigned long long* part, long long ntiles,
+                                                    long long launched, int graph) {
     __shared__ unsigned long long s[3][256];
+    if (graph && cnt[kCntHalt] != 0) return;
+    const long long H = cnt[kCntHopsStep];
+    if (graph && cnt[kCntAct0 + kCntLine * ((H + 1) & 1)] != 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            cnt[kCntHalt] = 1;
+            cnt[kCntDone] = 1;  // the forward-step kernel's halt test
+        }
+        return;
+    }
     unsigned long long v[3] = {0, 0, 0};
     for (long long t = blockIdx.x * 256LL + threadIdx.x; t < ntiles; t += gridDim.x * 256LL)
         for (int c = 0; c < 3; ++c) {
@@ -2305,12 +2337,28 @@ __global__ __launch_bounds__(256) void k_step_tally(long long* cnt, unsigned lon
         if (s[0][0]) atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[kCntUpdates]), s[0][0]);
         if (s[1][0]) atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[kCntBytes]), s[1][0]);
         if (s[2][0]) atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[kCntTiles]), s[2][0]);
+        if (blockIdx.x == 0) {
+            cnt[kCntSerial] += launched;
+            cnt[kCntLastHops] = H;
+        }
+    }
+}
+
+// Last kernel of a step: an error flag raised by the step halts the steps
+// enqueued after it (the host reports it).
+__global__ void k_step_end(long long* cnt, int halt_on) {
+    if (!halt_on || threadIdx.x != 0 || cnt[kCntHalt] != 0) return;
+    if (cnt[kCntFlags] & (kFlagVipOverflow | kFlagRecOverflow | kFlagNonFinite | kFlagDrift)) {
+        cnt[kCntHalt] = 2;
+        cnt[kCntDone] = 1;  // the forward-step kernel's halt test
     }
 }
 
 // ------------------------------------------------------------- chemistry --
 
 struct ChemArgs {
+    int halt_on;  // steps replayed from a graph: exit at once while the halt word is set
+    const long long* cnt;
     long long N;
     int nf, mode, isothermal, freeze, rr_on;
     double dt, frac;
@@ -2335,6 +2383,7 @@ struct ChemArgs {
 // d[(1+x)T]/dt = 2 (H - Lambda) / (3 k n_H), H = n_H y sum_nu Gamma_nu eps_nu
 // with the current y.  RR photons: alpha_1 n_e x N_H dt_sub.
 __global__ __launch_bounds__(256) void k_chem(ChemArgs a) {
+    if (a.halt_on && a.cnt[kCntHalt] != 0) return;
     const long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (j >= a.N) return;
     const double nH = a.nH[j], NH = a.NH[j];
@@ -2417,6 +2466,8 @@ __global__ __launch_bounds__(256) void k_chem(ChemArgs a) {
 // ---------------------------------------------------------------- ledger --
 
 struct LedgerArgs {
+    int halt_on;  // steps replayed from a graph: exit at once while the halt word is set
+    const long long* cnt;
     int nf, rr_bin, rr_on;
     long long n_chunks;
     const int* chunk_inst;
@@ -2430,6 +2481,7 @@ struct LedgerArgs {
 
 // Per chunk of one instance's particles: fixed-order partial sums.
 __global__ __launch_bounds__(256) void k_ledger_partial(LedgerArgs a) {
+    if (a.halt_on && a.cnt[kCntHalt] != 0) return;
     const long long c = blockIdx.x;
     const long long lo = a.chunk_lo[c], hi = a.chunk_hi[c];
     __shared__ double red[256];
@@ -2461,6 +2513,8 @@ __global__ __launch_bounds__(256) void k_ledger_partial(LedgerArgs a) {
 constexpr int kEmTallyBlock = 1024;
 
 struct EmitTallyArgs {
+    int halt_on;  // steps replayed from a graph: exit at once while the halt word is set
+    const long long* cnt;
     int nf;
     long long per_em;              // emission cones per emitter and step (sub-steps x N_EC)
     const int* em_by_inst;         // emitter indices grouped by instance
@@ -2472,6 +2526,7 @@ struct EmitTallyArgs {
 
 __global__ __launch_bounds__(kEmTallyBlock) void k_emit_tally(EmitTallyArgs a) {
     __shared__ double sx[kEmTallyBlock], sr[kEmTallyBlock];
+    if (a.halt_on && a.cnt[kCntHalt] != 0) return;
     const int k = blockIdx.x / a.nf, nu = blockIdx.x % a.nf;
     const long long e0 = a.em_ioff[k];
     const long long total = (a.em_ioff[k + 1] - e0) * a.per_em;
@@ -2501,6 +2556,7 @@ __global__ __launch_bounds__(kEmTallyBlock) void k_emit_tally(EmitTallyArgs a) {
 }
 
 struct LedgerFinalArgs {
+    int halt_on;  // steps replayed from a graph: exit at once while the halt word is set
     int n_inst, nf, f32;
     const long long* inst_chunk0;   // [n_inst+1] chunk ranges
     const double* partial;          // [n_chunks][nf][3]: E_rr, A, F
@@ -2514,6 +2570,7 @@ struct LedgerFinalArgs {
 };
 
 __global__ void k_ledger_final(LedgerFinalArgs a) {
+    if (a.halt_on && a.cnt[kCntHalt] != 0) return;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= a.n_inst * a.nf) return;
     const int k = t / a.nf, nu = t % a.nf;

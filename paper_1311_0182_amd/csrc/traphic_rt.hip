@@ -163,6 +163,9 @@ struct rt_ctx {
     long long last_hops = 8;   // forward steps of the previous RT step
     // forward steps 1..n of an RT step, captured once per n and replayed
     std::map<int, hipGraphExec_t> hop_graphs;
+    std::map<long long, hipGraphExec_t> step_graphs;  // whole RT steps, by 2 * forward steps + RR buffer parity
+    bool step_graphs_on = false;                      // rt_set_step_graphs
+    bool capturing = false;                           // a whole step is being captured: its kernels obey the halt word
     // autotuner of the forward-step shape: -1 tune once work is representative
     int hop_shape = 0;
     int tune_mode = -1;        // -1 automatic, -2 tune now, 0..kHopShapes-1 fixed by the caller
@@ -448,6 +451,7 @@ rt_status launch_vip(rt_ctx* c, int hop) {
     a.act_wr = (hop + 1) & 1;
     a.list_rd = hop & 1;
     a.list_wr = (hop + 1) & 1;
+    a.halt_on = c->capturing ? 1 : 0;
     const unsigned nsb = static_cast<unsigned>(std::min<long long>(1024, (c->vip_cap + 255) / 256));
     hipLaunchKernelGGL(k_vip_sample, dim3(nsb), dim3(256), 0, c->stream, a);
     hipLaunchKernelGGL(k_vip_chain, dim3(1024), dim3(256), 0, c->stream, a);
@@ -456,15 +460,40 @@ rt_status launch_vip(rt_ctx* c, int hop) {
     // virtual-particle chains just launched); hop 0 runs every tile
     if (hop > 0) {
         hipLaunchKernelGGL(k_tile_list, dim3(static_cast<unsigned>(c->hot_len / kTileListChunk)), dim3(256), 0, c->stream,
-                           c->hot[hop & 1], c->ntiles, hop, hop & 1, c->rev_off, c->N, c->tileT, c->tlist, c->cnt);
+                           c->hot[hop & 1], c->ntiles, hop, hop & 1, c->rev_off, c->N, c->tileT, c->tlist, c->cnt,
+                           c->capturing ? 1 : 0);
         HIPCHK(c, hipGetLastError());
     }
     return RT_OK;
 }
 
-__global__ void k_step_reset(long long* cnt, long long serial) {
+__global__ void k_step_clear(const long long* cnt, int halt_on, int* head0, int* head1, long long N, double* A,
+                             double* P, long long NA) {
+    if (halt_on && cnt[kCntHalt] != 0) return;
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < NA; t += (long long)gridDim.x * blockDim.x) {
+        A[t] = 0.0;
+        P[t] = 0.0;
+        if (t < N) {
+            head0[t] = -1;
+            head1[t] = -1;
+        }
+    }
+}
+
+__global__ void k_set_counter(long long* cnt, int idx, long long v) {
+    if (threadIdx.x == 0) cnt[idx] = v;
+}
+
+__global__ void k_clear_halt(long long* cnt) {
     if (threadIdx.x == 0) {
-        cnt[kCntSerial] = serial;
+        cnt[kCntHalt] = 0;
+        cnt[kCntDone] = 0;
+    }
+}
+
+__global__ void k_step_reset(long long* cnt, long long serial, int set_serial, int halt_on) {
+    if (threadIdx.x == 0 && !(halt_on && cnt[kCntHalt] != 0)) {
+        if (set_serial) cnt[kCntSerial] = serial;
         cnt[kCntAct0] = 0;
         cnt[kCntAct0 + kCntLine] = 0;
         cnt[kCntVipCnt0] = 0;
@@ -523,6 +552,15 @@ float elapsed(rt_ctx* c, size_t slot) {
     return ms;
 }
 
+// Captured graphs refer to buffers, kernel variants and launch shapes: drop
+// them when any of those change.
+void drop_graphs(rt_ctx* c) {
+    for (auto& kv : c->hop_graphs) (void)hipGraphExecDestroy(kv.second);
+    c->hop_graphs.clear();
+    for (auto& kv : c->step_graphs) (void)hipGraphExecDestroy(kv.second);
+    c->step_graphs.clear();
+}
+
 // Forward steps 1..n as one graph.  Their launches do not change from step to
 // step (the step index and the stamps are read from device counters), so a
 // graph is captured once per n and replayed.  If capture is not possible the
@@ -576,7 +614,6 @@ rt_status launch_rr_original(rt_ctx* c) {
     r.nsub = c->nsub;
     r.rr_bin = c->p.rr_bin;
     r.seed = c->p.seed;
-    r.step = static_cast<uint32_t>(c->step);
     r.m0 = c->n_emit;
     r.u_ec = c->u_ec;
     r.pos = c->pos;
@@ -604,6 +641,7 @@ rt_status launch_rr_original(rt_ctx* c) {
     r.xr_fx = c->xr_fx;
     r.Ufx = c->Ufx;
     r.cnt = c->cnt;
+    r.halt_on = c->capturing ? 1 : 0;
     hipLaunchKernelGGL(k_rr_send, dim3(grid_for(c->N * c->nsub, 64)), dim3(64), 0, c->stream, r);
     HIPCHK(c, hipGetLastError());
     const int tpb = c->nrc <= 16 ? 64 : 32;  // LDS: tpb * nrc * 48 bytes
@@ -612,30 +650,24 @@ rt_status launch_rr_original(rt_ctx* c) {
     return RT_OK;
 }
 
-rt_status one_step(rt_ctx* c, bool* hopcap) {
-    // The autotuner times the forward-step shapes on steps whose work is
-    // representative (at least 16 forward steps in the previous step),
-    // alternating the shape from one forward step to the next.
-    c->tuning_now = c->tune_mode < 0 && !c->tuned && (c->last_hops >= 16 || c->tune_mode == -2);
-    // stamps are 30-bit: restart them (and forget every old mark) long before they wrap
-    if (c->serial + c->p.max_hops + 2 >= (1ll << 30)) {
-        for (int b = 0; b < 2; ++b) {
-            HIPCHK(c, hipMemsetAsync(c->inbox[b], 0xff, c->inbox_bytes, c->stream));
-            TRY(fill_i32(c, c->hot[b], c->hot_len, -1));
-        }
-        c->serial = 0;
-    }
-    // timing slots: 0 emission, 1 chemistry, 2 ledger, 3.. hops (vip then hop)
-    TRY(fill_i32(c, c->head[0], c->N, -1));
-    TRY(fill_i32(c, c->head[1], c->N, -1));
-    TRY(fill_f64(c, c->A, c->N * c->nf, 0.0));
-    TRY(fill_f64(c, c->P, c->N * c->nf, 0.0));
-    hipLaunchKernelGGL(k_step_reset, dim3(1), dim3(64), 0, c->stream, c->cnt, c->serial);
+// Start of an RT step: the step's accumulators cleared, the counters reset,
+// rotations, emission (sources; the predecessor RR scheme), the emission
+// cones' virtual particles and the first forward step.  set_serial: the stamp
+// base is the host's (one step at a time); otherwise the device's own, which
+// every finished step advances (steps replayed from a graph).
+rt_status step_front(rt_ctx* c, bool set_serial) {
+    const int ho = c->capturing ? 1 : 0;
+    hipLaunchKernelGGL(k_step_clear, dim3(std::min<unsigned>(grid_for(c->N * c->nf, 256), 4096)), dim3(256), 0, c->stream,
+                       c->cnt, ho, c->head[0], c->head[1], c->N, c->A, c->P, c->N * c->nf);
     HIPCHK(c, hipGetLastError());
+    hipLaunchKernelGGL(k_step_reset, dim3(1), dim3(64), 0, c->stream, c->cnt, c->serial, set_serial ? 1 : 0, ho);
+    HIPCHK(c, hipGetLastError());
+    // timing slots: 0 emission, 1 chemistry, 2 ledger, 3.. hops (vip then hop)
     TRY(time_begin(c, 0));
     StepBeginArgs sb{};
+    sb.cnt = c->cnt;
+    sb.halt_on = ho;
     sb.seed = c->p.seed;
-    sb.step = static_cast<uint32_t>(c->step);
     sb.nrc = c->nrc;
     sb.nec = c->nec;
     sb.nsub = c->nsub;
@@ -678,6 +710,7 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
         ea.vip = c->vip[0];
         ea.vip_cap = c->vip_cap;
         ea.cnt = c->cnt;
+        ea.halt_on = ho;
         ea.xr_fx = c->xr_fx;
         ea.Ufx = c->Ufx;
         ea.bar = c->any_bar ? c->bar_d : nullptr;
@@ -690,13 +723,14 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
     TRY(time_begin(c, 3));
     TRY(launch_hop_any(c, 0));
     TRY(time_end(c, 3));
-    // Forward steps are enqueued in batches between host checks of the device
-    // counters.  Automatic batching enqueues one more than the previous step
-    // needed (a step rarely needs more than one extra: launches past the end
-    // exit at once, cheaper than a host round trip), then goes one at a time.
-    int batch = c->p.hop_batch > 0 ? c->p.hop_batch : std::max(1, static_cast<int>(c->last_hops) + 1);
+    return RT_OK;
+}
+
+// Forward steps h, h + 1, ... one batch at a time with a host check of the
+// device counters after each, until no packet is active or the cap is
+// reached.  Returns the forward steps run (H) and the next unlaunched index.
+rt_status hop_loop(rt_ctx* c, int h, int batch, long long* H_out, int* h_out, bool* hopcap) {
     long long H = 0;
-    int h = 1;
     for (;;) {
         if (h <= c->p.max_hops) {
             const int hend = std::min(h + batch - 1, c->p.max_hops);
@@ -723,16 +757,22 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
             break;
         }
     }
+    *H_out = H;
+    *h_out = h;
+    return RT_OK;
+}
+
+// End of an RT step: tallies (launched: forward-step launches of the step,
+// hop 0 included), chemistry, ledger, the error check.  graph: see k_step_tally.
+rt_status step_tail(rt_ctx* c, long long launched, bool graph) {
     hipLaunchKernelGGL(k_step_tally, dim3(static_cast<unsigned>(std::min<long long>(64, (c->ntiles + 255) / 256))),
-                       dim3(256), 0, c->stream, c->cnt, c->part, c->ntiles);
+                       dim3(256), 0, c->stream, c->cnt, c->part, c->ntiles, launched, graph ? 1 : 0);
     HIPCHK(c, hipGetLastError());
-    // stamps of this step were serial .. serial + h - 1 (launched forward steps)
-    c->last_stamp = c->serial + H;
-    c->serial += h;
-    c->last_hops = H;
     // chemistry
     TRY(time_begin(c, 1));
     ChemArgs ca{};
+    ca.cnt = c->cnt;
+    ca.halt_on = c->capturing ? 1 : 0;
     ca.N = c->N;
     ca.nf = c->nf;
     ca.mode = c->p.recomb_mode;
@@ -758,6 +798,8 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
     // ledger
     TRY(time_begin(c, 2));
     LedgerArgs la{};
+    la.cnt = c->cnt;
+    la.halt_on = c->capturing ? 1 : 0;
     la.nf = c->nf;
     la.rr_bin = c->p.rr_bin;
     la.rr_on = c->rr_on ? 1 : 0;
@@ -772,6 +814,8 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
     hipLaunchKernelGGL(k_ledger_partial, dim3(static_cast<unsigned>(c->n_chunks)), dim3(256), 0, c->stream, la);
     HIPCHK(c, hipGetLastError());
     EmitTallyArgs et{};
+    et.cnt = c->cnt;
+    et.halt_on = c->capturing ? 1 : 0;
     et.nf = c->nf;
     et.per_em = static_cast<long long>(c->nsub) * c->nec;
     et.em_by_inst = c->em_by_inst;
@@ -795,9 +839,20 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
     lf.led = c->led;
     lf.scale = c->scale;
     lf.cnt = c->cnt;
+    lf.halt_on = c->capturing ? 1 : 0;
     hipLaunchKernelGGL(k_ledger_final, dim3(grid_for(c->n_inst * c->nf, 64)), dim3(64), 0, c->stream, lf);
     HIPCHK(c, hipGetLastError());
+    hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, c->stream, c->cnt, c->capturing ? 1 : 0);
+    HIPCHK(c, hipGetLastError());
     TRY(time_end(c, 2));
+    return RT_OK;
+}
+
+// Host bookkeeping after a step that ran H forward steps with `launched`
+// launches, then the counters read back (tuning and timing use them).
+rt_status step_done(rt_ctx* c, long long H, long long launched) {
+    c->serial += launched;
+    c->last_hops = H;
     c->nrr_cur ^= 1;
     c->step += 1;
     HIPCHK(c, hipMemcpyAsync(c->h_cnt, c->cnt, sizeof(long long) * kCntN, hipMemcpyDeviceToHost, c->stream));
@@ -814,8 +869,7 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
                     best = k;
             c->hop_shape = best;
             c->tuned = true;
-            for (auto& kv : c->hop_graphs) (void)hipGraphExecDestroy(kv.second);
-            c->hop_graphs.clear();
+            drop_graphs(c);
         }
         c->tuning_now = false;
     }
@@ -831,6 +885,123 @@ rt_status one_step(rt_ctx* c, bool* hopcap) {
             c->tm[1] += 1;
         }
     }
+    return RT_OK;
+}
+
+// Stamps are 30-bit: restart them (and forget every old mark) long before they wrap.
+rt_status restart_stamps_if_needed(rt_ctx* c, long long ahead) {
+    if (c->serial + ahead + c->p.max_hops + 2 < (1ll << 30)) return RT_OK;
+    for (int b = 0; b < 2; ++b) {
+        HIPCHK(c, hipMemsetAsync(c->inbox[b], 0xff, c->inbox_bytes, c->stream));
+        TRY(fill_i32(c, c->hot[b], c->hot_len, -1));
+    }
+    c->serial = 0;
+    hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(64), 0, c->stream, c->cnt, static_cast<int>(kCntSerial), 0ll);
+    HIPCHK(c, hipGetLastError());
+    return RT_OK;
+}
+
+// One RT step, checked by the host as it goes (used while tuning or timing,
+// before the forward-step count of a step is known, and with a fixed batch).
+rt_status one_step(rt_ctx* c, bool* hopcap) {
+    // The autotuner times the forward-step shapes on steps whose work is
+    // representative (at least 16 forward steps in the previous step),
+    // alternating the shape from one forward step to the next.
+    c->tuning_now = c->tune_mode < 0 && !c->tuned && (c->last_hops >= 16 || c->tune_mode == -2);
+    TRY(restart_stamps_if_needed(c, 0));
+    TRY(step_front(c, true));
+    // Forward steps are enqueued in batches between host checks of the device
+    // counters.  Automatic batching enqueues one more than the previous step
+    // needed (a step rarely needs more than one extra: launches past the end
+    // exit at once, cheaper than a host round trip), then goes one at a time.
+    const int batch = c->p.hop_batch > 0 ? c->p.hop_batch : std::max(1, static_cast<int>(c->last_hops) + 1);
+    long long H = 0;
+    int h = 1;
+    TRY(hop_loop(c, 1, batch, &H, &h, hopcap));
+    TRY(step_tail(c, h, false));
+    return step_done(c, H, h);
+}
+
+// The whole RT step with hg forward steps after hop 0, captured once per
+// (hg, parity of the RR double buffer) and replayed: no host check inside.
+rt_status step_graph(rt_ctx* c, int hg, hipGraphExec_t* out) {
+    const long long key = 2ll * hg + c->nrr_cur;
+    auto it = c->step_graphs.find(key);
+    if (it != c->step_graphs.end()) {
+        *out = it->second;
+        return RT_OK;
+    }
+    *out = nullptr;
+    if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        c->graphs_ok = false;
+        return RT_OK;
+    }
+    c->capturing = true;
+    rt_status st = step_front(c, false);
+    for (int q = 1; q <= hg && st == RT_OK; ++q) {
+        st = launch_vip(c, q);
+        if (st == RT_OK) st = launch_hop_any(c, q);
+    }
+    if (st == RT_OK) st = step_tail(c, hg + 1, true);
+    c->capturing = false;
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(c->stream, &g);
+    hipGraphExec_t ex = nullptr;
+    if (st != RT_OK || ec != hipSuccess || !g || hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        c->graphs_ok = false;
+        c->sticky = false;
+        c->err.clear();
+        return RT_OK;
+    }
+    (void)hipGraphDestroy(g);
+    c->step_graphs.emplace(key, ex);
+    *out = ex;
+    return RT_OK;
+}
+
+// Up to n RT steps, each replayed from its whole-step graph and enqueued
+// back to back with a single host check at the end.  A step that needs more
+// forward steps than its graph holds halts the queue on the device; it is
+// finished here one forward step at a time.  Returns the steps finished.
+rt_status graph_steps(rt_ctx* c, int n, int* done, bool* hopcap) {
+    *done = 0;
+    const int hg = static_cast<int>(std::min<long long>(c->p.max_hops, c->last_hops + 1));
+    TRY(restart_stamps_if_needed(c, static_cast<long long>(hg + 1) * n));
+    const long long step0 = c->step;
+    const int cur0 = c->nrr_cur;
+    int launched_steps = 0;
+    for (int s = 0; s < n; ++s) {
+        hipGraphExec_t ex = nullptr;
+        TRY(step_graph(c, hg, &ex));
+        if (!ex) break;  // capture not possible: the caller goes on step by step
+        HIPCHK(c, hipGraphLaunch(ex, c->stream));
+        c->nrr_cur ^= 1;
+        ++launched_steps;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->h_cnt, c->cnt, sizeof(long long) * kCntN, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const long long halt = c->h_cnt[kCntHalt];
+    const long long started = c->h_cnt[kCntSteps] - step0;  // the step counter counts a step at its start
+    const long long finished = halt == 1 ? started - 1 : started;
+    c->step = step0 + finished;
+    c->nrr_cur = cur0 ^ static_cast<int>(finished & 1);
+    c->serial = c->h_cnt[kCntSerial];
+    if (finished > 0) c->last_hops = c->h_cnt[kCntLastHops];
+    *done = static_cast<int>(finished);
+    if (halt == 0) return RT_OK;
+    hipLaunchKernelGGL(k_clear_halt, dim3(1), dim3(64), 0, c->stream, c->cnt);
+    HIPCHK(c, hipGetLastError());
+    if (halt == 2) return RT_OK;  // the error flags of the last finished step are reported by the caller
+    // finish the halted step: its first hg forward steps ran
+    long long H = 0;
+    int h = hg + 1;
+    TRY(hop_loop(c, hg + 1, 1, &H, &h, hopcap));
+    TRY(step_tail(c, h, false));
+    TRY(step_done(c, H, h));
+    *done += 1;
     return RT_OK;
 }
 
@@ -1275,8 +1446,7 @@ rt_status rt_add_sources(rt_ctx* c, int32_t n_src, const int32_t* inst, const in
     // particles of empty emission cones): drop them, and free the old buffers
     // once no queued work uses them.
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (auto& kv : c->hop_graphs) (void)hipGraphExecDestroy(kv.second);
-    c->hop_graphs.clear();
+    drop_graphs(c);
     dfree(c, c->em_kind);
     dfree(c, c->em_inst);
     dfree(c, c->em_pos);
@@ -1322,8 +1492,24 @@ rt_status rt_step(rt_ctx* c, int32_t n_steps) {
     for (int k = 0; k < 8; ++k) c->tm[k] = 0.0;
     if (c->timing) HIPCHK(c, hipMemsetAsync(c->cnt + kCntBytes, 0, 2 * sizeof(long long), c->stream));
     bool hopcap = false;
-    for (int s = 0; s < n_steps; ++s) {
-        TRY(one_step(c, &hopcap));
+    // a halt left by an error of the previous call
+    hipLaunchKernelGGL(k_clear_halt, dim3(1), dim3(64), 0, c->stream, c->cnt);
+    HIPCHK(c, hipGetLastError());
+    for (int s = 0; s < n_steps;) {
+        // whole-step graphs once the forward-step count is known and nothing
+        // needs the host between forward steps (a tuning step, timing, a fixed
+        // batch); while the tuner waits for a representative step, one step
+        // per check
+        const bool tune_pending = c->tune_mode < 0 && !c->tuned;
+        const bool graphable = c->step_graphs_on && c->graphs_ok && !c->timing && c->p.hop_batch <= 0 && c->last_hops > 0 &&
+                               !(tune_pending && (c->last_hops >= 16 || c->tune_mode == -2));
+        int done = 0;
+        if (graphable) TRY(graph_steps(c, tune_pending ? 1 : std::min(n_steps - s, 1024), &done, &hopcap));
+        if (done == 0) {
+            TRY(one_step(c, &hopcap));
+            done = 1;
+        }
+        s += done;
         const long long flags = c->h_cnt[kCntFlags];
         if (flags & (kFlagVipOverflow | kFlagRecOverflow)) return fail(c, RT_EOVERFLOW, "work buffer overflow");
         if (flags & kFlagNonFinite) return fail(c, RT_ENONFINITE, "non-finite ledger");
@@ -1486,6 +1672,8 @@ rt_status rt_set_barrier(rt_ctx* c, int32_t inst, const double* center, double r
             if (!std::isfinite(center[a])) return fail(c, RT_EINVAL, "barrier: centre must be finite");
     for (int a = 0; a < 3; ++a) c->bar[4 * inst + a] = radius > 0.0 ? center[a] : 0.0;
     c->bar[4 * inst + 3] = radius;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    drop_graphs(c);  // the forward steps' kernel variant and arguments follow the barrier
     c->any_bar = false;
     for (int k = 0; k < c->n_inst; ++k) c->any_bar = c->any_bar || c->bar[4 * k + 3] > 0.0;
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1625,12 +1813,18 @@ rt_status rt_get_timing(rt_ctx* c, double* out, int32_t n) {
     return RT_OK;
 }
 
+rt_status rt_set_step_graphs(rt_ctx* c, int32_t on) {
+    if (!c || (on != 0 && on != 1)) return RT_EINVAL;
+    if (c->sticky) return RT_EDEVICE;
+    c->step_graphs_on = on != 0;
+    return RT_OK;
+}
+
 rt_status rt_set_hop_shape(rt_ctx* c, int32_t shape) {
     if (!c || shape < -2 || shape >= kHopShapes) return RT_EINVAL;
     if (c->sticky) return RT_EDEVICE;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (auto& kv : c->hop_graphs) (void)hipGraphExecDestroy(kv.second);
-    c->hop_graphs.clear();
+    drop_graphs(c);
     c->tune_mode = shape;
     if (shape >= 0) {
         c->hop_shape = shape;
@@ -1754,8 +1948,7 @@ rt_status rt_set_state_blob(rt_ctx* c, const void* blob, size_t bytes) {
 void rt_destroy(rt_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
-    for (auto& kv : c->hop_graphs) (void)hipGraphExecDestroy(kv.second);
-    c->hop_graphs.clear();
+    drop_graphs(c);
     for (auto& b : c->owned) {
         if (c->p.dealloc)
             c->p.dealloc(c->p.alloc_user, b.p);

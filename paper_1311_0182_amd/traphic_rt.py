@@ -26,7 +26,7 @@ DEALLOC_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 EXPORTS = ["rt_init", "rt_add_sources", "rt_step", "rt_get_state", "rt_get_bins", "rt_get_neighbours",
            "rt_n_emitters", "rt_get_emitter_neighbours", "rt_get_cone_masks", "rt_get_pending_rr",
            "rt_set_timing", "rt_get_timing", "rt_set_hop_shape", "rt_get_hop_shape", "rt_get_state_blob",
-           "rt_set_state_blob", "rt_shell_profile", "rt_shell_profile_noalloc", "rt_set_barrier", "rt_destroy",
+           "rt_set_state_blob", "rt_shell_profile", "rt_shell_profile_noalloc", "rt_set_barrier", "rt_set_step_graphs", "rt_destroy",
            "rt_last_error"]
 
 
@@ -101,6 +101,8 @@ def load():
     L.rt_shell_profile_noalloc.restype = C.c_int
     L.rt_shell_profile_noalloc.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, dp, dp, C.c_double, C.c_double,
                                            C.c_int32, C.c_int32, C.c_double, dp, i64p]
+    L.rt_set_step_graphs.restype = C.c_int
+    L.rt_set_step_graphs.argtypes = [C.c_void_p, C.c_int32]
     L.rt_set_barrier.restype = C.c_int
     L.rt_set_barrier.argtypes = [C.c_void_p, C.c_int32, dp, C.c_double]
     L.rt_destroy.restype = None
@@ -268,6 +270,9 @@ class Context:
         keys = ["hop_ms", "hop_launches", "vip_ms", "chem_ms", "emit_ms", "ledger_ms", "hop_bytes_total",
                 "hop_tiles_total", "dense_bytes_per_hop"]
         return {k: float(out[i]) for i, k in enumerate(keys)}
+
+    def set_step_graphs(self, on=True):
+        self._check(load().rt_set_step_graphs(self.h, 1 if on else 0))
 
     def set_hop_shape(self, shape=-1):
         self._check(load().rt_set_hop_shape(self.h, int(shape)))

@@ -181,10 +181,52 @@ def test_graph_replay_matches_eager():
             assert np.array_equal(sg[key], se[key]), (prec, key)
 
 
+def test_whole_step_graphs_match_eager():
+    # With whole-step graphs on and the launch configuration fixed, whole RT
+    # steps replay from graphs
+    # enqueued back to back (one host check per call).  A step that needs more
+    # forward steps than its graph holds halts the queue on the device and is
+    # finished by the host; the steps after it are enqueued again.  The
+    # Stromgren front needs more forward steps from step to step, so a 12-step
+    # call goes through such halts.  The state must match, bit for bit, the
+    # same steps made one launch at a time with a host check after each batch
+    # (the stamps that number forward steps differ: a graph holds a fixed
+    # number of them).
+    cfg = I.stromgren(16, rr=True, n_ngb=32, dt_myr=0.2)
+    RT = _rt()
+    for prec in ("fp64", "fp32"):
+        g = RT.Context(cfg, precision=prec)
+        g.set_hop_shape(3)
+        g.set_step_graphs(True)
+        e = RT.Context(cfg, precision=prec)
+        e.set_hop_shape(3)
+        e.set_timing(True)
+        g.step(1)
+        e.step(1)
+        g.step(12)
+        for _ in range(12):
+            e.step(1)
+        sg, se = g.state(), e.state()
+        say(prec, "counters", sg["counters"], se["counters"])
+        for key in ("xHI", "T", "A", "P", "ledger", "counters"):
+            assert np.array_equal(sg[key], se[key]), (prec, key)
+        for a, b in zip(g.bins(), e.bins()):
+            assert np.array_equal(a, b), prec
+        g.step(3)          # and again after the host-side finish
+        for _ in range(3):
+            e.step(1)
+        sg, se = g.state(), e.state()
+        for key in ("xHI", "T", "A", "P", "ledger", "counters"):
+            assert np.array_equal(sg[key], se[key]), (prec, key)
+        for a, b in zip(g.bins(), e.bins()):
+            assert np.array_equal(a, b), prec
+
+
 def test_hop_shapes_identical_and_tuner():
     # Every workgroup shape of the forward step adds a slot's contributions in
     # the same order, and the tuner alternates shapes while it times them: all
-    # runs must agree bit for bit.
+    # runs must agree bit for bit (state and packet bins; the stamps that
+    # number forward steps depend on how steps were enqueued).
     cfg = I.stromgren(16, rr=True, n_ngb=32, dt_myr=0.5)
     RT = _rt()
     for prec in ("fp64", "fp32"):
@@ -193,14 +235,16 @@ def test_hop_shapes_identical_and_tuner():
             ctx = RT.Context(cfg, precision=prec)
             ctx.set_hop_shape(shape)
             ctx.step(12)
-            blobs.append(ctx.get_blob())
+            st = ctx.state()
+            blobs.append([st[k] for k in ("xHI", "T", "A", "P", "ledger", "counters")] + list(ctx.bins()))
             info = ctx.hop_shape()
             say(prec, "shape", shape, info)
             if shape >= 0:
                 assert info["shape"] == shape and not info["tuned"]
             else:
                 assert info["tuned"] and 0 <= info["shape"] <= 5 and all(m > 0 for m in info["ms_per_launch"])
-        assert all(b == blobs[0] for b in blobs[1:]), prec
+        for b in blobs[1:]:
+            assert all(np.array_equal(x, y) for x, y in zip(b, blobs[0])), prec
     with pytest.raises(RT.RTError):
         RT.Context(cfg).set_hop_shape(6)
 
