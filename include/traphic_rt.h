@@ -69,7 +69,10 @@ typedef struct {
     int32_t n_tc;          /* transmission cones: cone solid angle 4 pi / N_TC, >= 3 */
     int32_t n_rc;          /* reception cones per particle and bin: 1, 2, 4, 8, 16 or 32 */
     int32_t n_ec;          /* emission cones of point sources, 1..64 */
-    int32_t n_freq;        /* grey frequency bins, 1..15 */
+    int32_t n_freq;        /* grey frequency bins, 1..15; n_rc * n_freq (the packet slots of a
+                              particle) must be a power of two of at most 64, since one
+                              wavefront lane holds one slot and a particle's slots share a
+                              wavefront (pad with an unused bin if needed) */
     int32_t rr_bin;        /* bin that carries RR photons, or -1 */
     int32_t recomb_mode;   /* RT_CASE_B_OTS, RT_CASE_A_NO_RR, RT_RR_TRANSPORT or RT_RR_ORIGINAL */
     int32_t isothermal;    /* 1: T fixed; 0: photoheating and radiative cooling */
