@@ -126,15 +126,18 @@ def stromgren(n_side=16, box_kpc=6.6, rr=False, n_ngb=32, ndot=5e48, n_h=1e-3,
               n_steps=100, seed_k=1, dt_myr=0.1, n_em=10, **pkw):
     """Stromgren HII region (section 3 set-up, scaled): uniform neutral hydrogen,
     one monochromatic 13.6 eV source at the exact box centre.  With rr=True a
-    second bin carries recombination photons (case A + explicit transport)."""
+    second bin carries recombination photons (case A + explicit transport);
+    with rr="shared" they travel in the source's own bin (section 2.2's
+    further saving, appropriate here since both are 13.6 eV photons)."""
     rng = np.random.default_rng(BASE_SEED + seed_k)
     L = box_kpc * KPC_CM
     lo = np.zeros(3)
     pos = jittered_lattice(n_side, lo, L, rng)
     nh, NH, xhi, T = _uniform_gas(pos, n_h, L, 1.0, 1e4)
-    n_freq = 2 if rr else 1
+    shared = rr == "shared"
+    n_freq = 2 if (rr and not shared) else 1
     params = default_params(
-        n_ngb=n_ngb, n_freq=n_freq, rr_bin=(1 if rr else -1),
+        n_ngb=n_ngb, n_freq=n_freq, rr_bin=(0 if shared else 1 if rr else -1),
         recomb_mode=(RR_TRANSPORT if rr else CASE_B_OTS),
         dt=dt_myr * MYR_S, n_em=n_em, seed=BASE_SEED + seed_k)
     params.update(pkw)
@@ -144,7 +147,8 @@ def stromgren(n_side=16, box_kpc=6.6, rr=False, n_ngb=32, ndot=5e48, n_h=1e-3,
     rate[0, 0] = ndot
     src = _point_sources([0], [L / 2, L / 2, L / 2], rate)
     inst = dict(pos=pos, nH=nh, NH=NH, xHI=xhi, T=T, box_lo=lo, box_hi=lo + L)
-    return _pack(f"stromgren{n_side}{'_rr' if rr else ''}", params, sigma, eps, [inst], src, n_steps)
+    return _pack(f"stromgren{n_side}{'_rr_shared' if shared else '_rr' if rr else ''}", params, sigma, eps, [inst], src,
+                 n_steps)
 
 
 def batched(n_inst=64, side_lo=8, side_hi=48, n_ngb=48, n_steps=100, seed_k=4, rr=True, **pkw):

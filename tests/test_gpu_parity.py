@@ -118,6 +118,14 @@ def test_fp64_parity_rr_ragged():
     _compare_fp64(cfg, 20)
 
 
+def test_fp64_parity_rr_in_the_source_bin():
+    # section 2.2's shared bin: the recombination photons travel in the
+    # source's 13.6 eV bin (one bin: N_RC packet slots per particle)
+    cfg = I.stromgren(11, rr="shared", n_ngb=32, dt_myr=0.5)
+    say("11^3 with RR in the source bin, 20 steps")
+    _compare_fp64(cfg, 20)
+
+
 def test_fp64_parity_batched():
     cfg = I.batched(n_inst=6, side_lo=6, side_hi=12, n_ngb=32, n_steps=10)
     say("batched 6 instances, 10 steps")
@@ -134,10 +142,12 @@ def test_fp64_parity_plane_front_chain():
     assert rel(sg["P"], so["P"]) < 1e-12
 
 
-@pytest.mark.parametrize("name", ["rr11", "batched6"])
+@pytest.mark.parametrize("name", ["rr11", "rr11_shared", "batched6"])
 def test_fp32_transport_within_bound(name):
     if name == "rr11":
         cfg, steps = I.stromgren(11, rr=True, n_ngb=32, dt_myr=0.5), 20
+    elif name == "rr11_shared":
+        cfg, steps = I.stromgren(11, rr="shared", n_ngb=32, dt_myr=0.5), 20
     else:
         cfg, steps = I.batched(n_inst=6, side_lo=6, side_hi=12, n_ngb=32), 10
     say("fp32", name)

@@ -659,6 +659,29 @@ def test_rr_in_reception_cones_matches_the_original_scheme():
     assert lost[1] == 0.0
 
 
+def test_rr_in_the_source_bin_matches_a_bin_of_its_own():
+    # Section 2.2: transporting the recombination photons in the stellar bin
+    # saves memory and, when both spectra are alike (here both are 13.6 eV
+    # photons with the same cross-section), changes little.  The same Stromgren
+    # problem with RR in a bin of its own and in the source's bin: the ionized
+    # fractions of six radial shells agree to 10^-3 and the photons emitted in
+    # the shared bin are the source's plus the RR photons to 10^-3.
+    a = I.stromgren(12, rr=True, n_ngb=32, dt_myr=0.5)
+    b = I.stromgren(12, rr="shared", n_ngb=32, dt_myr=0.5)
+    out = []
+    for cfg in (a, b):
+        s = O.OracleSim(cfg)
+        s.step(20)
+        out.append((_shell_xhii(cfg, s.state()), s.state()["ledger"][0]))
+        s.close()
+    (xa, la), (xb, lb) = out
+    assert lb.shape[0] == 1 and la.shape[0] == 2
+    assert np.max(np.abs(xa - xb)) < 1e-3
+    assert abs(lb[0, 0] / (la[0, 0] + la[1, 0]) - 1) < 1e-3
+    E, A, X, R, F = lb[0]
+    assert abs(E - A - X - R - F) <= 1e-12 * E
+
+
 # ----- clocks (section 2.1: packets move until the clock reaches c dt) ---------
 
 C_LIGHT = 2.99792458e10
