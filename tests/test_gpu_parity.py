@@ -126,6 +126,34 @@ def test_fp64_parity_rr_in_the_source_bin():
     _compare_fp64(cfg, 20)
 
 
+def test_late_steps_against_oracle():
+    # The late-step regime at a size the oracle runs in half a minute: 24^3
+    # particles with 48 neighbours and RR, 40 steps of 0.5 Myr (about 25
+    # forward steps per step and 10^6 virtual particles by the end, many
+    # packets arriving per slot), FP64 and FP32 against the same oracle run.
+    cfg = I.stromgren(24, rr=True, n_ngb=48, dt_myr=0.5)
+    steps = 40
+    say("24^3 with RR, 40 steps")
+    s, _ = run_oracle(cfg, steps)
+    so = s.state()
+    assert so["counters"][2] > 500000 and so["counters"][1] > 20 * steps / 2
+    g64 = run_gpu(cfg, steps, "fp64")
+    sg = g64.state()
+    say("counters oracle", so["counters"], "gpu", sg["counters"])
+    assert np.array_equal(so["counters"], sg["counters"])
+    assert rel(sg["xHI"], so["xHI"]) < 1e-6
+    assert np.max(residual(sg["ledger"])) < 1e-12
+    assert rel(sg["ledger"][..., 0], so["ledger"][..., 0]) < 1e-12
+    g64.close()
+    g32 = run_gpu(cfg, steps, "fp32")
+    s32 = g32.state()
+    dx = np.max(np.abs(s32["xHI"] - so["xHI"]))
+    say("fp32 max |dx_HI|", dx, "residual", np.max(residual(s32["ledger"])))
+    assert dx <= 1e-3
+    assert np.max(residual(s32["ledger"])) <= 1e-6
+    g32.close()
+
+
 def test_fp64_parity_batched():
     cfg = I.batched(n_inst=6, side_lo=6, side_hi=12, n_ngb=32, n_steps=10)
     say("batched 6 instances, 10 steps")
@@ -305,6 +333,15 @@ def test_full_size_first_steps_fp64():
     assert np.array_equal(so["counters"], sg["counters"])
     assert rel(sg["xHI"], so["xHI"]) < 1e-6
     assert np.max(residual(sg["ledger"])) < 1e-12
+    ctx.close()
+    # and the FP32 transport against the same oracle run, at full size
+    c32 = run_gpu(cfg, 3, "fp32")
+    s32 = c32.state()
+    dx = np.max(np.abs(s32["xHI"] - so["xHI"]))
+    say("fp32 full size max |dx_HI|", dx)
+    assert dx <= 1e-3
+    assert np.max(residual(s32["ledger"])) <= 1e-6
+    c32.close()
 
 
 @pytest.mark.parametrize("case", ["no_sources", "ionized_start", "tiny_instances"])
