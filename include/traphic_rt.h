@@ -8,9 +8,13 @@
  * Conventions for every entry point
  *   - Units are cgs: positions in cm, densities in cm^-3, time in s, photon
  *     counts in photons, energies in erg, temperatures in K.
- *   - Every array argument is a HOST pointer (one exception: passing_dev of
- *     rt_shell_profile_noalloc), owned by the caller and only
- *     read (inputs) or written (outputs) during the call.  The library copies
+ *   - Array arguments are owned by the caller and only read (inputs) or
+ *     written (outputs) during the call.  The arrays of rt_init and
+ *     rt_add_sources, and the outputs of rt_get_state, may be host or device
+ *     memory (the library asks the runtime which; device inputs are copied to
+ *     the host first, since validation reads them there).  Every other array
+ *     argument is a host pointer, except passing_dev of
+ *     rt_shell_profile_noalloc, which is device memory.  The library copies
  *     inputs to device memory it owns.
  *   - All device work runs on the HIP stream given to rt_init.  rt_step only
  *     enqueues work (it waits on the stream only to decide when a step's

@@ -1005,15 +1005,66 @@ rt_status graph_steps(rt_ctx* c, int n, int* done, bool* hopcap) {
     return RT_OK;
 }
 
+// Input arrays may be host or device memory: device (and managed) arrays are
+// copied to the host first, since validation and set-up read them there.
+// Returns p itself for host memory, nullptr if the copy failed.
+template <typename T>
+const T* staged(const T* p, size_t n, std::vector<T>& buf) {
+    if (!p || n == 0) return p;
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();  // pageable host memory is unknown to the runtime
+        return p;
+    }
+    if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged) return p;
+    buf.resize(n);
+    if (hipMemcpy(buf.data(), p, n * sizeof(T), hipMemcpyDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return buf.data();
+}
+
 }  // namespace
 
 extern "C" {
 
 const char* rt_last_error(const rt_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
+namespace {
+rt_status init_impl(rt_ctx** out, const rt_params* p, const double* sigma_nu, const double* eps_nu, int32_t n_inst,
+                    const int64_t* inst_off, const double* box, const double* pos, const double* n_H, const double* N_H,
+                    const double* x_HI0, const double* T0, void* hip_stream);
+}  // namespace
+
 rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, const double* eps_nu, int32_t n_inst,
                   const int64_t* inst_off, const double* box, const double* pos, const double* n_H, const double* N_H,
                   const double* x_HI0, const double* T0, void* hip_stream) {
+    if (!out || !p || !sigma_nu || !eps_nu || !inst_off || !box || !pos || !n_H || !N_H || !x_HI0 || !T0 || n_inst < 1 ||
+        p->n_freq < 1 || p->n_freq > 15)
+        return RT_EINVAL;
+    std::vector<int64_t> off_h;
+    const int64_t* off = staged(inst_off, static_cast<size_t>(n_inst) + 1, off_h);
+    if (!off) return RT_EINVAL;
+    const long long N = off[n_inst];
+    if (off[0] != 0 || N <= 0 || N >= (1ll << 26)) return RT_EINVAL;
+    std::vector<double> sg, ep, bx, ps, nh, NHh, xh, th;
+    const double* a0 = staged(sigma_nu, p->n_freq, sg);
+    const double* a1 = staged(eps_nu, p->n_freq, ep);
+    const double* a2 = staged(box, 6 * static_cast<size_t>(n_inst), bx);
+    const double* a3 = staged(pos, 3 * static_cast<size_t>(N), ps);
+    const double* a4 = staged(n_H, N, nh);
+    const double* a5 = staged(N_H, N, NHh);
+    const double* a6 = staged(x_HI0, N, xh);
+    const double* a7 = staged(T0, N, th);
+    if (!a0 || !a1 || !a2 || !a3 || !a4 || !a5 || !a6 || !a7) return RT_EINVAL;
+    return init_impl(out, p, a0, a1, n_inst, off, a2, a3, a4, a5, a6, a7, hip_stream);
+}
+
+namespace {
+rt_status init_impl(rt_ctx** out, const rt_params* p, const double* sigma_nu, const double* eps_nu, int32_t n_inst,
+                    const int64_t* inst_off, const double* box, const double* pos, const double* n_H, const double* N_H,
+                    const double* x_HI0, const double* T0, void* hip_stream) {
     if (!out || !p || !sigma_nu || !eps_nu || !inst_off || !box || !pos || !n_H || !N_H || !x_HI0 || !T0)
         return RT_EINVAL;
     *out = nullptr;
@@ -1329,9 +1380,33 @@ rt_status rt_init(rt_ctx** out, const rt_params* p, const double* sigma_nu, cons
     *out = c;
     return RT_OK;
 }
+}  // namespace
+
+namespace {
+rt_status add_sources_impl(rt_ctx* c, int32_t n_src, const int32_t* inst, const int32_t* kind, const double* pos,
+                           const double* rate, const int32_t* n_side);
+}  // namespace
 
 rt_status rt_add_sources(rt_ctx* c, int32_t n_src, const int32_t* inst, const int32_t* kind, const double* pos,
                          const double* rate, const int32_t* n_side) {
+    if (!c) return RT_EINVAL;
+    if (c->sticky) return RT_EDEVICE;
+    if (n_src < 0) return fail(c, RT_EINVAL, "n_src < 0");
+    std::vector<int32_t> ih, kh, nh;
+    std::vector<double> ph, rh;
+    const int32_t* i1 = staged(inst, n_src, ih);
+    const int32_t* k1 = staged(kind, n_src, kh);
+    const double* p1 = staged(pos, 3 * static_cast<size_t>(n_src), ph);
+    const double* r1 = staged(rate, static_cast<size_t>(n_src) * c->nf, rh);
+    const int32_t* n1 = staged(n_side, n_src, nh);
+    if ((inst && !i1) || (kind && !k1) || (pos && !p1) || (rate && !r1) || (n_side && !n1))
+        return fail(c, RT_EINVAL, "source arrays could not be read");
+    return add_sources_impl(c, n_src, i1, k1, p1, r1, n1);
+}
+
+namespace {
+rt_status add_sources_impl(rt_ctx* c, int32_t n_src, const int32_t* inst, const int32_t* kind, const double* pos,
+                           const double* rate, const int32_t* n_side) {
     if (!c) return RT_EINVAL;
     if (c->sticky) return RT_EDEVICE;
     if (n_src < 0 || (n_src > 0 && (!inst || !kind || !pos || !rate))) return fail(c, RT_EINVAL, "null source arrays");
@@ -1484,6 +1559,7 @@ rt_status rt_add_sources(rt_ctx* c, int32_t n_src, const int32_t* inst, const in
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return RT_OK;
 }
+}  // namespace
 
 rt_status rt_step(rt_ctx* c, int32_t n_steps) {
     if (!c) return RT_EINVAL;
@@ -1525,14 +1601,14 @@ rt_status rt_get_state(rt_ctx* c, double* x_HI, double* T, double* absorbed, dou
     if (!c) return RT_EINVAL;
     if (c->sticky) return RT_EDEVICE;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (x_HI) HIPCHK(c, hipMemcpy(x_HI, c->xHI, sizeof(double) * c->N, hipMemcpyDeviceToHost));
-    if (T) HIPCHK(c, hipMemcpy(T, c->T, sizeof(double) * c->N, hipMemcpyDeviceToHost));
-    if (absorbed) HIPCHK(c, hipMemcpy(absorbed, c->A, sizeof(double) * c->N * c->nf, hipMemcpyDeviceToHost));
-    if (passing) HIPCHK(c, hipMemcpy(passing, c->P, sizeof(double) * c->N * c->nf, hipMemcpyDeviceToHost));
-    if (ledger) HIPCHK(c, hipMemcpy(ledger, c->led, sizeof(double) * 5 * c->n_inst * c->nf, hipMemcpyDeviceToHost));
+    if (x_HI) HIPCHK(c, hipMemcpy(x_HI, c->xHI, sizeof(double) * c->N, hipMemcpyDefault));
+    if (T) HIPCHK(c, hipMemcpy(T, c->T, sizeof(double) * c->N, hipMemcpyDefault));
+    if (absorbed) HIPCHK(c, hipMemcpy(absorbed, c->A, sizeof(double) * c->N * c->nf, hipMemcpyDefault));
+    if (passing) HIPCHK(c, hipMemcpy(passing, c->P, sizeof(double) * c->N * c->nf, hipMemcpyDefault));
+    if (ledger) HIPCHK(c, hipMemcpy(ledger, c->led, sizeof(double) * 5 * c->n_inst * c->nf, hipMemcpyDefault));
     if (counters) {
         long long h[kCntN];
-        HIPCHK(c, hipMemcpy(h, c->cnt, sizeof(h), hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(h, c->cnt, sizeof(h), hipMemcpyDefault));
         counters[0] = h[kCntSteps];
         counters[1] = h[kCntHops];
         counters[2] = h[kCntVips];

@@ -507,3 +507,60 @@ def test_refused_fp32_rescale_is_reported():
     ctx.set_blob(bytes(blob))
     assert ctx.step(1, allow=(RT.RT_EDRIFT,)) == RT.RT_EDRIFT
     ctx.close()
+
+
+def test_device_arrays_at_the_boundary(monkeypatch):
+    # rt_init, rt_add_sources and rt_get_state take host or device memory:
+    # a context built from device arrays (and its sources added from device
+    # arrays) runs exactly like one built from host arrays, and its state read
+    # into device arrays equals the state read into host arrays.
+    import ctypes as C
+
+    import torch
+    RT = _rt()
+    cfg = I.stromgren(10, rr=True, n_ngb=32, dt_myr=0.5)
+
+    def dev(a, dtype):
+        return torch.tensor(np.ascontiguousarray(a, dtype=dtype), device="cuda")
+
+    def ptr(t, ct):
+        return C.cast(C.c_void_p(t.data_ptr()), C.POINTER(ct))
+
+    def dev_init_call(handle, params, cfg_, stream_ptr):
+        d = [dev(cfg_[k], np.float64) for k in ("sigma", "eps")]
+        off = dev(cfg_["inst_off"], np.int64)
+        r = [dev(cfg_[k], np.float64) for k in ("box", "pos", "nH", "NH", "xHI", "T")]
+        torch.cuda.synchronize()
+        return RT.load().rt_init(C.byref(handle), C.byref(params), ptr(d[0], C.c_double), ptr(d[1], C.c_double),
+                                 int(cfg_["inst_off"].shape[0] - 1), ptr(off, C.c_int64),
+                                 *[ptr(t, C.c_double) for t in r], C.c_void_p(stream_ptr))
+
+    host = RT.Context(cfg, precision="fp64")
+    monkeypatch.setattr(RT, "init_call", dev_init_call)
+    devc = RT.Context(cfg, precision="fp64", add_sources=False)
+    src = cfg["sources"]
+    ts = [dev(src["inst"], np.int32), dev(src["kind"], np.int32), dev(src["pos"], np.float64),
+          dev(src["rate"], np.float64), dev(src["n_side"], np.int32)]
+    torch.cuda.synchronize()
+    st = RT.load().rt_add_sources(devc.h, len(src["inst"]), ptr(ts[0], C.c_int32), ptr(ts[1], C.c_int32),
+                                  ptr(ts[2], C.c_double), ptr(ts[3], C.c_double), ptr(ts[4], C.c_int32))
+    assert st == RT.RT_OK
+    host.step(5)
+    devc.step(5)
+    sh, sd = host.state(), devc.state()
+    for k in ("xHI", "T", "A", "P", "ledger", "counters"):
+        assert np.array_equal(sh[k], sd[k]), k
+    # outputs into device memory
+    N, nf = devc.N, devc.nf
+    out = [torch.empty(N, dtype=torch.float64, device="cuda"), torch.empty(N, dtype=torch.float64, device="cuda"),
+           torch.empty(N * nf, dtype=torch.float64, device="cuda"), torch.empty(N * nf, dtype=torch.float64, device="cuda"),
+           torch.empty(devc.n_inst * nf * 5, dtype=torch.float64, device="cuda")]
+    cnt = torch.empty(4, dtype=torch.int64, device="cuda")
+    assert RT.load().rt_get_state(devc.h, *[ptr(t, C.c_double) for t in out], ptr(cnt, C.c_int64)) == RT.RT_OK
+    torch.cuda.synchronize()
+    assert np.array_equal(out[0].cpu().numpy(), sd["xHI"])
+    assert np.array_equal(out[2].cpu().numpy().reshape(N, nf), sd["A"])
+    assert np.array_equal(out[4].cpu().numpy().reshape(sd["ledger"].shape), sd["ledger"])
+    assert np.array_equal(cnt.cpu().numpy(), sd["counters"])
+    host.close()
+    devc.close()
