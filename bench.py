@@ -28,7 +28,8 @@ emission and the photon ledger.
             taken on the current kernel sources.
 
 Extra rows: the 64^3 Stromgren workload (FP32 vs FP64), the two schemes of
-emitting recombination radiation on it (section 2.2), the 128^3 shadow
+emitting recombination radiation on it (section 2.2), the 256^3 clustered field
+(FP32 only: its FP64 state would not fit beside it), the 128^3 shadow
 set-up (three blackbody bins + RR, N_TC = N_RC = N_EC = 16, heating and
 cooling; FP32 vs FP64), the batch solved one instance at a time in FP64, the
 intensity-profile diagnostic and the CPU oracle (the baseline, not the
@@ -90,6 +91,8 @@ def dense_bytes_per_hop(cfg, fp32):
 
 
 FORCE_SHAPE = -1   # --hop-shape
+CLUSTERED_LABEL = ("256^3 clustered field (16.8 M particles from a lognormal density in a 10 Mpc box, 1024 "
+                   "sources, 4 blackbody bins + RR padded to 8, N_ngb=48, N_TC=N_EC=32, N_RC=8, heating and cooling)")
 
 
 def tuned_shape(cfg, steps, precision="fp32"):
@@ -245,6 +248,34 @@ def rr_scheme_row(cfg, W, K):
     return out
 
 
+def fp32_row(cfg, W, K, label):
+    """FP32 transport only (the FP64 state of the full clustered field would not
+    fit beside it): rate, per-step split and the forward step's launches."""
+    import torch
+    sh = tuned_shape(cfg, W + K)["shape"]
+    torch.cuda.reset_peak_memory_stats()
+    r = run_timed(cfg, "fp32", W, K, shape=sh)
+    peak = torch.cuda.max_memory_allocated()
+    st = r["state"]
+    r["ctx"].close()
+    rt = run_timed(cfg, "fp32", W, K, timing=True, shape=sh)
+    tm = rt["timing"]
+    rt["ctx"].close()
+    launches = max(1.0, tm["hop_launches"])
+    print(f"{label}: fp32 {r['t']:.3f} s over {K} steps", file=sys.stderr, flush=True)
+    return {
+        "workload": label,
+        "steps": f"{W}..{W + K - 1}",
+        "fp32_updates_per_s": r["updates"] / r["t"],
+        "fp32_ms_per_step": r["t"] / K * 1e3,
+        "ledger_residual_fp32": residual(st["ledger"]),
+        "forward_steps_per_step": r["hops"] / K,
+        "device_memory_peak_GB": peak / 1e9,
+        "k_hop_float_avg_launch_ms": tm["hop_ms"] / launches,
+        "time_split_ms_per_step": {k: tm[k] / K for k in ("hop_ms", "vip_ms", "chem_ms", "emit_ms", "ledger_ms")},
+    }
+
+
 def pair_row(cfg, W, K, label):
     """FP32 and FP64 over the same window: rates (work counted on FP64), the
     forward-step kernel's time per launch and the dense-model bandwidth, and
@@ -298,7 +329,7 @@ def main():
     ap.add_argument("--headline-only", action="store_true", help="skip the extra rows")
     ap.add_argument("--hop-shape", type=int, default=-1,
                     help="forward-step launch configuration 0..5 for every run (-1: the library's tuner picks)")
-    ap.add_argument("--only", choices=["stromgren64_rr", "shadow128", "rr_schemes"], default=None,
+    ap.add_argument("--only", choices=["stromgren64_rr", "shadow128", "rr_schemes", "clustered256"], default=None,
                     help="run one extra row alone and print it (for profiling); no headline line")
     ap.add_argument("--c3-warmup", type=int, default=2)
     ap.add_argument("--c3-steps", type=int, default=3)
@@ -330,6 +361,9 @@ def main():
     FORCE_SHAPE = args.hop_shape
     if args.only == "stromgren64_rr":
         print(json.dumps({"stromgren64_rr": pair_row(I.config(2), W, K, "64^3 Stromgren with RR")}), flush=True)
+        return
+    if args.only == "clustered256":
+        print(json.dumps({"clustered256": fp32_row(I.config(5), 1, 2, CLUSTERED_LABEL)}), flush=True)
         return
     if args.only == "rr_schemes":
         print(json.dumps({"rr_schemes_stromgren64": rr_scheme_row(I.config(2), W, K)}), flush=True)
@@ -441,6 +475,7 @@ def main():
         out["stromgren64_rr"]["shell_profile"] = shell_profile_timing(rp["ctx"], c2)
         rp["ctx"].close()
         out["rr_schemes_stromgren64"] = rr_scheme_row(c2, W, K)
+        out["clustered256"] = fp32_row(I.config(5), 1, 2, CLUSTERED_LABEL)
         c3 = I.config(3)
         out["shadow128"] = pair_row(c3, args.c3_warmup, args.c3_steps,
                                     "128^3 shadow set-up (2097152 particles, plane front, 3 blackbody bins + RR, "

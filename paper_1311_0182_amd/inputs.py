@@ -455,10 +455,83 @@ def chain(n=12, spacing_kpc=0.1, n_h=1e-3, x_hi=1e-3, **pkw):
     return _pack("chain", params, [SIGMA_13P6], [0.0], [inst], src, 1)
 
 
+def lognormal_density(n_mesh, sigma_g, slope, rng):
+    """A lognormal density on an n_mesh^3 periodic mesh: a Gaussian random
+    field g with power spectrum P(k) ~ k^slope (the k = 0 mode removed), scaled
+    to variance sigma_g^2, and rho = exp(g - sigma_g^2 / 2) (mean 1 in
+    expectation)."""
+    white = rng.standard_normal((n_mesh, n_mesh, n_mesh))
+    fk = np.fft.rfftn(white)
+    kx = np.fft.fftfreq(n_mesh)
+    kz = np.fft.rfftfreq(n_mesh)
+    k2 = kx[:, None, None] ** 2 + kx[None, :, None] ** 2 + kz[None, None, :] ** 2
+    amp = np.zeros_like(k2)
+    nz = k2 > 0
+    amp[nz] = k2[nz] ** (slope / 4.0)    # sqrt(P(k)) = k^(slope / 2)
+    g = np.fft.irfftn(fk * amp, s=(n_mesh, n_mesh, n_mesh))
+    g *= sigma_g / g.std()
+    return np.exp(g - 0.5 * sigma_g * sigma_g)
+
+
+def clustered(n_side=256, box_mpc=10.0, n_h=1e-3, sigma_g=1.5, slope=-2.5, n_src=1024, ndot_lo=1e48,
+              ndot_hi=1e52, n_ngb=48, n_tc=32, n_rc=8, n_ec=32, t0=100.0, n_steps=20, seed_k=5, dt_myr=0.1,
+              vip_capacity=1 << 25, **pkw):
+    """The large clustered field: n_side^3 equal-mass particles sampled from a
+    lognormal density on an n_side^3 mesh in a box_mpc cube (cell counts N
+    rho_c / sum rho by largest-remainder rounding, ties to the lower cell index;
+    uniform within cells); a particle's n_H is that of its cell (mean n_h), its
+    N_H the same for all.  n_src point sources at the densest particles (ties to
+    the lower index) with Ndot drawn from dN/dNdot ~ Ndot^-2 between ndot_lo and
+    ndot_hi; a 1e5 K blackbody in four grey bins (13.6-18-24.6-54.4-100 eV) and
+    the recombination bin, padded with three empty bins so that a particle's
+    packet slots (n_rc x 8) fill one wavefront: n_rc = 8, where the paper-scale
+    recipe would use 32.  Photoheating and cooling from T0 = 100 K."""
+    rng = np.random.default_rng(BASE_SEED + seed_k)
+    L = box_mpc * 1e3 * KPC_CM
+    n = n_side
+    rho = lognormal_density(n, sigma_g, slope, rng)
+    N = n ** 3
+    q = N * rho.ravel() / rho.sum()
+    cnt = np.floor(q).astype(np.int64)
+    rest = N - int(cnt.sum())
+    if rest > 0:
+        order = np.argsort(-(q - cnt), kind="stable")
+        cnt[order[:rest]] += 1
+    cells = np.repeat(np.arange(n ** 3, dtype=np.int64), cnt)
+    ijk = np.stack([cells // (n * n), (cells // n) % n, cells % n], axis=1).astype(np.float64)
+    dx = L / n
+    pos = (ijk + rng.random((N, 3))) * dx
+    pos = np.minimum(pos, np.nextafter(L, 0.0))
+    dens = rho.ravel() / rho.mean()
+    nh = n_h * dens[cells]
+    NH = np.full(N, n_h * L ** 3 / N)
+    xhi = np.ones(N)
+    T = np.full(N, t0)
+    frac, sig, eps = blackbody_grey_bins(1e5, (13.6, 18.0, 24.6, 54.4, 100.0))
+    n_freq = 8
+    rr_bin = 4
+    params = default_params(
+        n_ngb=n_ngb, n_tc=n_tc, n_rc=n_rc, n_ec=n_ec, n_freq=n_freq, rr_bin=rr_bin,
+        recomb_mode=RR_TRANSPORT, isothermal=0, dt=dt_myr * MYR_S, n_em=1,
+        seed=BASE_SEED + seed_k, vip_capacity=vip_capacity)
+    params.update(pkw)
+    sigma = list(sig) + [SIGMA_13P6] * 4
+    eps_erg = [e * EV_ERG for e in eps] + [EPS_RR_EV * EV_ERG] + [0.0] * 3
+    dense = np.argsort(-nh, kind="stable")[:n_src]
+    u = rng.random(n_src)
+    ndot = 1.0 / (1.0 / ndot_lo - u * (1.0 / ndot_lo - 1.0 / ndot_hi))
+    rate = np.zeros((n_src, n_freq))
+    rate[:, :4] = ndot[:, None] * np.asarray(frac)[None, :]
+    src = _point_sources(np.zeros(n_src, np.int32), pos[dense], rate)
+    inst = dict(pos=pos, nH=nh, NH=NH, xHI=xhi, T=T, box_lo=np.zeros(3), box_hi=np.full(3, L))
+    return _pack(f"clustered{n_side}", params, sigma, eps_erg, [inst], src, n_steps)
+
+
 def config(k, **kw):
     """Named workloads: 1 = 16^3 Stromgren case B (FP64), 2 = 64^3 with recombination
     radiation (FP32 vs FP64), 3 = 128^3 shadow set-up (plane front, blackbody bins,
-    clump, heating and cooling), 4 = 64 batched instances with recombination radiation."""
+    clump, heating and cooling), 4 = 64 batched instances with recombination radiation,
+    5 = 256^3 particles of a clustered (lognormal) field with 1024 sources."""
     if k == 1:
         return stromgren(16, rr=False, n_ngb=32, n_steps=100, seed_k=1, **kw)
     if k == 2:
@@ -467,6 +540,8 @@ def config(k, **kw):
         return shadow(**kw)
     if k == 4:
         return batched(**kw)
+    if k == 5:
+        return clustered(**kw)
     raise ValueError(f"unknown workload {k}")
 
 

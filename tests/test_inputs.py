@@ -141,3 +141,37 @@ def test_shadow_boundary_layout():
     fast = I.shadow_boundary(n_side=8, n_pp=10, n_bd=5, flux=2e6)
     x2 = fast["boundary"]["pos"][I.boundary_schedule(fast, t), 0].max()
     assert x2 > x1 and abs(1e6 * t / 1e-3 - x1) < L / 5 and abs(2e6 * t / 1e-3 - x2) < L / 5
+
+
+def test_clustered_field_recipe():
+    # the lognormal recipe: g has the requested variance and a power spectrum
+    # falling as k^-2.5; rho = exp(g - sigma^2/2) has mean 1 up to sampling;
+    # cell counts by largest remainder give exactly N particles, each in its
+    # cell, carrying that cell's density; the sources sit at the densest
+    # particles with luminosities inside [1e48, 1e52]
+    rng = np.random.default_rng(3)
+    rho = I.lognormal_density(64, 1.5, -2.5, rng)
+    g = np.log(rho) + 0.5 * 1.5 ** 2
+    assert abs(g.std() - 1.5) < 1e-9
+    assert abs(rho.mean() - 1.0) < 0.2
+    fk = np.abs(np.fft.rfftn(g)) ** 2
+    kx = np.fft.fftfreq(64)
+    kz = np.fft.rfftfreq(64)
+    k = np.sqrt(kx[:, None, None] ** 2 + kx[None, :, None] ** 2 + kz[None, None, :] ** 2)
+    sel1 = (k > 0.04) & (k < 0.06)
+    sel2 = (k > 0.16) & (k < 0.24)
+    slope = np.log(fk[sel2].mean() / fk[sel1].mean()) / np.log(k[sel2].mean() / k[sel1].mean())
+    assert abs(slope + 2.5) < 0.15, slope
+    cfg = I.clustered(n_side=24, n_src=32, box_mpc=1.0)
+    N = 24 ** 3
+    L = float(cfg["box"][0][3])
+    assert cfg["pos"].shape == (N, 3)
+    assert np.all((cfg["pos"] >= 0) & (cfg["pos"] < L))
+    assert np.all(cfg["NH"] == cfg["NH"][0])
+    assert abs(cfg["NH"][0] - 1e-3 * L ** 3 / N) <= 1e-12 * cfg["NH"][0]
+    dens = np.sort(cfg["nH"])[::-1]
+    src = cfg["sources"]
+    assert np.all(np.sort(cfg["nH"][np.isin(np.arange(N), np.nonzero(np.isin(cfg["pos"], src["pos"]).all(1))[0])])[::-1] >= dens[31])
+    tot = src["rate"][:, :4].sum(axis=1)
+    assert np.all((tot >= 1e48 * (1 - 1e-12)) & (tot <= 1e52 * (1 + 1e-12)))
+    assert cfg["params"]["n_rc"] * cfg["params"]["n_freq"] == 64
