@@ -468,7 +468,7 @@ def lognormal_density(n_mesh, sigma_g, slope, rng):
     amp = np.zeros_like(k2)
     nz = k2 > 0
     amp[nz] = k2[nz] ** (slope / 4.0)    # sqrt(P(k)) = k^(slope / 2)
-    g = np.fft.irfftn(fk * amp, s=(n_mesh, n_mesh, n_mesh))
+    g = np.fft.irfftn(fk * amp, s=(n_mesh, n_mesh, n_mesh), axes=(0, 1, 2))
     g *= sigma_g / g.std()
     return np.exp(g - 0.5 * sigma_g * sigma_g)
 
