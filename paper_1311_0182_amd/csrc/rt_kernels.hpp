@@ -1217,6 +1217,7 @@ struct HopArgs {
     int list_wr;
     long long* cnt;
     unsigned long long* part;  // [tile][3]: packets moved, bytes, forward steps run (summed per RT step)
+    int* listlen;              // [max_hops + 2]: tiles on each forward step's list (the host sizes grids by it)
     int act_rd, act_wr;
 };
 
@@ -2222,12 +2223,15 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
             a.cnt[kCntDeep] = 0;  // and its virtual particles all handled
             // the next forward step's list count starts from zero
             a.cnt[kCntTileList + ((a.hop + 1) & 1)] = 0;
+            if (!a.hop0) a.listlen[a.hop] = static_cast<int>(c_list);
         }
     }
     // 32-bit arithmetic and shifts only: every workgroup, also the surplus
-    // ones, runs this before it exits
+    // ones, runs this before it exits.  The grid may be smaller than the list
+    // (sized from earlier steps): k_hop_tail takes the tiles past its end.
     const unsigned int n = static_cast<unsigned int>(a.hop0 ? a.ntiles : (c_list < a.ntiles ? c_list : a.ntiles));
-    const unsigned int nb = (n + (1u << a.lg_wpb) - 1u) >> a.lg_wpb;  // workgroups with tiles
+    const unsigned int nb0 = (n + (1u << a.lg_wpb) - 1u) >> a.lg_wpb;  // workgroups' worth of tiles
+    const unsigned int nb = nb0 < gridDim.x ? nb0 : gridDim.x;          // of them in this grid
     if (idle | capped | (blockIdx.x >= nb)) return;
     const unsigned int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
     const unsigned int e = (xcd_block32(blockIdx.x, nb) << a.lg_wpb) + wv;
@@ -2246,6 +2250,31 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
         e_t1 = static_cast<unsigned int>(w.z);
     }
     hop_tile<R, DT, S, kExt>(a, tile, e_t0, e_t1, stamp, threadIdx.x & 63u, lds_all + static_cast<size_t>(wv) * a.lds_wave);
+}
+
+// The tiles of a forward step's list past the end of k_hop's grid (a grid sized
+// from earlier steps' lists, so that launches dispatch few workgroups that
+// have nothing to do): a small grid takes them in turn.  Usually there are
+// none and every workgroup exits at once.  No step bookkeeping here.
+template <typename R, typename DT, typename S, bool kExt>
+__global__ __launch_bounds__(256) void k_hop_tail(HopArgs<R, DT> a, unsigned int covered) {
+    extern __shared__ __align__(32) unsigned char lds_all[];
+    const long long c_done = a.cnt[kCntDone];
+    const long long c_act = a.cnt[kCntAct0 + kCntLine * a.act_rd];
+    const long long c_serial = a.cnt[kCntSerial];
+    const long long c_list = a.cnt[kCntTileList + (a.hop & 1)];
+    const int stamp = static_cast<int>(c_serial) + a.hop;
+    const bool idle = (c_done != 0) | (c_act == 0);
+    const unsigned int n = static_cast<unsigned int>(c_list < a.ntiles ? c_list : a.ntiles);
+    if (idle | (a.hop > a.max_hops) | (n <= covered)) return;
+    const unsigned int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (unsigned int g = (covered >> a.lg_wpb) + blockIdx.x;; g += gridDim.x) {
+        const unsigned int e = (g << a.lg_wpb) + wv;
+        if (e >= n) break;
+        const int4 w = a.tlist[e];
+        hop_tile<R, DT, S, kExt>(a, w.x, static_cast<unsigned int>(w.y), static_cast<unsigned int>(w.z), stamp,
+                                 threadIdx.x & 63u, lds_all + static_cast<size_t>(wv) * a.lds_wave);
+    }
 }
 
 // The tiles marked for forward step `hop` (tile mark == its stamp), listed with

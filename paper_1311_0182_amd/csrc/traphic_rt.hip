@@ -166,6 +166,11 @@ struct rt_ctx {
     std::map<long long, hipGraphExec_t> step_graphs;  // whole RT steps, by 2 * forward steps + RR buffer parity
     bool step_graphs_on = false;                      // rt_set_step_graphs
     bool capturing = false;                           // a whole step is being captured: its kernels obey the halt word
+    // forward-step grids: the longest tile list seen per forward step index,
+    // from the device's record of each step's lists
+    int* listlen = nullptr;
+    int* h_listlen = nullptr;                         // pinned copy
+    std::vector<long long> est_tiles;
     // autotuner of the forward-step shape: -1 tune once work is representative
     int hop_shape = 0;
     int tune_mode = -1;        // -1 automatic, -2 tune now, 0..kHopShapes-1 fixed by the caller
@@ -294,6 +299,18 @@ void direction_set(int n, std::vector<double>& u) {
 
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
+constexpr long long kHopTailWGs = 256;
+
+// Workgroups for a forward step whose list has had up to `tiles` tiles: a
+// quarter more, rounded up to a power of two (so that graphs captured with it
+// stay valid while the lists grow a little), at least 64.
+long long grid_estimate(long long tiles, int wpb) {
+    const long long want = (tiles + tiles / 4 + wpb - 1) / wpb + 1;
+    long long g = 64;
+    while (g < want) g <<= 1;
+    return g;
+}
+
 template <typename R, typename DT, typename S, bool kBar>
 rt_status launch_hop(rt_ctx* c, int hop, bool pack) {
     HopArgs<R, DT> a{};
@@ -366,6 +383,7 @@ rt_status launch_hop(rt_ctx* c, int hop, bool pack) {
     a.list_wr = (hop + 1) & 1;
     a.cnt = c->cnt;
     a.part = c->part;
+    a.listlen = c->listlen;
     a.act_rd = hop & 1;
     a.act_wr = (hop + 1) & 1;
     // 1, 2 or 4 tiles (wavefronts) per workgroup, as many as 64 KiB of LDS hold
@@ -375,9 +393,21 @@ rt_status launch_hop(rt_ctx* c, int hop, bool pack) {
     const int wpb = 1 << a.lg_wpb;
     a.lds_wave = static_cast<unsigned int>(lds_wave);
     const size_t lds = lds_wave * wpb;
-    const long long n_wg = (c->ntiles + wpb - 1) / wpb;
+    const long long n_full = (c->ntiles + wpb - 1) / wpb;
+    // after hop 0 the grid is sized from the longest list this forward step
+    // has had (plus a quarter, rounded up to a power of two of workgroups), so
+    // that late, sparse forward steps do not dispatch a workgroup per tile;
+    // k_hop_tail takes any tiles past its end
+    long long n_wg = n_full;
+    if (hop > 0 && hop < static_cast<int>(c->est_tiles.size()) && c->est_tiles[hop] > 0)
+        n_wg = std::min(n_full, grid_estimate(c->est_tiles[hop], wpb));
     hipLaunchKernelGGL((k_hop<R, DT, S, kBar>), dim3(static_cast<unsigned>(n_wg)), dim3(64 * wpb), lds, c->stream, a);
     HIPCHK(c, hipGetLastError());
+    if (n_wg < n_full) {
+        hipLaunchKernelGGL((k_hop_tail<R, DT, S, kBar>), dim3(static_cast<unsigned>(kHopTailWGs)), dim3(64 * wpb), lds,
+                           c->stream, a, static_cast<unsigned int>(n_wg * wpb));
+        HIPCHK(c, hipGetLastError());
+    }
     return RT_OK;
 }
 
@@ -848,6 +878,22 @@ rt_status step_tail(rt_ctx* c, long long launched, bool graph) {
     return RT_OK;
 }
 
+// The forward steps' list lengths of the last step (copied to the pinned
+// mirror with the counters): the longest seen per forward step sizes its grid.
+// A grid that changes drops the captured graphs, which hold the old one.
+void absorb_list_lengths(rt_ctx* c, long long H) {
+    bool changed = false;
+    const long long top = std::min<long long>(H, static_cast<long long>(c->est_tiles.size()) - 1);
+    for (long long q = 1; q <= top; ++q) {
+        const long long seen = c->h_listlen[q];
+        if (seen <= c->est_tiles[q]) continue;
+        for (int w = 1; w <= 4; w <<= 1)
+            changed = changed || c->est_tiles[q] == 0 || grid_estimate(seen, w) != grid_estimate(c->est_tiles[q], w);
+        c->est_tiles[q] = seen;
+    }
+    if (changed) drop_graphs(c);
+}
+
 // Host bookkeeping after a step that ran H forward steps with `launched`
 // launches, then the counters read back (tuning and timing use them).
 rt_status step_done(rt_ctx* c, long long H, long long launched) {
@@ -856,7 +902,10 @@ rt_status step_done(rt_ctx* c, long long H, long long launched) {
     c->nrr_cur ^= 1;
     c->step += 1;
     HIPCHK(c, hipMemcpyAsync(c->h_cnt, c->cnt, sizeof(long long) * kCntN, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->h_listlen, c->listlen, sizeof(int) * c->est_tiles.size(), hipMemcpyDeviceToHost,
+                             c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    absorb_list_lengths(c, H);
     if (c->tuning_now) {
         for (long long q = 1; q <= H; ++q) {
             c->tune_ms[q % kHopShapes] += elapsed(c, 3 + 2 * q);
@@ -982,6 +1031,8 @@ rt_status graph_steps(rt_ctx* c, int n, int* done, bool* hopcap) {
         ++launched_steps;
     }
     HIPCHK(c, hipMemcpyAsync(c->h_cnt, c->cnt, sizeof(long long) * kCntN, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->h_listlen, c->listlen, sizeof(int) * c->est_tiles.size(), hipMemcpyDeviceToHost,
+                             c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const long long halt = c->h_cnt[kCntHalt];
     const long long started = c->h_cnt[kCntSteps] - step0;  // the step counter counts a step at its start
@@ -990,6 +1041,7 @@ rt_status graph_steps(rt_ctx* c, int n, int* done, bool* hopcap) {
     c->nrr_cur = cur0 ^ static_cast<int>(finished & 1);
     c->serial = c->h_cnt[kCntSerial];
     if (finished > 0) c->last_hops = c->h_cnt[kCntLastHops];
+    if (finished > 0) absorb_list_lengths(c, c->last_hops);
     *done = static_cast<int>(finished);
     if (halt == 0) return RT_OK;
     hipLaunchKernelGGL(k_clear_halt, dim3(1), dim3(64), 0, c->stream, c->cnt);
@@ -1332,6 +1384,10 @@ rt_status init_impl(rt_ctx** out, const rt_params* p, const double* sigma_nu, co
     ITRY(alloc_n(c, &c->cnt, kCntN));
     HIPCHK(c, hipMemsetAsync(c->cnt, 0, sizeof(long long) * kCntN, c->stream));
     HIPCHK(c, hipHostMalloc(reinterpret_cast<void**>(&c->h_cnt), sizeof(long long) * kCntN, hipHostMallocDefault));
+    HIPCHK(c, hipHostMalloc(reinterpret_cast<void**>(&c->h_listlen), sizeof(int) * (p->max_hops + 2), hipHostMallocDefault));
+    ITRY(alloc_n(c, &c->listlen, p->max_hops + 2ll));
+    ITRY(fill_i32(c, c->listlen, p->max_hops + 2ll, 0));
+    c->est_tiles.assign(p->max_hops + 2, 0);
     ITRY(alloc_n(c, &c->led, 5ll * n_inst * c->nf));
     ITRY(fill_f64(c, c->led, 5ll * n_inst * c->nf, 0.0));
     ITRY(alloc_n(c, &c->scale, 1ll * n_inst * c->nf));
@@ -2033,6 +2089,7 @@ void rt_destroy(rt_ctx* c) {
     }
     for (auto e : c->ev) (void)hipEventDestroy(e);
     if (c->h_cnt) (void)hipHostFree(c->h_cnt);
+    if (c->h_listlen) (void)hipHostFree(c->h_listlen);
     delete c;
 }
 
