@@ -300,6 +300,7 @@ void direction_set(int n, std::vector<double>& u) {
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 constexpr long long kHopTailWGs = 256;
+constexpr long long kHopUnseenWGs = 1024;
 
 // Workgroups for a forward step whose list has had up to `tiles` tiles: a
 // quarter more, rounded up to a power of two (so that graphs captured with it
@@ -396,11 +397,12 @@ rt_status launch_hop(rt_ctx* c, int hop, bool pack) {
     const long long n_full = (c->ntiles + wpb - 1) / wpb;
     // after hop 0 the grid is sized from the longest list this forward step
     // has had (plus a quarter, rounded up to a power of two of workgroups), so
-    // that late, sparse forward steps do not dispatch a workgroup per tile;
-    // k_hop_tail takes any tiles past its end
+    // that late, sparse forward steps do not dispatch a workgroup per tile; a
+    // forward step not seen yet gets kHopUnseenWGs; k_hop_tail takes any tiles
+    // past the end of the grid
     long long n_wg = n_full;
-    if (hop > 0 && hop < static_cast<int>(c->est_tiles.size()) && c->est_tiles[hop] > 0)
-        n_wg = std::min(n_full, grid_estimate(c->est_tiles[hop], wpb));
+    if (hop > 0 && hop < static_cast<int>(c->est_tiles.size()))
+        n_wg = std::min(n_full, c->est_tiles[hop] > 0 ? grid_estimate(c->est_tiles[hop], wpb) : kHopUnseenWGs);
     hipLaunchKernelGGL((k_hop<R, DT, S, kBar>), dim3(static_cast<unsigned>(n_wg)), dim3(64 * wpb), lds, c->stream, a);
     HIPCHK(c, hipGetLastError());
     if (n_wg < n_full) {
