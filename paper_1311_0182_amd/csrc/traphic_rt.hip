@@ -299,8 +299,10 @@ void direction_set(int n, std::vector<double>& u) {
 
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
-constexpr long long kHopTailWGs = 256;
+constexpr long long kHopTailMinWGs = 256;
+constexpr long long kHopTailMaxWGs = 65536;
 constexpr long long kHopUnseenWGs = 1024;
+constexpr long long kHopUnseenTailWGs = 8192;
 
 // Workgroups for a forward step whose list has had up to `tiles` tiles: a
 // quarter more, rounded up to a power of two (so that graphs captured with it
@@ -399,14 +401,23 @@ rt_status launch_hop(rt_ctx* c, int hop, bool pack) {
     // has had (plus a quarter, rounded up to a power of two of workgroups), so
     // that late, sparse forward steps do not dispatch a workgroup per tile; a
     // forward step not seen yet gets kHopUnseenWGs; k_hop_tail takes any tiles
-    // past the end of the grid
-    long long n_wg = n_full;
-    if (hop > 0 && hop < static_cast<int>(c->est_tiles.size()))
-        n_wg = std::min(n_full, c->est_tiles[hop] > 0 ? grid_estimate(c->est_tiles[hop], wpb) : kHopUnseenWGs);
+    // past the end of the grid.  Its grid is a 64th of k_hop's, at least 256
+    // workgroups (a list that outgrows its estimate, as the lists of a front
+    // advancing step by step do, then still fills the chip, while a tail with
+    // nothing to do dispatches few workgroups), and kHopUnseenTailWGs for a
+    // forward step not seen yet
+    long long n_wg = n_full, n_tail = kHopUnseenTailWGs;
+    if (hop > 0 && hop < static_cast<int>(c->est_tiles.size()) && c->est_tiles[hop] > 0) {
+        n_wg = std::min(n_full, grid_estimate(c->est_tiles[hop], wpb));
+        n_tail = std::min(kHopTailMaxWGs, std::max(kHopTailMinWGs, n_wg / 64));
+    } else if (hop > 0) {
+        n_wg = std::min(n_full, kHopUnseenWGs);
+    }
     hipLaunchKernelGGL((k_hop<R, DT, S, kBar>), dim3(static_cast<unsigned>(n_wg)), dim3(64 * wpb), lds, c->stream, a);
     HIPCHK(c, hipGetLastError());
     if (n_wg < n_full) {
-        hipLaunchKernelGGL((k_hop_tail<R, DT, S, kBar>), dim3(static_cast<unsigned>(kHopTailWGs)), dim3(64 * wpb), lds,
+        n_tail = std::min(n_full - n_wg, n_tail);
+        hipLaunchKernelGGL((k_hop_tail<R, DT, S, kBar>), dim3(static_cast<unsigned>(n_tail)), dim3(64 * wpb), lds,
                            c->stream, a, static_cast<unsigned int>(n_wg * wpb));
         HIPCHK(c, hipGetLastError());
     }
