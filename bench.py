@@ -97,9 +97,10 @@ CLUSTERED_LABEL = ("256^3 clustered field (16.8 M particles from a lognormal den
 
 def tuned_shape(cfg, steps, precision="fp32"):
     """The library's autotuner run over the same workload in an untimed
-    pass (steps RT steps; if none of them needs 16 forward steps, the tuner is
-    made to time the configurations on the last 3 of them).  Returns
-    rt_get_hop_shape's report; the timed runs then use the chosen one."""
+    pass (steps RT steps, at least 3; if the tuner has not finished by the last
+    3 of them, it is made to time the configurations on those 3, the number of
+    RT steps it times them over).  Returns rt_get_hop_shape's report; the
+    timed runs then use the chosen one."""
     from paper_1311_0182_amd import traphic_rt as RT
     if FORCE_SHAPE >= 0:
         return dict(shape=FORCE_SHAPE, tuned=False, ms_per_launch=[0.0] * 6)
@@ -107,7 +108,7 @@ def tuned_shape(cfg, steps, precision="fp32"):
     ctx.step(max(0, steps - 3))
     if not ctx.hop_shape()["tuned"]:
         ctx.set_hop_shape(-2)
-    ctx.step(3)
+        ctx.step(3)
     out = ctx.hop_shape()
     ctx.close()
     return out
@@ -284,7 +285,8 @@ def pair_row(cfg, W, K, label):
     sh32 = tuned_shape(cfg, W + K)["shape"]
     r32 = run_timed(cfg, "fp32", W, K, shape=sh32)
     r32["ctx"].close()
-    r64 = run_timed(cfg, "fp64", W, K, shape=tuned_shape(cfg, W + K, "fp64")["shape"])
+    sh64 = tuned_shape(cfg, W + K, "fp64")["shape"]
+    r64 = run_timed(cfg, "fp64", W, K, shape=sh64)
     r64["ctx"].close()
     rt = run_timed(cfg, "fp32", W, K, timing=True, shape=sh32)
     tm = rt["timing"]
@@ -306,6 +308,7 @@ def pair_row(cfg, W, K, label):
         "max_abs_dx_HI_at_end": float(np.max(np.abs(r32["state"]["xHI"] - r64["state"]["xHI"]))),
         "ledger_residual_fp32": residual(r32["state"]["ledger"]),
         "forward_steps_per_step": r64["hops"] / K,
+        "hop_shape": {"fp32": sh32, "fp64": sh64},
         "k_hop_float": {
             "avg_launch_ms": avg_ms,
             "launches": int(tm["hop_launches"]),

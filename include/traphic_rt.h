@@ -250,10 +250,14 @@ rt_status rt_get_timing(rt_ctx *ctx, double *out, int32_t n);
  * 64); shapes 3..5 are 0..2 with up to four tiles (independent wavefronts)
  * per workgroup, which cuts the workgroups a launch dispatches when few tiles
  * have work.  All configurations give identical results.  shape = -1 (the
- * default) lets the library choose: once an RT step needs at least 16 forward
- * steps, the next 3 steps time the configurations on alternate forward steps
- * and the fastest is kept; shape = -2 times them on the next 3 steps whatever
- * their size.  RT_EINVAL for another value.  rt_get_hop_shape reports the
+ * default) lets the library choose among shapes 0..2 (with grids sized from
+ * the lists, packing only lowers occupancy once the lists reach their working
+ * size): once an RT step needs at least 16 forward steps, the next 3 steps
+ * time them (each runs every third forward step, the assignment turning by
+ * one from step to step, so that each runs every forward-step index once;
+ * forward steps whose list outgrew its grid are not counted) and the fastest
+ * per launch is kept; shape = -2 times them on the next 3 steps whatever
+ * their size.  The tuner's ms per launch of shapes 3..5 reads 0.  RT_EINVAL for another value.  rt_get_hop_shape reports the
  * configuration in use, whether the tuner chose it, and the tuner's mean ms
  * per launch of each (6 doubles, 0 if not timed); any pointer may be NULL. */
 rt_status rt_set_hop_shape(rt_ctx *ctx, int32_t shape);

@@ -43,6 +43,16 @@ std::mutex g_scratch_mu;
 void* g_scratch[kMaxDevices] = {};
 }  // namespace
 
+// The tuner times the configurations with one tile per workgroup.  Packing
+// up to four tiles per workgroup cut the dispatch of workgroups with nothing
+// to do while every forward step dispatched one per tile; with grids sized
+// from the lists, packing only lowers the occupancy that LDS allows (measured
+// slower on the batched HII regions and the 64^3 Stromgren sphere once the
+// lists reach their working size,
+// though not in the first RT steps, where the tuner would see them), so the
+// packed configurations are used only when asked for.
+constexpr int kTuneShapes = kHopShapeKinds;
+
 struct rt_ctx {
     rt_params p{};
     hipStream_t stream = nullptr;
@@ -171,10 +181,11 @@ struct rt_ctx {
     int* listlen = nullptr;
     int* h_listlen = nullptr;                         // pinned copy
     std::vector<long long> est_tiles;
+    std::vector<long long> cap_tiles;                 // tiles the main grid of each forward step covered
     // autotuner of the forward-step shape: -1 tune once work is representative
     int hop_shape = 0;
     int tune_mode = -1;        // -1 automatic, -2 tune now, 0..kHopShapes-1 fixed by the caller
-    int tune_steps_left = 3;   // RT steps that time the shapes (alternating per forward step)
+    int tune_steps_left = kTuneShapes;  // RT steps that time the shapes (alternating per forward step)
     double tune_ms[kHopShapes] = {};
     long long tune_n[kHopShapes] = {};
     bool tuned = false;
@@ -299,6 +310,7 @@ void direction_set(int n, std::vector<double>& u) {
 
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
+constexpr long long kHopMinSavedWGs = 65536;
 constexpr long long kHopTailMinWGs = 256;
 constexpr long long kHopTailMaxWGs = 65536;
 constexpr long long kHopUnseenWGs = 1024;
@@ -312,6 +324,27 @@ long long grid_estimate(long long tiles, int wpb) {
     long long g = 64;
     while (g < want) g <<= 1;
     return g;
+}
+
+// The grids of forward step `hop` (> 0: hop 0 runs every tile) with `wpb`
+// tiles per workgroup, for a forward step whose list has had up to `est`
+// tiles (0: not seen yet): k_hop's workgroups, returned, and k_hop_tail's in
+// *n_tail (0: no tail).  The tail's grid is a 64th of the main one, at least
+// kHopTailMinWGs (a list that outgrows its estimate, as the lists of a front
+// advancing step by step do, then still fills the chip, while a tail with
+// nothing to do dispatches few workgroups), kHopUnseenTailWGs for a forward
+// step not seen yet.  A smaller grid pays only when it saves more workgroups
+// than the tail's launch costs (an idle workgroup costs well under a
+// nanosecond here, a launch a few microseconds): else the full grid, no tail.
+long long hop_grid(const rt_ctx* c, int hop, long long est, int wpb, long long* n_tail) {
+    const long long n_full = (c->ntiles + wpb - 1) / wpb;
+    *n_tail = 0;
+    if (hop == 0) return n_full;
+    const long long n_wg = std::min(n_full, est > 0 ? grid_estimate(est, wpb) : kHopUnseenWGs);
+    if (n_full - n_wg < kHopMinSavedWGs) return n_full;
+    const long long t = est > 0 ? std::min(kHopTailMaxWGs, std::max(kHopTailMinWGs, n_wg / 64)) : kHopUnseenTailWGs;
+    *n_tail = std::min(n_full - n_wg, t);
+    return n_wg;
 }
 
 template <typename R, typename DT, typename S, bool kBar>
@@ -398,25 +431,15 @@ rt_status launch_hop(rt_ctx* c, int hop, bool pack) {
     const size_t lds = lds_wave * wpb;
     const long long n_full = (c->ntiles + wpb - 1) / wpb;
     // after hop 0 the grid is sized from the longest list this forward step
-    // has had (plus a quarter, rounded up to a power of two of workgroups), so
-    // that late, sparse forward steps do not dispatch a workgroup per tile; a
-    // forward step not seen yet gets kHopUnseenWGs; k_hop_tail takes any tiles
-    // past the end of the grid.  Its grid is a 64th of k_hop's, at least 256
-    // workgroups (a list that outgrows its estimate, as the lists of a front
-    // advancing step by step do, then still fills the chip, while a tail with
-    // nothing to do dispatches few workgroups), and kHopUnseenTailWGs for a
-    // forward step not seen yet
-    long long n_wg = n_full, n_tail = kHopUnseenTailWGs;
-    if (hop > 0 && hop < static_cast<int>(c->est_tiles.size()) && c->est_tiles[hop] > 0) {
-        n_wg = std::min(n_full, grid_estimate(c->est_tiles[hop], wpb));
-        n_tail = std::min(kHopTailMaxWGs, std::max(kHopTailMinWGs, n_wg / 64));
-    } else if (hop > 0) {
-        n_wg = std::min(n_full, kHopUnseenWGs);
-    }
+    // has had, so that late, sparse forward steps do not dispatch a workgroup
+    // per tile; k_hop_tail takes any tiles past the end of that grid
+    long long n_tail = 0;
+    const long long n_wg = hop_grid(c, hop, hop < static_cast<int>(c->est_tiles.size()) ? c->est_tiles[hop] : 0,
+                                    wpb, &n_tail);
     hipLaunchKernelGGL((k_hop<R, DT, S, kBar>), dim3(static_cast<unsigned>(n_wg)), dim3(64 * wpb), lds, c->stream, a);
     HIPCHK(c, hipGetLastError());
-    if (n_wg < n_full) {
-        n_tail = std::min(n_full - n_wg, n_tail);
+    if (hop < static_cast<int>(c->cap_tiles.size())) c->cap_tiles[hop] = n_wg < n_full ? n_wg * wpb : c->ntiles;
+    if (n_tail > 0) {
         hipLaunchKernelGGL((k_hop_tail<R, DT, S, kBar>), dim3(static_cast<unsigned>(n_tail)), dim3(64 * wpb), lds,
                            c->stream, a, static_cast<unsigned int>(n_wg * wpb));
         HIPCHK(c, hipGetLastError());
@@ -769,6 +792,16 @@ rt_status step_front(rt_ctx* c, bool set_serial) {
     return RT_OK;
 }
 
+// The configuration a tuning step runs forward step q in: every
+// kTuneShapes-th forward step gets the same one, and the assignment turns by
+// one from one tuning step to the next, so that over the kTuneShapes tuning
+// steps each configuration runs every forward-step index (their lists differ
+// widely in length) about once.
+int tune_shape_of(const rt_ctx* c, int q) {
+    const int rot = kTuneShapes - c->tune_steps_left;
+    return (q + rot) % kTuneShapes;
+}
+
 // Forward steps h, h + 1, ... one batch at a time with a host check of the
 // device counters after each, until no packet is active or the cap is
 // reached.  Returns the forward steps run (H) and the next unlaunched index.
@@ -785,7 +818,7 @@ rt_status hop_loop(rt_ctx* c, int h, int batch, long long* H_out, int* h_out, bo
                 TRY(launch_vip(c, q));
                 TRY(time_end(c, 2 + 2 * q));
                 TRY(time_begin(c, 3 + 2 * q));
-                TRY(launch_hop_any(c, q, c->tuning_now ? q % kHopShapes : -1));
+                TRY(launch_hop_any(c, q, c->tuning_now ? tune_shape_of(c, q) : -1));
                 TRY(time_end(c, 3 + 2 * q));
             }
             h = hend + 1;
@@ -900,8 +933,12 @@ void absorb_list_lengths(rt_ctx* c, long long H) {
     for (long long q = 1; q <= top; ++q) {
         const long long seen = c->h_listlen[q];
         if (seen <= c->est_tiles[q]) continue;
-        for (int w = 1; w <= 4; w <<= 1)
-            changed = changed || c->est_tiles[q] == 0 || grid_estimate(seen, w) != grid_estimate(c->est_tiles[q], w);
+        for (int w = 1; w <= 4; w <<= 1) {
+            long long t0 = 0, t1 = 0;
+            const long long g0 = hop_grid(c, static_cast<int>(q), c->est_tiles[q], w, &t0);
+            const long long g1 = hop_grid(c, static_cast<int>(q), seen, w, &t1);
+            changed = changed || g0 != g1 || t0 != t1;
+        }
         c->est_tiles[q] = seen;
     }
     if (changed) drop_graphs(c);
@@ -920,13 +957,18 @@ rt_status step_done(rt_ctx* c, long long H, long long launched) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     absorb_list_lengths(c, H);
     if (c->tuning_now) {
+        // forward steps whose list outgrew the main grid (the tail kernel ran
+        // part of them) are left out: their time says more about the grid
+        // estimate of a growing list than about the configuration
         for (long long q = 1; q <= H; ++q) {
-            c->tune_ms[q % kHopShapes] += elapsed(c, 3 + 2 * q);
-            c->tune_n[q % kHopShapes] += 1;
+            if (q < static_cast<long long>(c->cap_tiles.size()) && c->h_listlen[q] > c->cap_tiles[q]) continue;
+            const int k = tune_shape_of(c, static_cast<int>(q));
+            c->tune_ms[k] += elapsed(c, 3 + 2 * q);
+            c->tune_n[k] += 1;
         }
         if (--c->tune_steps_left <= 0) {
             int best = 0;
-            for (int k = 1; k < kHopShapes; ++k)
+            for (int k = 1; k < kTuneShapes; ++k)
                 if (c->tune_n[k] > 0 && c->tune_ms[k] / c->tune_n[k] < c->tune_ms[best] / std::max(1ll, c->tune_n[best]))
                     best = k;
             c->hop_shape = best;
@@ -1401,6 +1443,7 @@ rt_status init_impl(rt_ctx** out, const rt_params* p, const double* sigma_nu, co
     ITRY(alloc_n(c, &c->listlen, p->max_hops + 2ll));
     ITRY(fill_i32(c, c->listlen, p->max_hops + 2ll, 0));
     c->est_tiles.assign(p->max_hops + 2, 0);
+    c->cap_tiles.assign(p->max_hops + 2, 0);
     ITRY(alloc_n(c, &c->led, 5ll * n_inst * c->nf));
     ITRY(fill_f64(c, c->led, 5ll * n_inst * c->nf, 0.0));
     ITRY(alloc_n(c, &c->scale, 1ll * n_inst * c->nf));
@@ -1977,7 +2020,7 @@ rt_status rt_set_hop_shape(rt_ctx* c, int32_t shape) {
     } else {
         c->hop_shape = 0;
         c->tuned = false;
-        c->tune_steps_left = 3;
+        c->tune_steps_left = kTuneShapes;
         for (int k = 0; k < kHopShapes; ++k) {
             c->tune_ms[k] = 0.0;
             c->tune_n[k] = 0;

@@ -280,7 +280,9 @@ def test_hop_shapes_identical_and_tuner():
             if shape >= 0:
                 assert info["shape"] == shape and not info["tuned"]
             else:
-                assert info["tuned"] and 0 <= info["shape"] <= 5 and all(m > 0 for m in info["ms_per_launch"])
+                # the tuner times the unpacked shapes 0..2 only
+                assert info["tuned"] and 0 <= info["shape"] <= 2
+                assert all(m > 0 for m in info["ms_per_launch"][:3]) and not any(info["ms_per_launch"][3:])
         for b in blobs[1:]:
             assert all(np.array_equal(x, y) for x, y in zip(b, blobs[0])), prec
     with pytest.raises(RT.RTError):
