@@ -1161,6 +1161,7 @@ struct HopArgs {
     long long N;
     int G, nrc, nf, K, rr_bin, rr_on, T, lgT;
     int hop, hop0, max_hops;
+    int list0;               // hop 0 runs the tiles of its list (k_mark_hop0), not every tile
     const double* pos;
     const int* rev_off;
     const unsigned int* rev_ik;   // receiver-sorted edges: sender << 6 | position in the sender's list
@@ -1195,8 +1196,9 @@ struct HopArgs {
     const R2<R>* mvc_rd;
     const Inbox<DT>* in_rd;
     const int* hot_rd;
-    const int4* tlist;       // tiles marked for this forward step (k_tile_list), hop > 0: {tile,
-                             // first and end receiver-sorted edge of its particles, 0}
+    const int4* tlist;       // tiles marked for this forward step (k_tile_list), hop > 0 or
+                             // list0: {tile, first and end receiver-sorted edge of its particles, 0}
+    int* rest;               // per tile: 1 if a slot held photons after the tile last ran
     long long ntiles;
     int lg_wpb;              // log2 of the wavefronts (tiles) per workgroup: 0, 1 or 2
     unsigned int lds_wave;   // LDS bytes of each wavefront
@@ -2175,6 +2177,10 @@ __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long lon
     // whether a packet moves next step (a flag, no count: plain stores), and
     // the tile's running tallies of packets moved, bytes and steps run
     if (tile_act && lane == 0) a.cnt[kCntAct0 + kCntLine * a.act_wr] = 1;
+    // whether photons stay in this tile's bins: the next RT step's first
+    // forward step runs it then (it also runs the tiles with records or RR)
+    const bool resting = __ballot(valid && nn > R(0)) != 0ull;
+    if (lane == 0) a.rest[tile] = resting ? 1 : 0;
     const unsigned long long nupd = __popcll(__ballot(departed));
     const unsigned long long wb = f32 ? wave_sum_u64_fast(nbytes) : wave_sum_u64(nbytes);
     if (lane < 3) a.part[3 * tile + lane] = tally + (lane == 0 ? nupd : (lane == 1 ? wb : 1ull));
@@ -2223,13 +2229,14 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
             a.cnt[kCntDeep] = 0;  // and its virtual particles all handled
             // the next forward step's list count starts from zero
             a.cnt[kCntTileList + ((a.hop + 1) & 1)] = 0;
-            if (!a.hop0) a.listlen[a.hop] = static_cast<int>(c_list);
+            if (!a.hop0 || a.list0) a.listlen[a.hop] = static_cast<int>(c_list);
         }
     }
     // 32-bit arithmetic and shifts only: every workgroup, also the surplus
     // ones, runs this before it exits.  The grid may be smaller than the list
     // (sized from earlier steps): k_hop_tail takes the tiles past its end.
-    const unsigned int n = static_cast<unsigned int>(a.hop0 ? a.ntiles : (c_list < a.ntiles ? c_list : a.ntiles));
+    const bool every = a.hop0 && !a.list0;  // hop 0 without a list runs every tile
+    const unsigned int n = static_cast<unsigned int>(every ? a.ntiles : (c_list < a.ntiles ? c_list : a.ntiles));
     const unsigned int nb0 = (n + (1u << a.lg_wpb) - 1u) >> a.lg_wpb;  // workgroups' worth of tiles
     const unsigned int nb = nb0 < gridDim.x ? nb0 : gridDim.x;          // of them in this grid
     if (idle | capped | (blockIdx.x >= nb)) return;
@@ -2237,7 +2244,7 @@ __global__ __launch_bounds__(256) void k_hop(HopArgs<R, DT> a) {
     const unsigned int e = (xcd_block32(blockIdx.x, nb) << a.lg_wpb) + wv;
     if (e >= n) return;
     long long tile, e_t0, e_t1;
-    if (a.hop0) {
+    if (every) {
         tile = e;
         const long long tj0 = tile * a.T;
         const long long tj1 = (tj0 + a.T < a.N) ? tj0 + a.T : a.N;
@@ -2264,7 +2271,7 @@ __global__ __launch_bounds__(256) void k_hop_tail(HopArgs<R, DT> a, unsigned int
     const long long c_serial = a.cnt[kCntSerial];
     const long long c_list = a.cnt[kCntTileList + (a.hop & 1)];
     const int stamp = static_cast<int>(c_serial) + a.hop;
-    const bool idle = (c_done != 0) | (c_act == 0);
+    const bool idle = (c_done != 0) | ((a.hop0 == 0) & (c_act == 0));
     const unsigned int n = static_cast<unsigned int>(c_list < a.ntiles ? c_list : a.ntiles);
     if (idle | (a.hop > a.max_hops) | (n <= covered)) return;
     const unsigned int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -2277,6 +2284,26 @@ __global__ __launch_bounds__(256) void k_hop_tail(HopArgs<R, DT> a, unsigned int
     }
 }
 
+// The marks of an RT step's first forward step (act_rd < 0 in k_tile_list then
+// lists them): a tile runs if photons rest in its bins (flag left by its last
+// run), or one of its particles has records to consume (emission, virtual
+// particles) or recombination photons to emit (rr_on).  Every other tile's
+// first forward step would rewrite what it holds.  One thread per tile; the
+// whole mark array is rewritten, so no older mark can match.
+__global__ __launch_bounds__(256) void k_mark_hop0(const int* __restrict__ rest, const int* __restrict__ head,
+                                                   const double* __restrict__ nrr, int rr_on, long long N, int T,
+                                                   long long ntiles, int* __restrict__ hot, const long long* cnt,
+                                                   int halt_on) {
+    if ((halt_on && cnt[kCntHalt] != 0) || cnt[kCntDone] != 0) return;
+    const int stamp = static_cast<int>(cnt[kCntSerial]);
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < ntiles; t += (long long)gridDim.x * blockDim.x) {
+        bool w = rest[t] != 0;
+        const long long j0 = t * T, j1 = (j0 + T < N) ? j0 + T : N;
+        for (long long j = j0; j < j1; ++j) w = w || head[j] >= 0 || (rr_on && nrr[j] > 0.0);
+        hot[t] = w ? stamp : -1;
+    }
+}
+
 // The tiles marked for forward step `hop` (tile mark == its stamp), listed with
 // their edge ranges for the forward-step kernel: each workgroup takes 4096 marks (16 consecutive per
 // thread, read as four 16-byte vectors), a workgroup prefix sum orders its
@@ -2286,7 +2313,8 @@ __global__ __launch_bounds__(256) void k_hop_tail(HopArgs<R, DT> a, unsigned int
 __global__ __launch_bounds__(256) void k_tile_list(const int* __restrict__ hot, long long ntiles, int hop, int act_rd,
                                                    const int* __restrict__ rev_off, long long N, int T,
                                                    int4* __restrict__ tlist, long long* cnt, int halt_on) {
-    if ((halt_on && cnt[kCntHalt] != 0) || cnt[kCntDone] != 0 || cnt[kCntAct0 + kCntLine * act_rd] == 0) return;
+    if ((halt_on && cnt[kCntHalt] != 0) || cnt[kCntDone] != 0 || (act_rd >= 0 && cnt[kCntAct0 + kCntLine * act_rd] == 0))
+        return;
     const int stamp = static_cast<int>(cnt[kCntSerial]) + hop;
     const long long t0 = blockIdx.x * kTileListChunk + threadIdx.x * 16ll;
     const int4* h4 = reinterpret_cast<const int4*>(hot + t0);  // the mark array is padded to whole chunks

@@ -121,6 +121,8 @@ struct rt_ctx {
     void* mvc[2] = {nullptr, nullptr};
     void* inbox[2] = {nullptr, nullptr};
     int* hot[2] = {nullptr, nullptr};
+    int* rest = nullptr;    // per tile: photons rest in its bins (left by its last run)
+    bool list0 = true;      // hop 0 runs a list of tiles (not with the predecessor RR scheme)
     int4* tlist = nullptr;  // tiles marked for the next forward step, with their edge ranges
     long long hot_len = 0; // entries of each mark array: ntiles padded to whole k_tile_list chunks
     unsigned long long* part = nullptr;  // per-tile tallies of a forward step
@@ -339,7 +341,7 @@ long long grid_estimate(long long tiles, int wpb) {
 long long hop_grid(const rt_ctx* c, int hop, long long est, int wpb, long long* n_tail) {
     const long long n_full = (c->ntiles + wpb - 1) / wpb;
     *n_tail = 0;
-    if (hop == 0) return n_full;
+    if (hop == 0 && !c->list0) return n_full;
     const long long n_wg = std::min(n_full, est > 0 ? grid_estimate(est, wpb) : kHopUnseenWGs);
     if (n_full - n_wg < kHopMinSavedWGs) return n_full;
     const long long t = est > 0 ? std::min(kHopTailMaxWGs, std::max(kHopTailMinWGs, n_wg / 64)) : kHopUnseenTailWGs;
@@ -361,6 +363,8 @@ rt_status launch_hop(rt_ctx* c, int hop, bool pack) {
     a.rr_pre = c->rr_orig ? c->rr_pre : nullptr;
     a.hop = hop;
     a.hop0 = hop == 0;
+    a.list0 = (hop == 0 && c->list0) ? 1 : 0;
+    a.rest = c->rest;
     a.max_hops = c->p.max_hops;
     a.pos = c->pos;
     a.rev_off = c->rev_off;
@@ -523,11 +527,18 @@ rt_status launch_vip(rt_ctx* c, int hop) {
     hipLaunchKernelGGL(k_vip_chain, dim3(1024), dim3(256), 0, c->stream, a);
     HIPCHK(c, hipGetLastError());
     // the tiles marked for this forward step (by the previous one and by the
-    // virtual-particle chains just launched); hop 0 runs every tile
-    if (hop > 0) {
+    // virtual-particle chains just launched); hop 0's marks come from
+    // k_mark_hop0 (with the predecessor RR scheme hop 0 runs every tile)
+    if (hop == 0 && c->list0) {
+        hipLaunchKernelGGL(k_mark_hop0, dim3(std::min<unsigned>(grid_for(c->ntiles, 256), 4096)), dim3(256), 0, c->stream,
+                           c->rest, c->head[0], c->nrr[c->nrr_cur], c->rr_on ? 1 : 0, c->N, c->tileT, c->ntiles, c->hot[0],
+                           c->cnt, c->capturing ? 1 : 0);
+        HIPCHK(c, hipGetLastError());
+    }
+    if (hop > 0 || c->list0) {
         hipLaunchKernelGGL(k_tile_list, dim3(static_cast<unsigned>(c->hot_len / kTileListChunk)), dim3(256), 0, c->stream,
-                           c->hot[hop & 1], c->ntiles, hop, hop & 1, c->rev_off, c->N, c->tileT, c->tlist, c->cnt,
-                           c->capturing ? 1 : 0);
+                           c->hot[hop & 1], c->ntiles, hop, hop > 0 ? (hop & 1) : -1, c->rev_off, c->N, c->tileT, c->tlist,
+                           c->cnt, c->capturing ? 1 : 0);
         HIPCHK(c, hipGetLastError());
     }
     return RT_OK;
@@ -930,7 +941,7 @@ rt_status step_tail(rt_ctx* c, long long launched, bool graph) {
 void absorb_list_lengths(rt_ctx* c, long long H) {
     bool changed = false;
     const long long top = std::min<long long>(H, static_cast<long long>(c->est_tiles.size()) - 1);
-    for (long long q = 1; q <= top; ++q) {
+    for (long long q = c->list0 ? 0 : 1; q <= top; ++q) {
         const long long seen = c->h_listlen[q];
         if (seen <= c->est_tiles[q]) continue;
         for (int w = 1; w <= 4; w <<= 1) {
@@ -1231,6 +1242,9 @@ rt_status init_impl(rt_ctx** out, const rt_params* p, const double* sigma_nu, co
     }
     c->rr_on = p->recomb_mode == RT_RR_TRANSPORT || p->recomb_mode == RT_RR_ORIGINAL;
     c->rr_orig = p->recomb_mode == RT_RR_ORIGINAL;
+    // the predecessor scheme's arrivals are summed per slot for hop 0, which
+    // then runs every tile
+    c->list0 = !c->rr_orig;
     const double cc = 1.0 - 2.0 / static_cast<double>(p->n_tc);
     c->c2 = cc * cc;
     c->inst_off.assign(inst_off, inst_off + n_inst + 1);
@@ -1398,6 +1412,10 @@ rt_status init_impl(rt_ctx** out, const rt_params* p, const double* sigma_nu, co
             ITRY(alloc_n(c, &c->part, 3 * c->ntiles));
             ITRY(alloc_n(c, &c->tlist, c->ntiles));
             HIPCHK(c, hipMemsetAsync(c->part, 0, sizeof(unsigned long long) * 3 * c->ntiles, c->stream));
+            // until a tile has run, whether photons rest in it is not known:
+            // every tile runs at the first hop 0
+            ITRY(alloc_n(c, &c->rest, c->ntiles));
+            ITRY(fill_i32(c, c->rest, c->ntiles, 1));
         }
         ITRY(alloc_n(c, &c->nrr[b], N));
         ITRY(fill_f64(c, c->nrr[b], N, 0.0));
@@ -2124,6 +2142,7 @@ rt_status rt_set_state_blob(rt_ctx* c, const void* blob, size_t bytes) {
         HIPCHK(c, hipMemsetAsync(c->inbox[b], 0xff, c->inbox_bytes, c->stream));
         TRY(fill_i32(c, c->hot[b], c->hot_len, -1));
     }
+    TRY(fill_i32(c, c->rest, c->ntiles, 1));  // the restored bins: every tile runs at the next hop 0
     if (c->f32) {
         hipLaunchKernelGGL(k_kappa_init, dim3(grid_for(c->N, 256)), dim3(256), 0, c->stream, c->N, c->xHI, c->nH,
                            c->L_d, c->inst_of, c->kappa);
