@@ -451,20 +451,23 @@ __device__ inline unsigned long long emis_key(long long m, int sub, int nu, int 
            (static_cast<unsigned long long>(arr) << 7) | static_cast<unsigned long long>(kidx);
 }
 
-// Emission (section 2.1): thread per (emitter, sub-step, neighbour).  Point
-// sources: each neighbour belongs to the Voronoi emission cone of the nearest
-// rotated direction; a packet is split equally among its cone's members.
-// Plane fronts: one packet along +x into the transmission cone.
+// Emission (section 2.1): a wavefront per (emitter, sub-step), a lane per
+// neighbour (n_ngb <= 64) and per emission cone (n_ec <= 64).  Point sources:
+// each neighbour belongs to the Voronoi emission cone of the nearest rotated
+// direction; a packet is split equally among its cone's members, counted
+// from the lanes' cones (each lane computes its own neighbour's once).  Plane
+// fronts: one packet along +x into the transmission cone.
 __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
     if (a.halt_on && a.cnt[kCntHalt] != 0) return;
-    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (t >= a.n_emit * a.nsub * a.K) return;
-    const int mem = static_cast<int>(t % a.K);
-    const long long ms = t / a.K;
+    const int lane = threadIdx.x & 63;
+    const long long ms = blockIdx.x * 4ll + (threadIdx.x >> 6);  // uniform per wavefront
+    if (ms >= a.n_emit * a.nsub) return;
     const int sub = static_cast<int>(ms % a.nsub);
     const long long m = ms / a.nsub;
     const int kind = a.em_kind[m];
     if (kind != 0 && sub > 0) return;
+    const bool in = lane < a.K;
+    const int mem = in ? lane : 0;  // lanes past n_ngb repeat neighbour 0 and are no member
     const double ex = a.em_pos[3 * m], ey = a.em_pos[3 * m + 1], ez = a.em_pos[3 * m + 2];
     const int* nb = a.em_ngb + m * a.K;
     const double* E = a.ecd + 3 * (ms * a.nec);
@@ -475,29 +478,28 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
     bool member;
     if (kind == 0) {
         cone = nearest_direction(E, a.nec, vx, vy, vz);
-        for (int u = 0; u < a.K; ++u) {
-            const int ju = nb[u];
-            const double ux = a.pos[3 * (long long)ju] - ex, uy = a.pos[3 * (long long)ju + 1] - ey, uz = a.pos[3 * (long long)ju + 2] - ez;
-            ncone += nearest_direction(E, a.nec, ux, uy, uz) == cone;
-        }
+        for (int u = 0; u < a.K; ++u) ncone += __builtin_amdgcn_readlane(cone, u) == cone;
         dx = E[3 * cone];
         dy = E[3 * cone + 1];
         dz = E[3 * cone + 2];
-        member = true;
+        member = in;
     } else {
-        member = in_cone(vx, vy, vz, dx, dy, dz, a.c2);
-        for (int u = 0; u < a.K; ++u) {
-            const int ju = nb[u];
-            const double ux = a.pos[3 * (long long)ju] - ex, uy = a.pos[3 * (long long)ju + 1] - ey, uz = a.pos[3 * (long long)ju + 2] - ez;
-            ncone += in_cone(ux, uy, uz, dx, dy, dz, a.c2);
-        }
+        member = in && in_cone(vx, vy, vz, dx, dy, dz, a.c2);
+        ncone = __popcll(__ballot(member));
+    }
+    // members of emission cone `lane` (point sources) or of the one cone (plane fronts)
+    int cntk = 0;
+    if (kind == 0) {
+        for (int u = 0; u < a.K; ++u) cntk += __builtin_amdgcn_readlane(cone, u) == lane;
+    } else {
+        cntk = ncone;
     }
     const int r = nearest_direction(a.wrc, a.nrc, dx, dy, dz);
     for (int nu = 0; nu < a.nf; ++nu) {
         const double pk = a.em_pk[m * a.nf + nu];
         if (!(pk > 0.0)) continue;
-        if (mem == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&a.cnt[kCntUpdates]),
-                                static_cast<unsigned long long>(kind == 0 ? a.nec : 1));
+        if (lane == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&a.cnt[kCntUpdates]),
+                                 static_cast<unsigned long long>(kind == 0 ? a.nec : 1));
         const double xj[3] = {a.pos[3 * (long long)j], a.pos[3 * (long long)j + 1], a.pos[3 * (long long)j + 2]};
         const double xe[3] = {ex, ey, ez};
         if (member && barrier_blocks(a.bar, a.em_inst[m], xe, xj)) {
@@ -528,24 +530,16 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
                 fx_add3(a.xr_fx + 3 * ((static_cast<long long>(a.em_inst[m]) * a.nf + nu) * 2 + 1), nin / a.Ufx[a.em_inst[m]],
                         a.cnt);
         }
-        // Empty cones become virtual particles (thread mem handles cones mem, mem + K, ...).
+        // Empty cones become virtual particles (lane kk handles cone kk).
         const int nk = kind == 0 ? a.nec : 1;
-        for (int kk = mem; kk < nk; kk += a.K) {
-            int cntk = 0;
+        if (lane < nk && cntk == 0) {
+            const int kk = lane;
             double kx = 1.0, ky = 0.0, kz = 0.0;
             if (kind == 0) {
-                for (int u = 0; u < a.K; ++u) {
-                    const int ju = nb[u];
-                    const double ux = a.pos[3 * (long long)ju] - ex, uy = a.pos[3 * (long long)ju + 1] - ey, uz = a.pos[3 * (long long)ju + 2] - ez;
-                    cntk += nearest_direction(E, a.nec, ux, uy, uz) == kk;
-                }
                 kx = E[3 * kk];
                 ky = E[3 * kk + 1];
                 kz = E[3 * kk + 2];
-            } else {
-                cntk = ncone;
             }
-            if (cntk != 0) continue;
             const long long v = push_vip(a.vip, a.cnt, 0, a.vip_cap);
             if (v < 0) {  // no room: the empty cone's packet leaves the transport as removed
                 fx_add3(a.xr_fx + 3 * ((static_cast<long long>(a.em_inst[m]) * a.nf + nu) * 2 + 1), pk / a.Ufx[a.em_inst[m]],

@@ -791,7 +791,8 @@ rt_status step_front(rt_ctx* c, bool set_serial) {
         ea.xr_fx = c->xr_fx;
         ea.Ufx = c->Ufx;
         ea.bar = c->any_bar ? c->bar_d : nullptr;
-        hipLaunchKernelGGL(k_emit, dim3(grid_for(c->n_emit * c->nsub * c->K, 256)), dim3(256), 0, c->stream, ea);
+        // a wavefront per (emitter, sub-step), four per workgroup
+        hipLaunchKernelGGL(k_emit, dim3(grid_for(c->n_emit * c->nsub, 4)), dim3(256), 0, c->stream, ea);
         HIPCHK(c, hipGetLastError());
     }
     if (c->rr_orig) TRY(launch_rr_original(c));
