@@ -744,6 +744,57 @@ __global__ __launch_bounds__(64) void k_rr_recv(RrArgs a) {
     }
 }
 
+// One workgroup (256 threads) lists the marked tiles of mark chunk `chunk`
+// (kTileListChunk marks, 16 consecutive per thread, read as four 16-byte
+// vectors): a workgroup prefix sum orders them and one atomic on *count
+// places them.  Every thread of the workgroup must call it.
+__device__ __forceinline__ void list_marked_chunk(const int* __restrict__ hot, long long ntiles, int stamp, long long chunk,
+                                                  const int* __restrict__ rev_off, long long N, int T,
+                                                  int4* __restrict__ tlist, long long* count) {
+    const long long t0 = chunk * kTileListChunk + threadIdx.x * 16ll;
+    const int4* h4 = reinterpret_cast<const int4*>(hot + t0);  // the mark array is padded to whole chunks
+    unsigned int bits = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int4 v = h4[q];
+        bits |= (v.x == stamp ? 1u : 0u) << (4 * q);
+        bits |= (v.y == stamp ? 1u : 0u) << (4 * q + 1);
+        bits |= (v.z == stamp ? 1u : 0u) << (4 * q + 2);
+        bits |= (v.w == stamp ? 1u : 0u) << (4 * q + 3);
+    }
+    if (t0 + 16 > ntiles) bits &= t0 >= ntiles ? 0u : ((1u << (ntiles - t0)) - 1u);
+    const int mine = __popc(bits);
+    // exclusive prefix over the workgroup, in thread (= tile) order
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int incl = mine;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += v;
+    }
+    __shared__ int wtot[4];
+    __shared__ long long base;
+    if (lane == 63) wtot[wv] = incl;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int w = 0; w < 4; ++w) {
+        before += w < wv ? wtot[w] : 0;
+        total += wtot[w];
+    }
+    if (threadIdx.x == 0)
+        base = total ? static_cast<long long>(atomicAdd(reinterpret_cast<unsigned long long*>(count),
+                                                        static_cast<unsigned long long>(total)))
+                     : 0ll;
+    __syncthreads();
+    long long at = base + before + incl - mine;
+    __syncthreads();  // wtot and base are free for the workgroup's next chunk
+    while (bits) {
+        const int b = __builtin_ctz(bits);
+        bits &= bits - 1u;
+        const long long t = t0 + b, j0 = t * T, j1 = (j0 + T < N) ? j0 + T : N;
+        tlist[at++] = make_int4(static_cast<int>(t), rev_off[j0], rev_off[j1], 0);
+    }
+}
+
 struct VipArgs {
     int halt_on;  // steps replayed from a graph: exit at once while the halt word is set
     const double* rr_ecd;  // direction sets of the predecessor RR scheme (virtual particles with ec <= -2)
@@ -777,6 +828,13 @@ struct VipArgs {
     long long rec_cap;
     int* hot;        // tiles that receive records in this forward step
     int lgT;
+    // hop > 0: k_vip_sample lists the tiles the previous forward step marked,
+    // and k_vip_chain appends those it marks first (no separate list launch)
+    int list_here;
+    int4* tlist;
+    const int* rev_off;
+    long long N, ntiles, nchunks;
+    int T;
     Vip* deep;       // virtual particles that landed inside their box, with their points
     double* deep_x;
     long long* cnt;
@@ -863,6 +921,13 @@ __global__ __launch_bounds__(256) void k_vip_sample(VipArgs a) {
             if (gid == 0) a.cnt[kCntDone] = 1;
             return;
         }
+    }
+    if (a.list_here) {
+        // the tiles the previous forward step marked for this one, a chunk of
+        // marks per workgroup in turn (every thread of the workgroup takes part)
+        const int stamp = static_cast<int>(a.cnt[kCntSerial]) + a.hop;
+        for (long long ch = blockIdx.x; ch < a.nchunks; ch += gridDim.x)
+            list_marked_chunk(a.hot, a.ntiles, stamp, ch, a.rev_off, a.N, a.T, a.tlist, &a.cnt[kCntTileList + (a.hop & 1)]);
     }
     long long n = a.cnt[kCntVipCnt0 + a.list_rd];
     if (n > a.vip_cap) n = a.vip_cap;
@@ -1104,7 +1169,16 @@ __global__ __launch_bounds__(256) void k_vip_chain(VipArgs a) {
                     rc.j = static_cast<int>(jk);
                     rc.o = q.nu * a.nrc + r;
                     push_record(a.rec, a.rec_next, a.head, idx1 + w8, rc);
-                    a.hot[jk >> a.lgT] = stamp;
+                    const long long tm = jk >> a.lgT;
+                    if (!a.list_here) {
+                        a.hot[tm] = stamp;
+                    } else if (atomicExch(&a.hot[tm], stamp) != stamp) {
+                        // the tile's first mark for this forward step: list it
+                        const long long at = static_cast<long long>(atomicAdd(
+                            reinterpret_cast<unsigned long long*>(&a.cnt[kCntTileList + (a.hop & 1)]), 1ull));
+                        const long long j0 = tm * a.T, j1 = (j0 + a.T < a.N) ? j0 + a.T : a.N;
+                        a.tlist[at] = make_int4(static_cast<int>(tm), a.rev_off[j0], a.rev_off[j1], 0);
+                    }
                 }
                 break;
             }
@@ -2278,6 +2352,7 @@ __global__ __launch_bounds__(256) void k_hop_tail(HopArgs<R, DT> a, unsigned int
     }
 }
 
+
 // The marks of an RT step's first forward step (act_rd < 0 in k_tile_list then
 // lists them): a tile runs if photons rest in its bins (flag left by its last
 // run), or one of its particles has records to consume (emission, virtual
@@ -2309,48 +2384,8 @@ __global__ __launch_bounds__(256) void k_tile_list(const int* __restrict__ hot, 
                                                    int4* __restrict__ tlist, long long* cnt, int halt_on) {
     if ((halt_on && cnt[kCntHalt] != 0) || cnt[kCntDone] != 0 || (act_rd >= 0 && cnt[kCntAct0 + kCntLine * act_rd] == 0))
         return;
-    const int stamp = static_cast<int>(cnt[kCntSerial]) + hop;
-    const long long t0 = blockIdx.x * kTileListChunk + threadIdx.x * 16ll;
-    const int4* h4 = reinterpret_cast<const int4*>(hot + t0);  // the mark array is padded to whole chunks
-    unsigned int bits = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int4 v = h4[q];
-        bits |= (v.x == stamp ? 1u : 0u) << (4 * q);
-        bits |= (v.y == stamp ? 1u : 0u) << (4 * q + 1);
-        bits |= (v.z == stamp ? 1u : 0u) << (4 * q + 2);
-        bits |= (v.w == stamp ? 1u : 0u) << (4 * q + 3);
-    }
-    if (t0 + 16 > ntiles) bits &= t0 >= ntiles ? 0u : ((1u << (ntiles - t0)) - 1u);
-    const int mine = __popc(bits);
-    // exclusive prefix over the workgroup, in thread (= tile) order
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int incl = mine;
-    for (int off = 1; off < 64; off <<= 1) {
-        const int v = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += v;
-    }
-    __shared__ int wtot[4];
-    __shared__ long long base;
-    if (lane == 63) wtot[wv] = incl;
-    __syncthreads();
-    int before = 0, total = 0;
-    for (int w = 0; w < 4; ++w) {
-        before += w < wv ? wtot[w] : 0;
-        total += wtot[w];
-    }
-    if (threadIdx.x == 0)
-        base = total ? static_cast<long long>(atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[kCntTileList + (hop & 1)]),
-                                                        static_cast<unsigned long long>(total)))
-                     : 0ll;
-    __syncthreads();
-    long long at = base + before + incl - mine;
-    while (bits) {
-        const int b = __builtin_ctz(bits);
-        bits &= bits - 1u;
-        const long long t = t0 + b, j0 = t * T, j1 = (j0 + T < N) ? j0 + T : N;
-        tlist[at++] = make_int4(static_cast<int>(t), rev_off[j0], rev_off[j1], 0);
-    }
+    list_marked_chunk(hot, ntiles, static_cast<int>(cnt[kCntSerial]) + hop, blockIdx.x, rev_off, N, T, tlist,
+                      &cnt[kCntTileList + (hop & 1)]);
 }
 
 // Adds the tiles' running tallies of an RT step to the counters and clears them.

@@ -514,6 +514,13 @@ rt_status launch_vip(rt_ctx* c, int hop) {
     a.rec_cap = c->rec_cap;
     a.hot = c->hot[hop & 1];
     a.lgT = c->lgT;
+    a.list_here = hop > 0 ? 1 : 0;
+    a.tlist = c->tlist;
+    a.rev_off = c->rev_off;
+    a.N = c->N;
+    a.ntiles = c->ntiles;
+    a.nchunks = c->hot_len / kTileListChunk;
+    a.T = c->tileT;
     a.deep = c->deep;
     a.deep_x = c->deep_x;
     a.cnt = c->cnt;
@@ -526,19 +533,17 @@ rt_status launch_vip(rt_ctx* c, int hop) {
     hipLaunchKernelGGL(k_vip_sample, dim3(nsb), dim3(256), 0, c->stream, a);
     hipLaunchKernelGGL(k_vip_chain, dim3(1024), dim3(256), 0, c->stream, a);
     HIPCHK(c, hipGetLastError());
-    // the tiles marked for this forward step (by the previous one and by the
-    // virtual-particle chains just launched); hop 0's marks come from
-    // k_mark_hop0 (with the predecessor RR scheme hop 0 runs every tile)
+    // the tiles marked for this forward step: after hop 0, k_vip_sample lists
+    // those the previous forward step marked and k_vip_chain appends its own;
+    // hop 0's marks come from k_mark_hop0 and k_tile_list lists them (with the
+    // predecessor RR scheme hop 0 runs every tile)
     if (hop == 0 && c->list0) {
         hipLaunchKernelGGL(k_mark_hop0, dim3(std::min<unsigned>(grid_for(c->ntiles, 256), 4096)), dim3(256), 0, c->stream,
                            c->rest, c->head[0], c->nrr[c->nrr_cur], c->rr_on ? 1 : 0, c->N, c->tileT, c->ntiles, c->hot[0],
                            c->cnt, c->capturing ? 1 : 0);
         HIPCHK(c, hipGetLastError());
-    }
-    if (hop > 0 || c->list0) {
         hipLaunchKernelGGL(k_tile_list, dim3(static_cast<unsigned>(c->hot_len / kTileListChunk)), dim3(256), 0, c->stream,
-                           c->hot[hop & 1], c->ntiles, hop, hop > 0 ? (hop & 1) : -1, c->rev_off, c->N, c->tileT, c->tlist,
-                           c->cnt, c->capturing ? 1 : 0);
+                           c->hot[0], c->ntiles, 0, -1, c->rev_off, c->N, c->tileT, c->tlist, c->cnt, c->capturing ? 1 : 0);
         HIPCHK(c, hipGetLastError());
     }
     return RT_OK;
