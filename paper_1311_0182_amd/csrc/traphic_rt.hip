@@ -331,11 +331,11 @@ long long grid_estimate(long long tiles, int wpb) {
 // The grids of forward step `hop` (> 0: hop 0 runs every tile) with `wpb`
 // tiles per workgroup, for a forward step whose list has had up to `est`
 // tiles (0: not seen yet): k_hop's workgroups, returned, and k_hop_tail's in
-// *n_tail (0: no tail).  The tail's grid is a 64th of the main one, at least
-// kHopTailMinWGs (a list that outgrows its estimate, as the lists of a front
-// advancing step by step do, then still fills the chip, while a tail with
-// nothing to do dispatches few workgroups), kHopUnseenTailWGs for a forward
-// step not seen yet.  A smaller grid pays only when it saves more workgroups
+// *n_tail (0: no tail).  The tail's grid is a 64th of the main one and at
+// least a 256th of the full grid and kHopTailMinWGs (a list that outgrows its
+// estimate, as the lists of a front advancing step by step do, then still
+// fills the chip, while a tail with nothing to do dispatches few workgroups),
+// kHopUnseenTailWGs for a forward step not seen yet.  A smaller grid pays only when it saves more workgroups
 // than the tail's launch costs (an idle workgroup costs well under a
 // nanosecond here, a launch a few microseconds): else the full grid, no tail.
 long long hop_grid(const rt_ctx* c, int hop, long long est, int wpb, long long* n_tail) {
@@ -344,7 +344,8 @@ long long hop_grid(const rt_ctx* c, int hop, long long est, int wpb, long long* 
     if (hop == 0 && !c->list0) return n_full;
     const long long n_wg = std::min(n_full, est > 0 ? grid_estimate(est, wpb) : kHopUnseenWGs);
     if (n_full - n_wg < kHopMinSavedWGs) return n_full;
-    const long long t = est > 0 ? std::min(kHopTailMaxWGs, std::max(kHopTailMinWGs, n_wg / 64)) : kHopUnseenTailWGs;
+    const long long t = est > 0 ? std::min(kHopTailMaxWGs, std::max(std::max(kHopTailMinWGs, n_full / 256), n_wg / 64))
+                                : kHopUnseenTailWGs;
     *n_tail = std::min(n_full - n_wg, t);
     return n_wg;
 }
