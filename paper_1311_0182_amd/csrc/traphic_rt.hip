@@ -122,6 +122,7 @@ struct rt_ctx {
     void* inbox[2] = {nullptr, nullptr};
     int* hot[2] = {nullptr, nullptr};
     int* rest = nullptr;    // per tile: photons rest in its bins (left by its last run)
+    bool rest_unknown = true;  // rest is all ones (set up or restored): hop 0's next list is every tile
     bool list0 = true;      // hop 0 runs a list of tiles (not with the predecessor RR scheme)
     int4* tlist = nullptr;  // tiles marked for the next forward step, with their edge ranges
     long long hot_len = 0; // entries of each mark array: ntiles padded to whole k_tile_list chunks
@@ -948,7 +949,11 @@ rt_status step_tail(rt_ctx* c, long long launched, bool graph) {
 void absorb_list_lengths(rt_ctx* c, long long H) {
     bool changed = false;
     const long long top = std::min<long long>(H, static_cast<long long>(c->est_tiles.size()) - 1);
-    for (long long q = c->list0 ? 0 : 1; q <= top; ++q) {
+    // a hop 0 that listed every tile (rest flags not known yet) says nothing
+    // about the lists to come
+    const long long q0 = (c->list0 && !c->rest_unknown) ? 0 : 1;
+    c->rest_unknown = false;
+    for (long long q = q0; q <= top; ++q) {
         const long long seen = c->h_listlen[q];
         if (seen <= c->est_tiles[q]) continue;
         for (int w = 1; w <= 4; w <<= 1) {
@@ -2150,6 +2155,7 @@ rt_status rt_set_state_blob(rt_ctx* c, const void* blob, size_t bytes) {
         TRY(fill_i32(c, c->hot[b], c->hot_len, -1));
     }
     TRY(fill_i32(c, c->rest, c->ntiles, 1));  // the restored bins: every tile runs at the next hop 0
+    c->rest_unknown = true;
     if (c->f32) {
         hipLaunchKernelGGL(k_kappa_init, dim3(grid_for(c->N, 256)), dim3(256), 0, c->stream, c->N, c->xHI, c->nH,
                            c->L_d, c->inst_of, c->kappa);
