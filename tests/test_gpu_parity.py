@@ -154,6 +154,53 @@ def test_late_steps_against_oracle():
     g32.close()
 
 
+def test_packets_resting_between_steps():
+    # c dt of about three particle spacings in thin gas: at the end of every RT
+    # step packets stop on their clocks and rest in their bins (41% of the
+    # slots after 30 steps), and the next step's first forward step, which runs
+    # only the tiles with resting photons, records or recombination photons to
+    # emit, must pick them up.  In the first steps the light covers only the
+    # tiles near the source, so tiles are both listed and left out.  FP64
+    # against the oracle (counters exact), FP32 within the bar, and a restored
+    # checkpoint (whether photons rest in a tile is not known then, so its
+    # first forward step runs every tile) continuing bit for bit.
+    cfg = I.stromgren(12, rr=True, n_ngb=32, dt_myr=0.005, n_h=1e-5)
+    steps = 30
+    say("12^3, c dt ~ 3 spacings, 30 steps")
+    s, _ = run_oracle(cfg, steps)
+    so = s.state()
+    Nb_o, _, _ = s.bins()
+    assert (Nb_o > 0).sum() > 5000
+    g64 = run_gpu(cfg, steps, "fp64")
+    sg = g64.state()
+    say("counters oracle", so["counters"], "gpu", sg["counters"])
+    assert np.array_equal(so["counters"], sg["counters"])
+    assert rel(sg["xHI"], so["xHI"]) < 1e-6
+    assert np.max(residual(sg["ledger"])) < 1e-12
+    Nb_g, _, _ = g64.bins()
+    assert np.array_equal(Nb_o > 0, Nb_g > 0)
+    assert rel(Nb_g[Nb_o > 0], Nb_o[Nb_o > 0]) < 1e-9
+    g64.close()
+    g32 = run_gpu(cfg, steps, "fp32")
+    dx = np.max(np.abs(g32.state()["xHI"] - so["xHI"]))
+    say("fp32 max |dx_HI|", dx)
+    assert dx <= 1e-3
+    g32.close()
+    for prec in ("fp64", "fp32"):
+        ref = run_gpu(cfg, 12, prec)
+        a = run_gpu(cfg, 6, prec)
+        b = _rt().Context(cfg, precision=prec)
+        b.set_blob(a.get_blob())
+        b.step(6)
+        sr, sb = ref.state(), b.state()
+        for key in ("xHI", "T", "A", "P", "ledger", "counters"):
+            assert np.array_equal(sr[key], sb[key]), (prec, key)
+        for x, y in zip(ref.bins(), b.bins()):
+            assert np.array_equal(x, y), prec
+        for c in (ref, a, b):
+            c.close()
+
+
 def test_fp64_parity_batched():
     cfg = I.batched(n_inst=6, side_lo=6, side_hi=12, n_ngb=32, n_steps=10)
     say("batched 6 instances, 10 steps")
