@@ -2459,7 +2459,22 @@ struct ChemArgs {
     float* kappa;
     const double* Linst;
     const int* inst_of;
+    const double* rc3;  // [N][3] alpha_A, alpha_B, beta at the particle's T while T is
+                        // fixed (isothermal or frozen runs), else null
 };
+
+// The recombination and collisional-ionization coefficients of each particle
+// at its temperature, for runs whose temperatures never change: evaluated once
+// instead of every step (the fits' powers and exponentials in FP64 were most
+// of the chemistry step), from the same T, hence the same values.
+__global__ __launch_bounds__(256) void k_rates_cache(long long N, const double* __restrict__ T, double* __restrict__ rc3) {
+    const long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    const Rates r = rates_at(T[j]);
+    rc3[3 * j] = r.aA;
+    rc3[3 * j + 1] = r.aB;
+    rc3[3 * j + 2] = r.beta;
+}
 
 // Chemistry step of one particle (section 2.1; section 2.2 for the RR
 // photons).  Gamma = sum_nu A_nu / (N_HI dt) with N_HI at the start of the
@@ -2487,7 +2502,13 @@ __global__ __launch_bounds__(256) void k_chem(ChemArgs a) {
     double rr = 0.0;
     if (a.freeze) {
         if (a.rr_on) {
-            const Rates rt = rates_at(Tc);
+            Rates rt = {};
+            if (a.rc3) {
+                rt.aA = a.rc3[3 * j];
+                rt.aB = a.rc3[3 * j + 1];
+            } else {
+                rt = rates_at(Tc);
+            }
             const double x = 1.0 - y;
             rr = (rt.aA - rt.aB) * (nH * x) * x * NH * a.dt;
         }
@@ -2504,7 +2525,15 @@ __global__ __launch_bounds__(256) void k_chem(ChemArgs a) {
         const bool caseB = a.mode == 0;
         double t = 0.0;
         // isothermal: T, hence every rate coefficient, is fixed over the step
-        Rates rt = rates_at(Tc);
+        // (and over the run: the coefficients come from the cache)
+        Rates rt = {};
+        if (a.rc3) {
+            rt.aA = a.rc3[3 * j];
+            rt.aB = a.rc3[3 * j + 1];
+            rt.beta = a.rc3[3 * j + 2];
+        } else {
+            rt = rates_at(Tc);
+        }
         for (int n = 0; t < a.dt && n < 1000000; ++n) {
             if (!a.isothermal && n > 0) rt = rates_at(Tc);
             const double alpha = caseB ? rt.aB : rt.aA;

@@ -121,6 +121,7 @@ struct rt_ctx {
     void* mvc[2] = {nullptr, nullptr};
     void* inbox[2] = {nullptr, nullptr};
     int* hot[2] = {nullptr, nullptr};
+    double* rc3 = nullptr;  // [N][3] rate coefficients while T never changes (isothermal or frozen)
     int* rest = nullptr;    // per tile: photons rest in its bins (left by its last run)
     bool rest_unknown = true;  // rest is all ones (set up or restored): hop 0's next list is every tile
     bool list0 = true;      // hop 0 runs a list of tiles (not with the predecessor RR scheme)
@@ -887,6 +888,7 @@ rt_status step_tail(rt_ctx* c, long long launched, bool graph) {
     ca.kappa = c->f32 ? c->kappa : nullptr;
     ca.Linst = c->L_d;
     ca.inst_of = c->inst_of;
+    ca.rc3 = c->rc3;
     hipLaunchKernelGGL(k_chem, dim3(grid_for(c->N, 256)), dim3(256), 0, c->stream, ca);
     HIPCHK(c, hipGetLastError());
     TRY(time_end(c, 1));
@@ -1331,6 +1333,11 @@ rt_status init_impl(rt_ctx** out, const rt_params* p, const double* sigma_nu, co
     ITRY(upload(c, &c->NH, N_H, N));
     ITRY(upload(c, &c->xHI, x_HI0, N));
     ITRY(upload(c, &c->T, T0, N));
+    if (p->isothermal || p->freeze_chem) {  // temperatures never change: rates evaluated once
+        ITRY(alloc_n(c, &c->rc3, 3 * N));
+        hipLaunchKernelGGL(k_rates_cache, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, c->T, c->rc3);
+        HIPCHK(c, hipGetLastError());
+    }
     ITRY(upload(c, &c->sigma_d, c->sigma.data(), c->nf));
     ITRY(upload(c, &c->sigmaf_d, sigf.data(), c->nf));
     ITRY(upload(c, &c->eps_d, c->eps.data(), c->nf));
@@ -2139,6 +2146,10 @@ rt_status rt_set_state_blob(rt_ctx* c, const void* blob, size_t bytes) {
     HIPCHK(c, hipMemcpy(c->xHI, q, 8 * c->N, hipMemcpyHostToDevice));
     q += 8 * c->N;
     HIPCHK(c, hipMemcpy(c->T, q, 8 * c->N, hipMemcpyHostToDevice));
+    if (c->rc3) {  // the restored temperatures' rate coefficients
+        hipLaunchKernelGGL(k_rates_cache, dim3(grid_for(c->N, 256)), dim3(256), 0, c->stream, c->N, c->T, c->rc3);
+        HIPCHK(c, hipGetLastError());
+    }
     q += 8 * c->N;
     HIPCHK(c, hipMemcpy(c->nrr[0], q, 8 * c->N, hipMemcpyHostToDevice));
     q += 8 * c->N;
