@@ -2490,12 +2490,13 @@ __global__ __launch_bounds__(256) void k_chem(ChemArgs a) {
     const double nH = a.nH[j], NH = a.NH[j];
     for (int nu = 0; nu < a.nf; ++nu) {
         long long* d = a.dep + 3 * (j * a.nf + nu);
-        if (d[0] != 0 || d[1] != 0 || d[2] != 0)
+        if (d[0] != 0 || d[1] != 0 || d[2] != 0) {  // cleared only where something was deposited
             a.A[j * a.nf + nu] += (static_cast<double>(d[0]) * kDepositCoarse + static_cast<double>(d[1]) * kDepositFine +
                                    static_cast<double>(d[2]) * kDepositFiner) * NH;
-        d[0] = 0;
-        d[1] = 0;
-        d[2] = 0;
+            d[0] = 0;
+            d[1] = 0;
+            d[2] = 0;
+        }
     }
     double y = a.xHI[j];
     double Tc = a.T[j];
