@@ -913,7 +913,12 @@ __device__ inline void vip_settle(const VipArgs& a, const Vip& q, int what, doub
 
 __global__ __launch_bounds__(256) void k_vip_sample(VipArgs a) {
     if (a.halt_on && a.cnt[kCntHalt] != 0) return;
-    const long long gid = blockIdx.x * 256LL + threadIdx.x;
+    // after hop 0 the first a.nchunks workgroups list the marked tiles (one
+    // chunk of marks each) and the others take the virtual particles, so the
+    // two run side by side
+    const long long nlist = a.list_here ? a.nchunks : 0;
+    const long long vblk = static_cast<long long>(blockIdx.x) - nlist;
+    const long long gid = vblk * 256LL + threadIdx.x;
     if (!a.hop0) {
         // Once one forward step has found nothing to move, every later launch
         // of this step must exit: the ping-pong counters it would read are stale.
@@ -922,12 +927,11 @@ __global__ __launch_bounds__(256) void k_vip_sample(VipArgs a) {
             return;
         }
     }
-    if (a.list_here) {
-        // the tiles the previous forward step marked for this one, a chunk of
-        // marks per workgroup in turn (every thread of the workgroup takes part)
-        const int stamp = static_cast<int>(a.cnt[kCntSerial]) + a.hop;
-        for (long long ch = blockIdx.x; ch < a.nchunks; ch += gridDim.x)
-            list_marked_chunk(a.hot, a.ntiles, stamp, ch, a.rev_off, a.N, a.T, a.tlist, &a.cnt[kCntTileList + (a.hop & 1)]);
+    if (vblk < 0) {
+        // the tiles the previous forward step marked for this one
+        list_marked_chunk(a.hot, a.ntiles, static_cast<int>(a.cnt[kCntSerial]) + a.hop, blockIdx.x, a.rev_off, a.N, a.T,
+                          a.tlist, &a.cnt[kCntTileList + (a.hop & 1)]);
+        return;
     }
     long long n = a.cnt[kCntVipCnt0 + a.list_rd];
     if (n > a.vip_cap) n = a.vip_cap;
@@ -940,7 +944,7 @@ __global__ __launch_bounds__(256) void k_vip_sample(VipArgs a) {
     const int lane = threadIdx.x & 63;
     const int sub = lane % kVipLanes;
     const int gshift = lane - sub;
-    const long long groups = gridDim.x * (256LL / kVipLanes);
+    const long long groups = (static_cast<long long>(gridDim.x) - nlist) * (256LL / kVipLanes);
     const long long g0 = gid / kVipLanes;
     // a uniform trip count per wavefront: its groups stay in step
     const long long wbase = (gid - lane) / kVipLanes;

@@ -532,8 +532,10 @@ rt_status launch_vip(rt_ctx* c, int hop) {
     a.list_rd = hop & 1;
     a.list_wr = (hop + 1) & 1;
     a.halt_on = c->capturing ? 1 : 0;
+    // workgroups for the virtual particles, after those that list the marked tiles
     const unsigned nsb = static_cast<unsigned>(std::min<long long>(1024, (c->vip_cap + 255) / 256));
-    hipLaunchKernelGGL(k_vip_sample, dim3(nsb), dim3(256), 0, c->stream, a);
+    const unsigned nlist = hop > 0 ? static_cast<unsigned>(a.nchunks) : 0u;
+    hipLaunchKernelGGL(k_vip_sample, dim3(nsb + nlist), dim3(256), 0, c->stream, a);
     hipLaunchKernelGGL(k_vip_chain, dim3(1024), dim3(256), 0, c->stream, a);
     HIPCHK(c, hipGetLastError());
     // the tiles marked for this forward step: after hop 0, k_vip_sample lists
