@@ -826,7 +826,7 @@ struct VipArgs {
     int* rec_next;
     int* head;
     long long rec_cap;
-    int* hot;        // tiles that receive records in this forward step
+    int* hot;        // marks of this forward step's tiles (deliveries of the previous one, records)
     int lgT;
     // hop > 0: k_vip_sample lists the tiles the previous forward step marked,
     // and k_vip_chain appends those it marks first (no separate list launch)
@@ -1268,8 +1268,8 @@ struct HopArgs {
     const R2<R>* mvc_rd;
     const Inbox<DT>* in_rd;
     const int* hot_rd;
-    const int4* tlist;       // tiles marked for this forward step (k_tile_list), hop > 0 or
-                             // list0: {tile, first and end receiver-sorted edge of its particles, 0}
+    const int4* tlist;       // this forward step's list of tiles (every tile at hop 0 without
+                             // list0): {tile, first and end receiver-sorted edge of its particles, 0}
     int* rest;               // per tile: 1 if a slot held photons after the tile last ran
     long long ntiles;
     int lg_wpb;              // log2 of the wavefronts (tiles) per workgroup: 0, 1 or 2
@@ -1547,8 +1547,8 @@ struct HopLds {
 
 // One forward step (section 2.1), receiver-sorted.  A workgroup of one
 // wavefront owns a tile of T = 64 / G consecutive particles, one lane per slot
-// (particle j, bin nu, reception cone r), and runs only if the tile is marked
-// for this step (hop 0 of an RT step runs every tile).  Gathering: the inboxes of the tile's incoming edges
+// (particle j, bin nu, reception cone r), and runs only if the tile is on this
+// forward step's list.  Gathering: the inboxes of the tile's incoming edges
 // are staged in LDS; each slot counts the packets that arrive in its cone
 // (from LDS alone), a prefix sum lays the (edge, packet, slot) pairs out in
 // one queue, and all lanes load and attenuate the queued packets together
@@ -2262,14 +2262,13 @@ __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long lon
 }
 
 // The forward-step kernel: workgroups of a.wpb independent wavefronts, one
-// tile each, each wavefront with its own share of the LDS.  Hop 0 of an RT
-// step runs every tile; a later forward step runs only the tiles k_tile_list
-// found marked for it, packed into the first workgroups of the launch, so the
-// real work is dispatched first and the surplus workgroups read one counter
-// and exit (several tiles per workgroup cut their number).  Workgroups are
-// dispatched round-robin over the 8 XCDs; xcd_block gives each XCD a
-// contiguous share of the tiles (of the list, sorted within each k_tile_list
-// block), so that neighbouring particles share that XCD's L2.  The
+// tile each, each wavefront with its own share of the LDS.  A forward step
+// runs the tiles of its list (hop 0 with the predecessor RR scheme: every
+// tile), packed into the first workgroups of the launch, so the real work is
+// dispatched first and the surplus workgroups read one counter and exit.
+// Workgroups are dispatched round-robin over the 8 XCDs; xcd_block gives each
+// XCD a contiguous share of the list (sorted within each chunk of marks), so
+// that neighbouring particles share that XCD's L2.  The
 // launch-level flags are read once: a launch past the last forward step of an
 // RT step, or past the cap, runs no tile.
 // kExt: the variant for the rarely used features, a barrier disk (its edges
@@ -2410,12 +2409,13 @@ __global__ __launch_bounds__(256) void k_step_tally(long long* cnt, unsigned lon
         }
         return;
     }
+    // the sums first (loads only, so they overlap), then the clears
     unsigned long long v[3] = {0, 0, 0};
+#pragma unroll 4
     for (long long t = blockIdx.x * 256LL + threadIdx.x; t < ntiles; t += gridDim.x * 256LL)
-        for (int c = 0; c < 3; ++c) {
-            v[c] += part[3 * t + c];
-            part[3 * t + c] = 0;
-        }
+        for (int c = 0; c < 3; ++c) v[c] += part[3 * t + c];
+    for (long long t = blockIdx.x * 256LL + threadIdx.x; t < ntiles; t += gridDim.x * 256LL)
+        for (int c = 0; c < 3; ++c) part[3 * t + c] = 0;
     for (int c = 0; c < 3; ++c) s[c][threadIdx.x] = v[c];
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {

@@ -330,7 +330,7 @@ long long grid_estimate(long long tiles, int wpb) {
     return g;
 }
 
-// The grids of forward step `hop` (> 0: hop 0 runs every tile) with `wpb`
+// The grids of forward step `hop` (hop 0 without its list runs every tile) with `wpb`
 // tiles per workgroup, for a forward step whose list has had up to `est`
 // tiles (0: not seen yet): k_hop's workgroups, returned, and k_hop_tail's in
 // *n_tail (0: no tail).  The tail's grid is a 64th of the main one and at
