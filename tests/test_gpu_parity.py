@@ -201,6 +201,30 @@ def test_packets_resting_between_steps():
             c.close()
 
 
+def test_frozen_chemistry_rr_against_oracle():
+    # Transport-only runs (chemistry frozen): x_HI and T stay as given and each
+    # step emits the RR photons of the frozen ionized fraction, from rate
+    # coefficients the library evaluates once per particle (temperatures never
+    # change).  FP64 against the oracle: counters exact, x_HI untouched, the
+    # pending RR photons and the ledger within rounding.
+    cfg = I.stromgren(12, rr=True, n_ngb=32, dt_myr=0.5, freeze_chem=1)
+    N = cfg["pos"].shape[0]
+    cfg["xHI"] = np.linspace(0.05, 0.95, N)
+    steps = 4
+    say("12^3 frozen chemistry with RR, 4 steps")
+    s, _ = run_oracle(cfg, steps)
+    so = s.state()
+    g = run_gpu(cfg, steps, "fp64")
+    sg = g.state()
+    say("counters oracle", so["counters"], "gpu", sg["counters"])
+    assert np.array_equal(so["counters"], sg["counters"])
+    assert np.array_equal(sg["xHI"], cfg["xHI"])
+    assert rel(g.pending_rr(), s.nrr()) < 1e-12
+    assert rel(sg["ledger"][..., 0], so["ledger"][..., 0]) < 1e-12
+    assert np.max(residual(sg["ledger"])) < 1e-12
+    g.close()
+
+
 def test_fp64_parity_batched():
     cfg = I.batched(n_inst=6, side_lo=6, side_hi=12, n_ngb=32, n_steps=10)
     say("batched 6 instances, 10 steps")
