@@ -257,9 +257,10 @@ rt_status rt_get_timing(rt_ctx *ctx, double *out, int32_t n);
  * one from step to step, so that each runs every forward-step index once;
  * forward steps whose list outgrew its grid are not counted) and the fastest
  * per launch is kept; shape = -2 times them on the next 3 steps whatever
- * their size.  The tuner's ms per launch of shapes 3..5 reads 0.  RT_EINVAL for another value.  rt_get_hop_shape reports the
+ * their size.  RT_EINVAL for another value.  rt_get_hop_shape reports the
  * configuration in use, whether the tuner chose it, and the tuner's mean ms
- * per launch of each (6 doubles, 0 if not timed); any pointer may be NULL. */
+ * per launch of each (6 doubles, 0 if not timed: always for shapes 3..5);
+ * any pointer may be NULL. */
 rt_status rt_set_hop_shape(rt_ctx *ctx, int32_t shape);
 
 /* Whole-step graphs (on = 1; default 0): rt_step enqueues each RT step as one
