@@ -315,6 +315,7 @@ void direction_set(int n, std::vector<double>& u) {
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 constexpr long long kHopMinSavedWGs = 65536;
+constexpr long long kHopHeadroomTiles = 4096;
 constexpr long long kHopTailMinWGs = 256;
 constexpr long long kHopTailMaxWGs = 65536;
 constexpr long long kHopUnseenWGs = 1024;
@@ -324,7 +325,8 @@ constexpr long long kHopUnseenTailWGs = 8192;
 // quarter more, rounded up to a power of two (so that graphs captured with it
 // stay valid while the lists grow a little), at least 64.
 long long grid_estimate(long long tiles, int wpb) {
-    const long long want = (tiles + tiles / 4 + wpb - 1) / wpb + 1;
+    const long long room = std::max(tiles / 4, kHopHeadroomTiles);
+    const long long want = (tiles + room + wpb - 1) / wpb + 1;
     long long g = 64;
     while (g < want) g <<= 1;
     return g;
@@ -948,10 +950,13 @@ rt_status step_tail(rt_ctx* c, long long launched, bool graph) {
 }
 
 // The forward steps' list lengths of the last step (copied to the pinned
-// mirror with the counters): the longest seen per forward step sizes its grid.
-// A grid that changes drops the captured graphs, which hold the old one.
+// mirror with the counters): the longest seen per forward step sizes its grid
+// at the next launch.  Captured graphs keep the grids of their capture and
+// are dropped (captured again at the next step, with grids from the new
+// lengths) only when a forward step's list came within a tenth of the end of
+// the grid it ran with.
 void absorb_list_lengths(rt_ctx* c, long long H) {
-    bool changed = false;
+    bool refit = false;
     const long long top = std::min<long long>(H, static_cast<long long>(c->est_tiles.size()) - 1);
     // a hop 0 that listed every tile (rest flags not known yet) says nothing
     // about the lists to come
@@ -959,16 +964,11 @@ void absorb_list_lengths(rt_ctx* c, long long H) {
     c->rest_unknown = false;
     for (long long q = q0; q <= top; ++q) {
         const long long seen = c->h_listlen[q];
-        if (seen <= c->est_tiles[q]) continue;
-        for (int w = 1; w <= 4; w <<= 1) {
-            long long t0 = 0, t1 = 0;
-            const long long g0 = hop_grid(c, static_cast<int>(q), c->est_tiles[q], w, &t0);
-            const long long g1 = hop_grid(c, static_cast<int>(q), seen, w, &t1);
-            changed = changed || g0 != g1 || t0 != t1;
-        }
-        c->est_tiles[q] = seen;
+        const long long cap = c->cap_tiles[q];
+        if (cap < c->ntiles && seen * 10 > cap * 9) refit = true;
+        if (seen > c->est_tiles[q]) c->est_tiles[q] = seen;
     }
-    if (changed) drop_graphs(c);
+    if (refit) drop_graphs(c);
 }
 
 // Host bookkeeping after a step that ran H forward steps with `launched`
