@@ -265,16 +265,17 @@ rt_status rt_set_hop_shape(rt_ctx *ctx, int32_t shape);
 
 /* Whole-step graphs (on = 1; default 0): rt_step enqueues each RT step as one
  * captured graph, the steps back to back, with a single host check at the end
- * of the call instead of one per batch of forward steps.  A graph holds one
- * forward step more than the previous step needed; if a step needs more, it
+ * of the call instead of one per batch of forward steps.  A graph holds at
+ * least two forward steps more than the previous step needed, rounded up to a
+ * multiple of four; if a step needs more, it
  * halts the queue on the device (every later kernel exits at once) and the
  * call finishes that step one forward step at a time, then goes on.  Used
  * only once a step has run and the launch configuration is settled (not
  * while timing, tuning, or with a fixed hop_batch).  Results are identical
  * either way; the stamps that number forward steps differ.  It is not the
- * default: the unused forward steps a graph must hold cost more on the
- * measured workloads than the host checks they replace.  RT_EINVAL for
- * another value. */
+ * default: on the measured workloads it is no faster once its graphs exist
+ * and slower while new ones are captured (the fronts' forward-step counts
+ * grow).  RT_EINVAL for another value. */
 rt_status rt_set_step_graphs(rt_ctx *ctx, int32_t on);
 rt_status rt_get_hop_shape(rt_ctx *ctx, int32_t *shape, int32_t *tuned, double *ms_per_launch);
 

@@ -1099,7 +1099,12 @@ rt_status step_graph(rt_ctx* c, int hg, hipGraphExec_t* out) {
 // finished here one forward step at a time.  Returns the steps finished.
 rt_status graph_steps(rt_ctx* c, int n, int* done, bool* hopcap) {
     *done = 0;
-    const int hg = static_cast<int>(std::min<long long>(c->p.max_hops, c->last_hops + 1));
+    // forward steps a step graph holds: at least two more than the last step
+    // needed, rounded up to a multiple of four, so that a step whose fronts
+    // grew rarely halts the queue and one graph serves several steps (an idle
+    // forward step costs its four launches, ~15 us; a halt a host round trip
+    // per forward step and often a new capture)
+    const int hg = static_cast<int>(std::min<long long>(c->p.max_hops, (c->last_hops + 2 + 3) / 4 * 4));
     TRY(restart_stamps_if_needed(c, static_cast<long long>(hg + 1) * n));
     const long long step0 = c->step;
     const int cur0 = c->nrr_cur;

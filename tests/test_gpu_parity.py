@@ -300,7 +300,10 @@ def test_whole_step_graphs_match_eager():
     # call goes through such halts.  The state must match, bit for bit, the
     # same steps made one launch at a time with a host check after each batch
     # (the stamps that number forward steps differ: a graph holds a fixed
-    # number of them).
+    # number of them).  Here the steps need 6, 6, 7, 8, 8, 9, ... forward
+    # steps (the oracle's count): the 12-step call starts with graphs of 8
+    # (two more than the first step's 6, rounded up to a multiple of four), so
+    # its sixth step halts.
     cfg = I.stromgren(16, rr=True, n_ngb=32, dt_myr=0.2)
     RT = _rt()
     for prec in ("fp64", "fp32"):
