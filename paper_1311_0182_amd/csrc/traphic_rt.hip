@@ -20,6 +20,7 @@ using namespace trt;
 namespace {
 
 constexpr int kChunk = 2048;      // particles per ledger partial sum
+constexpr int kCellDense = 8;     // particles in the fullest neighbour-search cell before cells are refined
 constexpr int kMaxDevices = 64;
 // Scratch of rt_shell_profile_noalloc: the shell histogram (sums, then
 // counts), the largest any call may need.
@@ -1308,14 +1309,33 @@ rt_status init_impl(rt_ctx** out, const rt_params* p, const double* sigma_nu, co
         mean_NH[k] = sum / static_cast<double>(n);
         c->L[k] = Lmax;
         clf[k] = static_cast<float>(Lmax / (kCLight * p->dt));
-        const double cs = std::cbrt(2.0 * vol / static_cast<double>(n));
-        for (int a = 0; a < 3; ++a) {
-            const double La = box[6 * k + 3 + a] - box[6 * k + a];
-            int m = static_cast<int>(La / cs);
-            m = std::max(1, std::min(m, 1024));
-            g.nc[a] = m;
-            g.cs[a] = La / m;
-            g.lo[a] = box[6 * k + a];
+        // cells of ~2 particles on average; where the particles cluster (the
+        // fullest cell holds more than kCellDense), finer until the fullest
+        // would hold about kCellDense (at most 8x per axis and 1024 cells per
+        // axis), so that neighbour searches in dense regions sort fewer
+        // candidates (the search is exact whatever the cells)
+        double cs = std::cbrt(2.0 * vol / static_cast<double>(n));
+        auto set_cells = [&](double csz) {
+            for (int a = 0; a < 3; ++a) {
+                const double La = box[6 * k + 3 + a] - box[6 * k + a];
+                int m = static_cast<int>(La / csz);
+                m = std::max(1, std::min(m, 1024));
+                g.nc[a] = m;
+                g.cs[a] = La / m;
+                g.lo[a] = box[6 * k + a];
+            }
+        };
+        set_cells(cs);
+        {
+            std::vector<int> occ(static_cast<size_t>(g.nc[0]) * g.nc[1] * g.nc[2], 0);
+            int most = 0;
+            for (long long i = inst_off[k]; i < inst_off[k + 1]; ++i) {
+                int ci[3];
+                for (int a = 0; a < 3; ++a)
+                    ci[a] = std::max(0, std::min(g.nc[a] - 1, static_cast<int>((pos[3 * i + a] - g.lo[a]) / g.cs[a])));
+                most = std::max(most, ++occ[(static_cast<size_t>(ci[0]) * g.nc[1] + ci[1]) * g.nc[2] + ci[2]]);
+            }
+            if (most > kCellDense) set_cells(cs / std::min(8.0, std::cbrt(static_cast<double>(most) / kCellDense)));
         }
         g.cell0 = ncell;
         ncell += static_cast<long long>(g.nc[0]) * g.nc[1] * g.nc[2];
