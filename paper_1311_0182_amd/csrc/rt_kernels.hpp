@@ -2585,6 +2585,8 @@ __global__ __launch_bounds__(256) void k_chem(ChemArgs a) {
 
 // ---------------------------------------------------------------- ledger --
 
+constexpr int kLedgerBinsPerPass = 4;  // bins summed per pass of k_ledger_partial
+
 struct LedgerArgs {
     int halt_on;  // steps replayed from a graph: exit at once while the halt word is set
     const long long* cnt;
@@ -2605,22 +2607,39 @@ __global__ __launch_bounds__(256) void k_ledger_partial(LedgerArgs a) {
     const long long c = blockIdx.x;
     const long long lo = a.chunk_lo[c], hi = a.chunk_hi[c];
     __shared__ double red[256];
-    for (int nu = 0; nu < a.nf; ++nu) {
-        double v[3] = {0, 0, 0};
+    // passes over the chunk's particles, four bins at a time (the bins of a
+    // particle are adjacent in A and Fp, so a pass reads each line once);
+    // each thread adds its particles in the same order for every bin, and the
+    // tree below is fixed
+    for (int nu0 = 0; nu0 < a.nf; nu0 += kLedgerBinsPerPass) {
+        double v[kLedgerBinsPerPass][3];
+#pragma unroll
+        for (int u = 0; u < kLedgerBinsPerPass; ++u) v[u][0] = v[u][1] = v[u][2] = 0.0;
         for (long long j = lo + threadIdx.x; j < hi; j += 256) {
-            if (a.rr_on && nu == a.rr_bin) v[0] += a.nrr_prev[j];
-            v[1] += a.A[j * a.nf + nu];
-            v[2] += a.Fp[j * a.nf + nu];
+#pragma unroll
+            for (int u = 0; u < kLedgerBinsPerPass; ++u) {
+                const int nu = nu0 + u;
+                if (nu < a.nf) {
+                    if (a.rr_on && nu == a.rr_bin) v[u][0] += a.nrr_prev[j];
+                    v[u][1] += a.A[j * a.nf + nu];
+                    v[u][2] += a.Fp[j * a.nf + nu];
+                }
+            }
         }
-        for (int k = 0; k < 3; ++k) {
-            red[threadIdx.x] = v[k];
-            __syncthreads();
-            for (int off = 128; off > 0; off >>= 1) {
-                if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+#pragma unroll
+        for (int u = 0; u < kLedgerBinsPerPass; ++u) {
+            const int nu = nu0 + u;
+            if (nu >= a.nf) break;
+            for (int k = 0; k < 3; ++k) {
+                red[threadIdx.x] = v[u][k];
+                __syncthreads();
+                for (int off = 128; off > 0; off >>= 1) {
+                    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+                    __syncthreads();
+                }
+                if (threadIdx.x == 0) a.partial[(c * a.nf + nu) * 3 + k] = red[0];
                 __syncthreads();
             }
-            if (threadIdx.x == 0) a.partial[(c * a.nf + nu) * 3 + k] = red[0];
-            __syncthreads();
         }
     }
 }
