@@ -95,7 +95,9 @@ typedef struct {
                               2^16, B/8 and B (1 - 1/n_tc)^n_ngb for B = N n_freq n_rc slots) */
     int64_t record_capacity; /* arrival/deposit records per forward step (0: default, the
                                 larger of 2^20 and 4 vip_capacity) */
-    /* Optional device allocator (e.g. PyTorch's caching allocator).  NULL: hipMalloc/hipFree. */
+    /* Optional device allocator (e.g. PyTorch's caching allocator).  NULL: hipMalloc/hipFree.
+     * It must return ordinary (coarse-grained) device memory: the kernels add
+     * to some arrays with hardware floating-point atomics. */
     void *(*alloc)(void *user, size_t bytes);
     void (*dealloc)(void *user, void *ptr);
     void *alloc_user;

@@ -1615,10 +1615,8 @@ __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long lon
     const int inst_l = a.inst_of[jc];
     const R flo_l = a.floor_b[jc];
     const int hd_l = a.head[jc];
-    const double A0_l = a.A[ia], P0_l = a.P[ia];
     const Bin4<R> q0_l = a.pk[jc * G + o];
     const R c0_l = a.pcl[jc * G + o];
-    const unsigned long long tally_l = a.part[3 * tile + (lane < 3 ? lane : 0)];
     R ka_l, sg_l, nh_l;  // the optical depth's per-particle and per-bin factors
     if constexpr (f32) {
         ka_l = a.kappa[jc];
@@ -1638,8 +1636,6 @@ __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long lon
     const float clf_l = f32 ? a.clf[inst] : 0.0f;
     // algorithmic bytes this lane moves (slot state, gathered packets, edges)
     unsigned long long nbytes = 0;
-    // the tile's running tallies (read early, written back at the end)
-    const unsigned long long tally = lane < 3 ? tally_l : 0ull;
 
     Acc<R> acc = {};
     int narr = 0;            // packets merged into the bin besides the one that stays
@@ -1650,7 +1646,6 @@ __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long lon
     bool have_stay = false, departed = false;
     const R flo = valid ? flo_l : R(0);
     const int hd = valid ? hd_l : -1;
-    const double A0 = (valid && r == 0) ? A0_l : 0.0, P0 = (valid && r == 0) ? P0_l : 0.0;
     q0.x = valid ? q0_l.x : R(0);  // selects, so that the loads stay up front
     q0.y = valid ? q0_l.y : R(0);
     q0.z = valid ? q0_l.z : R(0);
@@ -2012,9 +2007,11 @@ __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long lon
         ag = group_sum(asum + aerr, nrc);
         pg = group_sum(psum + perr, nrc);
     }
+    // added in place (one lane per (j, nu) and launch, so the sum is the
+    // plain A + ag U): no register holds the old values through the tile
     if (valid && r == 0 && (ag != R(0) || pg != R(0))) {
-        a.A[ia] = A0 + static_cast<double>(ag) * U;
-        a.P[ia] = P0 + static_cast<double>(pg) * U;
+        unsafeAtomicAdd(&a.A[ia], static_cast<double>(ag) * U);
+        unsafeAtomicAdd(&a.P[ia], static_cast<double>(pg) * U);
         nbytes += 32;
     }
     // arrivals the barrier removed: one set of atomics per (instance, bin),
@@ -2255,7 +2252,8 @@ __device__ __forceinline__ void hop_tile(const HopArgs<R, DT>& a, const long lon
     if (lane == 0) a.rest[tile] = resting ? 1 : 0;
     const unsigned long long nupd = __popcll(__ballot(departed));
     const unsigned long long wb = f32 ? wave_sum_u64_fast(nbytes) : wave_sum_u64(nbytes);
-    if (lane < 3) a.part[3 * tile + lane] = tally + (lane == 0 ? nupd : (lane == 1 ? wb : 1ull));
+    // the tile's running tallies, added in place (the tile's own entries)
+    if (lane < 3) atomicAdd(&a.part[3 * tile + lane], lane == 0 ? nupd : (lane == 1 ? wb : 1ull));
     // every LDS read of this tile has been consumed before the next tile stages
     __builtin_amdgcn_s_waitcnt(0);
     wave_sync();
