@@ -2706,17 +2706,39 @@ struct LedgerFinalArgs {
     long long* cnt;
 };
 
-__global__ void k_ledger_final(LedgerFinalArgs a) {
+// One workgroup of kLedgerFinalBlock threads per (instance, bin): thread i sums
+// the instance's chunks i, i + kLedgerFinalBlock, ... in order, then a fixed
+// tree over the threads (the same order on every run, whatever the timing).
+constexpr int kLedgerFinalBlock = 256;
+
+__global__ __launch_bounds__(kLedgerFinalBlock) void k_ledger_final(LedgerFinalArgs a) {
     if (a.halt_on && a.cnt[kCntHalt] != 0) return;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blockIdx.x;
     if (t >= a.n_inst * a.nf) return;
     const int k = t / a.nf, nu = t % a.nf;
     double v[5] = {0, 0, 0, 0, 0};
-    for (long long c = a.inst_chunk0[k]; c < a.inst_chunk0[k + 1]; ++c) {
+    for (long long c = a.inst_chunk0[k] + threadIdx.x; c < a.inst_chunk0[k + 1]; c += kLedgerFinalBlock) {
         v[0] += a.partial[(c * a.nf + nu) * 3 + 0];
         v[1] += a.partial[(c * a.nf + nu) * 3 + 1];
         v[4] += a.partial[(c * a.nf + nu) * 3 + 2];
     }
+    __shared__ double s0[kLedgerFinalBlock], s1[kLedgerFinalBlock], s4[kLedgerFinalBlock];
+    s0[threadIdx.x] = v[0];
+    s1[threadIdx.x] = v[1];
+    s4[threadIdx.x] = v[4];
+    __syncthreads();
+    for (int w = kLedgerFinalBlock / 2; w > 0; w >>= 1) {
+        if (static_cast<int>(threadIdx.x) < w) {
+            s0[threadIdx.x] += s0[threadIdx.x + w];
+            s1[threadIdx.x] += s1[threadIdx.x + w];
+            s4[threadIdx.x] += s4[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    v[0] = s0[0];
+    v[1] = s1[0];
+    v[4] = s4[0];
     unsigned long long* fx = a.xr_fx + 6 * static_cast<long long>(t);
     v[2] = fx_value3(fx) * a.Ufx[k] + a.emt[2 * t];
     v[3] = fx_value3(fx + 3) * a.Ufx[k] + a.emt[2 * t + 1];

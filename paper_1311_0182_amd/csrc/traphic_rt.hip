@@ -942,7 +942,7 @@ rt_status step_tail(rt_ctx* c, long long launched, bool graph) {
     lf.scale = c->scale;
     lf.cnt = c->cnt;
     lf.halt_on = c->capturing ? 1 : 0;
-    hipLaunchKernelGGL(k_ledger_final, dim3(grid_for(c->n_inst * c->nf, 64)), dim3(64), 0, c->stream, lf);
+    hipLaunchKernelGGL(k_ledger_final, dim3(static_cast<unsigned>(c->n_inst * c->nf)), dim3(kLedgerFinalBlock), 0, c->stream, lf);
     HIPCHK(c, hipGetLastError());
     hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, c->stream, c->cnt, c->capturing ? 1 : 0);
     HIPCHK(c, hipGetLastError());
