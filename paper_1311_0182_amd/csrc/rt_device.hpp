@@ -351,8 +351,11 @@ __device__ inline double knn_query(const GridInfo& g, const int* __restrict__ ce
 // doubles order like their bit patterns), counting with one ballot per
 // register slot; the search stops when that distance cannot be beaten by
 // unvisited cells, and otherwise the buffer is cut to the K best and later
-// shells only add candidates no farther than the current K-th.  Same result
-// as the serial query (the K smallest pairs are unique).
+// shells only add candidates no farther than the current K-th.  The same cut
+// is made within a pass whenever the next round of candidates might not fit,
+// so a dense cube of cells (hundreds of particles around a clustered point)
+// stays in the buffer.  Same result as the serial query (the K smallest pairs
+// are unique).
 // ---------------------------------------------------------------------------
 constexpr int kWaveCand = 640;
 constexpr int kWavePer = kWaveCand / 64;
@@ -538,8 +541,9 @@ __device__ inline double wave_select(WaveKnn& L, int n, int K, int lane) {
 }
 
 // Returns false if the candidate buffer overflowed (the caller then falls
-// back to the serial query).  On success res_idx/res_d2[0..K) are sorted and
-// kth = res_d2[K-1].
+// back to the serial query; with the cuts above this needs K > kWaveCand - 256,
+// beyond kMaxNgb, so it is a guard only).  On success res_idx/res_d2[0..K)
+// are sorted and kth = res_d2[K-1].
 __device__ inline bool knn_wave(const GridInfo& g, const int* __restrict__ cell_start,
                                 const int* __restrict__ cell_idx, const double* __restrict__ cpos,
                                 double qx, double qy, double qz, int self, int K, WaveKnn& L, int lane) {
@@ -647,6 +651,12 @@ __device__ inline bool knn_wave(const GridInfo& g, const int* __restrict__ cell_
                         const double ez = cpos[3 * static_cast<long long>(kc[i]) + 2] - qz;
                         d2v[i] = ex * ex + ey * ey + ez * ez;
                     }
+                }
+                // a full buffer is cut to its K best first (their K-th distance
+                // becomes the bound), so a dense cube never overflows it
+                if (n + 256 > kWaveCand && n >= K) {
+                    bound = wave_select(L, n, K, lane);
+                    n = K;
                 }
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
