@@ -124,15 +124,17 @@ __global__ void k_cell_count(long long N, const double* __restrict__ pos, const 
     atomicAdd(&cnt[cell], 1);
 }
 
-// Exclusive scan of n ints into out[n+1], one workgroup, sequential chunks.
-__global__ __launch_bounds__(1024) void k_scan_i32(const int* __restrict__ in, long long n, int* __restrict__ out) {
+// Exclusive scan of in[lo, hi) into out[lo, hi), starting from carry0, by one
+// workgroup of 1024 threads in sequential chunks; returns the running total.
+__device__ inline int scan_range_i32(const int* __restrict__ in, long long lo, long long hi, int carry0,
+                                     int* __restrict__ out) {
     __shared__ int part[1024];
     __shared__ int carry;
-    if (threadIdx.x == 0) carry = 0;
+    if (threadIdx.x == 0) carry = carry0;
     __syncthreads();
-    for (long long base = 0; base < n; base += 1024) {
+    for (long long base = lo; base < hi; base += 1024) {
         const long long i = base + threadIdx.x;
-        const int v = i < n ? in[i] : 0;
+        const int v = i < hi ? in[i] : 0;
         part[threadIdx.x] = v;
         __syncthreads();
         for (int off = 1; off < 1024; off <<= 1) {
@@ -141,12 +143,47 @@ __global__ __launch_bounds__(1024) void k_scan_i32(const int* __restrict__ in, l
             part[threadIdx.x] += t;
             __syncthreads();
         }
-        if (i < n) out[i] = carry + part[threadIdx.x] - v;
+        if (i < hi) out[i] = carry + part[threadIdx.x] - v;
         __syncthreads();
         if (threadIdx.x == 1023) carry += part[1023];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[n] = carry;
+    const int total = carry;
+    __syncthreads();
+    return total;
+}
+
+// Exclusive scan of n ints into out[n+1], one workgroup.
+__global__ __launch_bounds__(1024) void k_scan_i32(const int* __restrict__ in, long long n, int* __restrict__ out) {
+    const int total = scan_range_i32(in, 0, n, 0, out);
+    if (threadIdx.x == 0) out[n] = total;
+}
+
+// The same scan over many workgroups, for long arrays (the cells of a finely
+// divided grid): workgroup b sums its range [b per, (b + 1) per) (k_scan_sums),
+// the sums are scanned by k_scan_i32, and each range is scanned from its offset
+// (k_scan_apply).  Integer sums: the result does not depend on the split.
+constexpr int kScanBlocks = 1024;
+__global__ __launch_bounds__(1024) void k_scan_sums(const int* __restrict__ in, long long n, long long per,
+                                                    int* __restrict__ sums) {
+    const long long lo = blockIdx.x * per, hi = lo + per < n ? lo + per : n;
+    int v = 0;
+    for (long long i = lo + threadIdx.x; i < hi; i += 1024) v += in[i];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    __shared__ int ws[16];
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < 16; ++w) t += ws[w];
+        sums[blockIdx.x] = t;
+    }
+}
+__global__ __launch_bounds__(1024) void k_scan_apply(const int* __restrict__ in, long long n, long long per,
+                                                     const int* __restrict__ offs, int nb, int* __restrict__ out) {
+    const long long lo = blockIdx.x * per, hi = lo + per < n ? lo + per : n;
+    (void)scan_range_i32(in, lo, hi, offs[blockIdx.x], out);
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = offs[nb];
 }
 
 __global__ void k_cell_fill(long long N, const int* __restrict__ cell_of, const int* __restrict__ start,
@@ -182,6 +219,35 @@ __global__ __launch_bounds__(128) void k_knn(long long n, const double* __restri
     h[i] = knn_query(g, cell_start, cell_idx, pos, qpos[3 * i], qpos[3 * i + 1], qpos[3 * i + 2],
                      exclude_self ? static_cast<int>(i) : -1, K, bd, bi);
     for (int k = 0; k < K; ++k) ngb[i * K + k] = bi[k];
+}
+
+// The particles' own neighbour lists with the wavefront search (one wavefront
+// per particle, four per workgroup): the same lists and smoothing lengths as
+// k_knn (the K nearest (d^2, index) pairs are unique), without one thread
+// working through every candidate of a dense region alone.
+__global__ __launch_bounds__(256) void k_knn_wave(long long n, const double* __restrict__ pos,
+                                                  const int* __restrict__ inst_of, const GridInfo* __restrict__ grid,
+                                                  const int* __restrict__ cell_start, const int* __restrict__ cell_idx,
+                                                  const double* __restrict__ cpos, int K, int* __restrict__ ngb,
+                                                  double* __restrict__ h) {
+    __shared__ WaveKnn lds[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    WaveKnn& L = lds[wv];
+    const long long stride = static_cast<long long>(gridDim.x) * 4;
+    for (long long i = static_cast<long long>(blockIdx.x) * 4 + wv; i < n; i += stride) {
+        const GridInfo g = grid[inst_of[i]];
+        const double qx = pos[3 * i], qy = pos[3 * i + 1], qz = pos[3 * i + 2];
+        if (!knn_wave(g, cell_start, cell_idx, cpos, qx, qy, qz, static_cast<int>(i), K, L, lane)) {
+            if (lane == 0) {
+                knn_query(g, cell_start, cell_idx, pos, qx, qy, qz, static_cast<int>(i), K, L.res_d2, L.res_idx);
+                L.kth = L.res_d2[K - 1];
+            }
+            wave_sync();
+        }
+        if (lane < K) ngb[i * K + lane] = L.res_idx[lane];
+        if (lane == 0) h[i] = sqrt(L.kth);
+        wave_sync();  // the wavefront's LDS is reused for its next particle
+    }
 }
 
 __global__ void k_rev_count(long long nE, const int* __restrict__ ngb, int* __restrict__ cnt) {

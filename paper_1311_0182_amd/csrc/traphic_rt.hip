@@ -90,6 +90,7 @@ struct rt_ctx {
     int* cell_start = nullptr;
     int* cell_idx = nullptr;
     double* cell_pos = nullptr;  // positions in cell order (cell_idx order), for the wavefront kNN
+    int* scan_tmp = nullptr;     // block sums and their offsets of the many-workgroup scan
     double *u_rc = nullptr, *u_ec = nullptr;
     double* rot = nullptr;
     float* wrcf = nullptr;
@@ -609,6 +610,29 @@ rt_status fill_i32(rt_ctx* c, int* p, long long n, int v) {
     HIPCHK(c, hipGetLastError());
     return RT_OK;
 }
+// Exclusive scan of n ints into out[n+1]: one workgroup for short arrays,
+// otherwise the three-pass scan over up to kScanBlocks workgroups.
+rt_status scan_i32(rt_ctx* c, const int* in, long long n, int* out) {
+    if (n <= 65536) {
+        hipLaunchKernelGGL(k_scan_i32, dim3(1), dim3(1024), 0, c->stream, in, n, out);
+        HIPCHK(c, hipGetLastError());
+        return RT_OK;
+    }
+    if (!c->scan_tmp) {
+        const rt_status s = alloc_n(c, &c->scan_tmp, 2ll * (kScanBlocks + 1));
+        if (s != RT_OK) return s;
+    }
+    const long long per = (n + kScanBlocks - 1) / kScanBlocks;
+    const int nb = static_cast<int>((n + per - 1) / per);
+    int* sums = c->scan_tmp;
+    int* offs = c->scan_tmp + kScanBlocks + 1;
+    hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(1024), 0, c->stream, in, n, per, sums);
+    hipLaunchKernelGGL(k_scan_i32, dim3(1), dim3(1024), 0, c->stream, sums, static_cast<long long>(nb), offs);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(1024), 0, c->stream, in, n, per, offs, nb, out);
+    HIPCHK(c, hipGetLastError());
+    return RT_OK;
+}
+
 rt_status fill_f64(rt_ctx* c, double* p, long long n, double v) {
     hipLaunchKernelGGL(k_fill_f64, dim3(std::min<unsigned>(grid_for(n, 256), 4096)), dim3(256), 0, c->stream, p, n, v);
     HIPCHK(c, hipGetLastError());
@@ -1399,13 +1423,14 @@ rt_status init_impl(rt_ctx** out, const rt_params* p, const double* sigma_nu, co
     ITRY(fill_i32(c, cursor, std::max<long long>(ncell, N), 0));
     hipLaunchKernelGGL(k_cell_count, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, c->pos, c->inst_of, c->grid_d,
                        cell_of, cnt);
-    hipLaunchKernelGGL(k_scan_i32, dim3(1), dim3(1024), 0, c->stream, cnt, ncell, c->cell_start);
+    ITRY(scan_i32(c, cnt, ncell, c->cell_start));
     hipLaunchKernelGGL(k_cell_fill, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, cell_of, c->cell_start, cursor,
                        c->cell_idx);
     ITRY(alloc_n(c, &c->cell_pos, 3 * N));
     hipLaunchKernelGGL(k_cell_pos, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, c->cell_idx, c->pos, c->cell_pos);
-    hipLaunchKernelGGL(k_knn, dim3(grid_for(N, 128)), dim3(128), 0, c->stream, N, c->pos, c->inst_of, 1, c->grid_d,
-                       c->cell_start, c->cell_idx, c->pos, c->K, c->ngb, c->h);
+    hipLaunchKernelGGL(k_knn_wave, dim3(static_cast<unsigned>(std::min<long long>((N + 3) / 4, 8192))), dim3(256), 0,
+                       c->stream, N, c->pos, c->inst_of, c->grid_d, c->cell_start, c->cell_idx, c->cell_pos, c->K,
+                       c->ngb, c->h);
     // reverse lists, sorted by sender
     ITRY(alloc_n(c, &c->rev_off, N + 1));
     ITRY(alloc_n(c, &c->rev_src, N * c->K));
@@ -1415,7 +1440,7 @@ rt_status init_impl(rt_ctx** out, const rt_params* p, const double* sigma_nu, co
     ITRY(fill_i32(c, rcnt, N, 0));
     ITRY(fill_i32(c, cursor, N, 0));
     hipLaunchKernelGGL(k_rev_count, dim3(grid_for(N * c->K, 256)), dim3(256), 0, c->stream, N * c->K, c->ngb, rcnt);
-    hipLaunchKernelGGL(k_scan_i32, dim3(1), dim3(1024), 0, c->stream, rcnt, N, c->rev_off);
+    ITRY(scan_i32(c, rcnt, N, c->rev_off));
     hipLaunchKernelGGL(k_rev_fill, dim3(grid_for(N * c->K, 256)), dim3(256), 0, c->stream, N, c->K, c->ngb, c->rev_off,
                        cursor, c->rev_src, c->rev_pos);
     hipLaunchKernelGGL(k_rev_sort, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, c->rev_off, c->rev_src,

@@ -49,10 +49,20 @@ def rel(a, b):
 
 # ----------------------------------------------------------------------------
 
-@pytest.mark.parametrize("name", ["stromgren11", "batched4"])
+@pytest.mark.parametrize("name", ["stromgren11", "batched4", "stromgren52", "clustered32"])
 def test_neighbour_lists_bit_exact(name):
-    cfg = I.stromgren(11, rr=False, n_ngb=32) if name == "stromgren11" else \
-        I.batched(n_inst=4, side_lo=6, side_hi=10, n_ngb=48)
+    """Neighbour lists and smoothing lengths equal the oracle's bit for bit.
+    stromgren52 (140,608 particles, ~70,000 cells) takes the many-workgroup
+    scans of the cell counts and reverse lists; clustered32 has dense cells,
+    where the wavefront search cuts its candidate buffer."""
+    if name == "stromgren11":
+        cfg = I.stromgren(11, rr=False, n_ngb=32)
+    elif name == "batched4":
+        cfg = I.batched(n_inst=4, side_lo=6, side_hi=10, n_ngb=48)
+    elif name == "stromgren52":
+        cfg = I.stromgren(52, rr=False, n_ngb=48)
+    else:
+        cfg = I.clustered(n_side=32, box_mpc=0.04, n_src=16)
     say("case", name, "N", cfg["pos"].shape[0])
     s = O.OracleSim(cfg)
     ctx = _rt().Context(cfg, precision="fp64")
