@@ -336,7 +336,7 @@ long long grid_estimate(long long tiles, int wpb) {
 
 // The grids of forward step `hop` (hop 0 without its list runs every tile) with `wpb`
 // tiles per workgroup, for a forward step whose list has had up to `est`
-// tiles (0: not seen yet): k_hop's workgroups, returned, and k_hop_tail's in
+// tiles (0: none seen, for this or any nearby forward step): k_hop's workgroups, returned, and k_hop_tail's in
 // *n_tail (0: no tail).  The tail's grid is a 64th of the main one and at
 // least a 256th of the full grid and kHopTailMinWGs (a list that outgrows its
 // estimate, as the lists of a front advancing step by step do, then still
@@ -445,8 +445,15 @@ rt_status launch_hop(rt_ctx* c, int hop, bool pack) {
     // has had, so that late, sparse forward steps do not dispatch a workgroup
     // per tile; k_hop_tail takes any tiles past the end of that grid
     long long n_tail = 0;
-    const long long n_wg = hop_grid(c, hop, hop < static_cast<int>(c->est_tiles.size()) ? c->est_tiles[hop] : 0,
-                                    wpb, &n_tail);
+    // a forward step with no list seen yet borrows the longest list of the
+    // nearest earlier one (else of the next one, for a hop 0 whose first list
+    // covered every tile), so that a long first list still gets a full-width
+    // grid rather than the narrow tail
+    const int nest = static_cast<int>(c->est_tiles.size());
+    long long est = hop < nest ? c->est_tiles[hop] : 0;
+    for (int q = std::min(hop, nest) - 1; est == 0 && q >= 0; --q) est = c->est_tiles[q];
+    if (est == 0 && hop + 1 < nest) est = c->est_tiles[hop + 1];
+    const long long n_wg = hop_grid(c, hop, est, wpb, &n_tail);
     hipLaunchKernelGGL((k_hop<R, DT, S, kBar>), dim3(static_cast<unsigned>(n_wg)), dim3(64 * wpb), lds, c->stream, a);
     HIPCHK(c, hipGetLastError());
     if (hop < static_cast<int>(c->cap_tiles.size())) c->cap_tiles[hop] = n_wg < n_full ? n_wg * wpb : c->ntiles;
